@@ -1,0 +1,237 @@
+/*
+ * FP64 reference ("oracle") for the all-pairs hot path.  TEST INFRASTRUCTURE ONLY:
+ * it exists to check the GPU library, shares no code with it, and only the test
+ * suite, the smoke check and the benchmark's CPU-baseline leg may call it.
+ *
+ * The all-pairs problem computes f(l(i), l(j)) for every 1 <= i < j <= n
+ * (Section III).  The paper treats each application's compare kernel as a black
+ * box (Section V), so each function below is the plain textbook definition of the
+ * pair function the application names, evaluated in double precision over the
+ * exact f32/int64 values the GPU consumes, one pair at a time:
+ *
+ *   ncc      Section V-A: normalised cross-correlation of two noise patterns,
+ *            read as zero-lag Pearson correlation.
+ *   overlap  Section V-C: the transform-dependent cross term of the L2 distance
+ *            between two Gaussian mixtures, sum_k sum_l exp(-|x_k-y_l|^2/(4 s^2)).
+ *   grad     Section V-C: the registration optimiser's gradient of that term with
+ *            respect to a rigid transform (theta, tx, ty) of the second cloud,
+ *            rotating about its centroid.
+ *   sparse   Section V-B: cosine similarity of two sparse composition vectors,
+ *            with the exact size of the key intersection.
+ *
+ * Pairs are passed as explicit lists (pi[p], pj[p]); the packed upper-triangle
+ * index of (i,j), i<j, is i*n - i*(i+1)/2 + (j-i-1).  Loops over pairs are
+ * OpenMP-parallel; within a pair everything is a plain sequential FP64 loop.
+ * Built with gcc -O2 and no fast-math.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stddef.h>
+
+int64_t oracle_packed_index(int64_t i, int64_t j, int64_t n)
+{
+    /* rows 0..i-1 of the strict upper triangle hold (n-1) + (n-2) + ... + (n-i) pairs */
+    int64_t before = 0;
+    for (int64_t r = 0; r < i; ++r) before += n - 1 - r;
+    return before + (j - i - 1);
+}
+
+/* ---------------------------------------------------------------------------------------
+ * NCC: rho_ij = sum_k (a_k - mu_a)(b_k - mu_b) / sqrt(sum_k (a_k-mu_a)^2 * sum_k (b_k-mu_b)^2)
+ * ------------------------------------------------------------------------------------- */
+
+/* Per-item mean and sum of squared deviations (two passes, FP64). */
+void oracle_ncc_stats(const float *X, int64_t n, int64_t d, int64_t ld, double *mu, double *ss)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < n; ++i) {
+        const float *a = X + i * ld;
+        double s = 0.0;
+        for (int64_t k = 0; k < d; ++k) s += (double)a[k];
+        double m = s / (double)d;
+        double q = 0.0;
+        for (int64_t k = 0; k < d; ++k) {
+            double c = (double)a[k] - m;
+            q += c * c;
+        }
+        mu[i] = m;
+        ss[i] = q;
+    }
+}
+
+/* rho for each listed pair, plus the error scale tau = sqrt(sum_k ahat_k^2 bhat_k^2) of
+ * the dot product of the two centred, unit-norm vectors.  A zero-variance item gives NaN. */
+void oracle_ncc_pairs(const float *X, int64_t d, int64_t ld, const double *mu, const double *ss,
+                      const int64_t *pi, const int64_t *pj, int64_t np, double *rho, double *tau)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t p = 0; p < np; ++p) {
+        const int64_t i = pi[p], j = pj[p];
+        const float *a = X + i * ld;
+        const float *b = X + j * ld;
+        const double ma = mu[i], mb = mu[j];
+        const double na = sqrt(ss[i]), nb = sqrt(ss[j]);
+        double cross = 0.0, t2 = 0.0;
+        for (int64_t k = 0; k < d; ++k) {
+            double ca = (double)a[k] - ma;
+            double cb = (double)b[k] - mb;
+            cross += ca * cb;
+            double ha = ca / na, hb = cb / nb;
+            t2 += ha * ha * hb * hb;
+        }
+        if (ss[i] > 0.0 && ss[j] > 0.0) {
+            rho[p] = cross / sqrt(ss[i] * ss[j]);
+            if (tau) tau[p] = sqrt(t2);
+        } else {
+            rho[p] = NAN;
+            if (tau) tau[p] = NAN;
+        }
+    }
+}
+
+/* ---------------------------------------------------------------------------------------
+ * Gaussian overlap: C_ij = sum_k sum_l exp(-|x_k - y_l|^2 / (4 sigma^2)),
+ * x = points of cloud i, y = points of cloud j (interleaved f32 xy, offsets per cloud).
+ * kappa_ij = sum |e_kl| w_kl / sum w_kl is the cost-weighted mean |exponent|; it sets
+ * how much FP32 rounding of the exponent a GPU result may legitimately carry.
+ * ------------------------------------------------------------------------------------- */
+void oracle_overlap_pairs(const float *xy, const int64_t *off, double sigma, const int64_t *pi,
+                          const int64_t *pj, int64_t np, double *cost, double *kappa)
+{
+    const double inv4s2 = 1.0 / (4.0 * sigma * sigma);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t p = 0; p < np; ++p) {
+        const int64_t i = pi[p], j = pj[p];
+        double c = 0.0, ce = 0.0;
+        for (int64_t k = off[i]; k < off[i + 1]; ++k) {
+            const double xk = xy[2 * k], yk = xy[2 * k + 1];
+            for (int64_t l = off[j]; l < off[j + 1]; ++l) {
+                const double dx = xk - (double)xy[2 * l];
+                const double dy = yk - (double)xy[2 * l + 1];
+                const double e = (dx * dx + dy * dy) * inv4s2;
+                const double w = exp(-e);
+                c += w;
+                ce += e * w;
+            }
+        }
+        cost[p] = c;
+        if (kappa) kappa[p] = c > 0.0 ? ce / c : 0.0;
+    }
+}
+
+/* ---------------------------------------------------------------------------------------
+ * Registration gradient.  For pair p = (i, j) and transform q = (theta, tx, ty):
+ *   y'_l = R(theta) (y_l - c_j) + c_j + t,   u_kl = y'_l - x_k,
+ *   w_kl = exp(-|u_kl|^2 / (4 sigma^2)),     C = sum w_kl,
+ *   dC/dt     = -(1/(2 sigma^2)) sum w_kl u_kl
+ *   dC/dtheta = -(1/(2 sigma^2)) sum w_kl <u_kl, dR/dtheta (y_l - c_j)>
+ * (dR/dtheta (y - c) = J R(theta)(y - c) with J the 90-degree rotation.)
+ * tau[p][m] = sqrt(sum_kl (d term_kl / d q_m)^2) * max(1, kappa/50) is the error floor
+ * for a signed sum of that many FP32 terms.  Params are double so finite differences
+ * can step them exactly.
+ * ------------------------------------------------------------------------------------- */
+void oracle_overlap_grad_pairs(const float *xy, const int64_t *off, const float *cen, double sigma,
+                               const int64_t *pi, const int64_t *pj, const double *params, int64_t np,
+                               double *cost, double *grad, double *tau, double *kappa)
+{
+    const double inv4s2 = 1.0 / (4.0 * sigma * sigma);
+    const double g = 2.0 * inv4s2; /* 1/(2 sigma^2) */
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t p = 0; p < np; ++p) {
+        const int64_t i = pi[p], j = pj[p];
+        const double th = params[3 * p], tx = params[3 * p + 1], ty = params[3 * p + 2];
+        const double ct = cos(th), st = sin(th);
+        const double cx = cen[2 * j], cy = cen[2 * j + 1];
+        double c = 0.0, ce = 0.0, gth = 0.0, gx = 0.0, gy = 0.0;
+        double q0 = 0.0, q1 = 0.0, q2 = 0.0;
+        for (int64_t l = off[j]; l < off[j + 1]; ++l) {
+            const double rx = (double)xy[2 * l] - cx, ry = (double)xy[2 * l + 1] - cy;
+            const double ox = ct * rx - st * ry, oy = st * rx + ct * ry; /* R (y - c) */
+            const double vx = -oy, vy = ox;                              /* dR/dtheta (y - c) */
+            const double yx = ox + cx + tx, yy = oy + cy + ty;
+            for (int64_t k = off[i]; k < off[i + 1]; ++k) {
+                const double ux = yx - (double)xy[2 * k];
+                const double uy = yy - (double)xy[2 * k + 1];
+                const double e = (ux * ux + uy * uy) * inv4s2;
+                const double w = exp(-e);
+                const double dth = -g * w * (ux * vx + uy * vy);
+                const double dx = -g * w * ux, dy = -g * w * uy;
+                c += w;
+                ce += e * w;
+                gth += dth;
+                gx += dx;
+                gy += dy;
+                q0 += dth * dth;
+                q1 += dx * dx;
+                q2 += dy * dy;
+            }
+        }
+        cost[p] = c;
+        grad[3 * p] = gth;
+        grad[3 * p + 1] = gx;
+        grad[3 * p + 2] = gy;
+        const double kap = c > 0.0 ? ce / c : 0.0;
+        if (kappa) kappa[p] = kap;
+        if (tau) {
+            const double f = kap > 50.0 ? kap / 50.0 : 1.0;
+            tau[3 * p] = sqrt(q0) * f;
+            tau[3 * p + 1] = sqrt(q1) * f;
+            tau[3 * p + 2] = sqrt(q2) * f;
+        }
+    }
+}
+
+/* ---------------------------------------------------------------------------------------
+ * Sparse cosine.  Each item is a list of strictly ascending int64 keys with f32 values.
+ * count = |K_i intersect K_j| by a two-pointer merge; dot = sum over shared keys of
+ * v_i * v_j; cos = dot / (|v_i|_2 |v_j|_2) with the norms over all entries of each item;
+ * keysum = wrapping 64-bit sum of the shared keys (an exactness witness).
+ * ------------------------------------------------------------------------------------- */
+void oracle_sparse_pairs(const int64_t *keys, const float *vals, const int64_t *off, const int64_t *pi,
+                         const int64_t *pj, int64_t np, double *cosv, int64_t *count, uint64_t *keysum)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t p = 0; p < np; ++p) {
+        const int64_t i = pi[p], j = pj[p];
+        int64_t a = off[i], ae = off[i + 1], b = off[j], be = off[j + 1];
+        double ni = 0.0, nj = 0.0;
+        for (int64_t k = a; k < ae; ++k) ni += (double)vals[k] * (double)vals[k];
+        for (int64_t k = b; k < be; ++k) nj += (double)vals[k] * (double)vals[k];
+        double dot = 0.0;
+        int64_t m = 0;
+        uint64_t ks = 0;
+        while (a < ae && b < be) {
+            if (keys[a] < keys[b]) {
+                ++a;
+            } else if (keys[b] < keys[a]) {
+                ++b;
+            } else {
+                dot += (double)vals[a] * (double)vals[b];
+                ++m;
+                ks += (uint64_t)keys[a];
+                ++a;
+                ++b;
+            }
+        }
+        cosv[p] = dot / (sqrt(ni) * sqrt(nj));
+        if (count) count[p] = m;
+        if (keysum) keysum[p] = ks;
+    }
+}
+
+/* Number of OpenMP threads the pair loops use (reported beside CPU timings). */
+int oracle_num_threads(void)
+{
+    int t = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        {
+#ifdef _OPENMP
+            extern int omp_get_num_threads(void);
+            t = omp_get_num_threads();
+#endif
+        }
+    }
+    return t;
+}
