@@ -1,0 +1,229 @@
+#!/usr/bin/env python3
+"""All-pairs benchmark on one MI355X.
+
+Workload: normalised cross-correlation of every pair of 4096 dense noise patterns of
+1,048,576 float32 values (64 N(0,1) sources, item = 0.02 * source + N(0,1), zero-mean and
+unit-norm), computed with the BF16 three-way split on the matrix cores (six bf16 products,
+FP32 accumulation).  One step = the whole hot path for one batch: per-item FP64 statistics
+and split (prepare), the persistent tile kernel over the divide-and-conquer queue, and the
+split-K epilogue into the packed upper triangle (8,386,560 results).
+
+Prints ONE JSON line.  ``value`` is pairs/s; ``roofline`` is the Gram kernel's algorithmic
+2*d flop per pair against the bf16 dense MFMA peak; ``cpu_baseline`` times the FP64 oracle
+on a bounded sample of the same workload on this host.  Extra fields report the plain
+FP32 and two-term split paths at the same shape and the other two pair functions.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "pairs/sec + % roofline per pair fn; BF16-split vs FP32 on same GPU at ≤1e-5 err"
+PEAK_BF16 = 2500.0      # TFLOP/s, dense bf16 MFMA
+PEAK_FP32_MFMA = 157.3  # TFLOP/s
+PEAK_HBM = 8000.0       # GB/s
+# VALU: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz = 3.93e13 lane-ops/s
+VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "ncc_gram_bf16x6_4096x1048576_counters.txt")
+
+
+def _src_hash(*names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2009_04755_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic_from_profile():
+    """HBM bytes per gram launch from the committed rocprofv3 counter summary, if it was
+    taken on the current kernel source; else None."""
+    if not os.path.exists(COUNTERS_FILE):
+        return None
+    vals = {}
+    with open(COUNTERS_FILE) as f:
+        for line in f:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != _src_hash("ncc.hip", "queue.hpp"):
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def _ensure_built():
+    from paper_2009_04755_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2009_04755_amd import build
+        build.build()
+
+
+def _time_fn(ctx, x, fn, out, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        ctx.allpairs(x, fn, out=out)
+    torch.cuda.synchronize()
+    kern = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.allpairs(x, fn, out=out)
+        kern.append(ctx.stats()["kernel_ns"] * 1e-9)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dt, sum(kern) / len(kern)
+
+
+def cpu_baseline(X, out, n, budget_s=15.0):
+    """FP64 oracle on pairs among the first rows of the workload; also a parity sample."""
+    import numpy as np
+    import oracle
+
+    rows = 24
+    Xh = X[:rows].cpu().numpy()
+    pi, pj = oracle.all_pairs(rows)
+    t0 = time.perf_counter()
+    oracle.ncc(Xh, pi[:8], pj[:8])
+    est = (time.perf_counter() - t0) / 8
+    m = int(max(8, min(pi.size, budget_s / max(est, 1e-6))))
+    reps = 1
+    while m * reps * est < budget_s * 0.5 and reps < 8:
+        reps += 1
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        rho, tau = oracle.ncc(Xh, pi[:m], pj[:m])
+    dt = time.perf_counter() - t0
+    idx = pi[:m] * n - pi[:m] * (pi[:m] + 1) // 2 + (pj[:m] - pi[:m] - 1)
+    got = out.cpu().numpy()[idx]
+    err = np.abs(got - rho) / np.maximum(np.abs(rho), tau)
+    return ({"value": m * reps / dt, "unit": "pairs/s", "cores": oracle.num_threads(), "kind": "oracle",
+             "sample": "%d pairs among the first %d of the 4096 patterns (1,048,576 values each), %d pass(es); "
+                       "FP64 stats + pair loop, data already in host memory" % (m, rows, reps)},
+            {"pairs": int(m), "max_floored_rel_err": float(err.max())})
+
+
+def other_pair_fns(ctx):
+    """Gaussian overlap (2048 uneven clouds), its 20-step registration, one line each."""
+    import numpy as np
+    import torch
+    from paper_2009_04755_amd import Clouds, register, synth
+
+    res = {}
+    off, xy = synth.point_clouds(2048, config=2)
+    cl = Clouds(torch.from_numpy(off).cuda(), torch.from_numpy(xy).cuda(), 0.02)
+    P = 2048 * 2047 // 2
+    out = torch.empty(P, device="cuda")
+    ctx.set(ovl_variant=0, ovl_block=0)
+    dt, kern = _time_fn(ctx, cl, "gauss_overlap", out, 5, 1)
+    cnt = np.diff(off).astype(np.float64)
+    terms = (cnt.sum() ** 2 - (cnt ** 2).sum()) / 2
+    # per term: 2 sub, mul, fma, mul, add (VALU) + exp (transcendental, counted as 4 slots)
+    peak_terms = VALU_LANE_OPS / 10.0
+    res["gauss_overlap"] = {"workload": "2048 clouds, 50..400 points, sigma 0.02", "pairs_per_s": 5 * P / dt,
+                            "kernel_ms": kern * 1e3, "terms_per_s": terms / kern,
+                            "roofline": {"bound": "alu", "achieved": terms / kern, "peak": peak_terms,
+                                         "unit": "terms/s", "frac": terms / kern / peak_terms}}
+    cen = torch.from_numpy(synth.cloud_centroids(off, xy)).cuda()
+    p0 = torch.from_numpy(synth.rigid_starts(P, config=3)).cuda()
+    register(cl, cen, p0, steps=1, ctx=ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    register(cl, cen, p0, steps=20, ctx=ctx)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern = ctx.stats()["kernel_ns"] * 1e-9
+    peak_g = VALU_LANE_OPS / 14.0  # 8 VALU + 2 hi/lo adds + exp (4 slots) per term
+    res["overlap_grad_20_steps"] = {"workload": "same clouds, adjoint of (theta, tx, ty), 20 GD steps",
+                                    "pair_steps_per_s": 20 * P / dt, "kernel_ms": kern * 1e3,
+                                    "roofline": {"bound": "alu", "achieved": terms / kern, "peak": peak_g,
+                                                 "unit": "terms/s", "frac": terms / kern / peak_g}}
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device copy (reference for HBM counter scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path (requested %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    _ensure_built()
+    from paper_2009_04755_amd import Context, synth
+
+    torch.cuda.set_device(0)
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    n, d = 4096, 1 << 20
+    P = n * (n - 1) // 2
+    X, _ = synth.dense_patterns_device(n, d, 64, 0.02, seed=1, device="cuda")
+    ctx = Context(0)
+    ctx.set(timing=1)
+    out = torch.empty(P, dtype=torch.float32, device="cuda")
+
+    dt, kern = _time_fn(ctx, X, "ncc_bf16x6", out, args.steps, args.warmup)
+    st = ctx.stats()
+    value = P * args.steps / dt
+    flop = 2.0 * d * P
+    achieved = flop / kern / 1e12
+    issued = 6 * 2.0 * st["tile"] ** 2 * ((d + 15) // 16 * 16) * st["tiles"]
+    traffic = _traffic_from_profile()
+    rec = {
+        "metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic (seeded, generated on the device)",
+        "config": {"workload": "NCC all pairs of 4096 patterns x 1,048,576 f32 values, BF16 3-way split "
+                               "(6 bf16 MFMA products, FP32 accumulation)",
+                   "n": n, "d": d, "pairs": P, "pair_fn": "ncc_bf16x6", "tile": st["tile"],
+                   "kchunk": st["kchunk"], "work_items": st["work_items"], "grid": st["grid"]},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_BF16, "traffic": traffic,
+                     "kernel": "k_ncc_gram<256, bf16x6>", "kernel_ms": kern * 1e3,
+                     "algorithmic_flop_per_launch": flop, "issued_mfma_flop_per_launch": issued,
+                     "issued_frac": issued / kern / 1e12 / PEAK_BF16},
+    }
+    for fn, peak in (("ncc_fp32", PEAK_FP32_MFMA), ("ncc_bf16x3", PEAK_BF16)):
+        dt2, kern2 = _time_fn(ctx, X, fn, out, 3, 1)
+        rec[fn] = {"pairs_per_s": 3 * P / dt2, "ms_per_step": dt2 / 3 * 1e3, "kernel_ms": kern2 * 1e3,
+                   "frac_of_own_peak": flop / kern2 / 1e12 / peak}
+    rec["bf16x6_speedup_vs_fp32"] = value / rec["ncc_fp32"]["pairs_per_s"]
+    # leave the BF16x6 result in `out` for the parity sample
+    ctx.allpairs(X, "ncc_bf16x6", out=out)
+    torch.cuda.synchronize()
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"], rec["parity_sample"] = cpu_baseline(X, out, n)
+    if not args.no_extras:
+        del X
+        torch.cuda.empty_cache()
+        rec["pair_fns"] = other_pair_fns(ctx)
+    print(json.dumps(rec))
+    sys.stdout.flush()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,224 @@
+/*
+ * rocket.h -- C ABI of the MI355X (gfx950) all-pairs library.
+ *
+ * The all-pairs problem (Section III of Heldens et al., "Rocket: Efficient and
+ * Scalable All-Pairs Computations on Heterogeneous Platforms", arXiv 2009.04755):
+ * for n items and a pair function f, compute f(l(i), l(j)) for every pair
+ * 1 <= i < j <= n, where l(i) loads and pre-processes item i.  The paper splits l
+ * into load / parse / host-to-device / GPU pre-process and f into GPU compare /
+ * device-to-host / post-process (Section III, Fig. "pipeline").  This library is
+ * the GPU part of that pipeline for one device:
+ *
+ *   rocket_prepare   the GPU pre-process stage of l for all n items at once;
+ *   rocket_compare   the GPU compare stage of f for all n(n-1)/2 pairs, as one
+ *                    persistent launch that pulls tiles of the pair matrix from an
+ *                    on-device queue (Section IV-B's divide-and-conquer split and
+ *                    work stealing, mapped onto the chip);
+ *   rocket_allpairs  both, back to back.
+ *
+ * Three pair functions are provided, one per application of Section V:
+ *   ROCKET_NCC_*          normalised cross-correlation of dense vectors (V-A);
+ *   ROCKET_GAUSS_OVERLAP  Gaussian-mixture overlap of 2-D point clouds (V-C);
+ *   ROCKET_SPARSE_COSINE  cosine of sparse key/value vectors plus the exact size
+ *                         of the key intersection (V-B);
+ * and rocket_overlap_cost_grad gives the overlap cost's gradient with respect to a
+ * rigid transform per pair (the registration optimiser of V-C).
+ *
+ * OUTPUT LAYOUT.  Results are written in the caller's item order as the packed
+ * strict upper triangle, row-major: pair (i, j), i < j, lands at
+ *     idx(i, j) = i*n - i*(i+1)/2 + (j - i - 1),   0 <= idx < P = n(n-1)/2.
+ *
+ * POINTERS AND OWNERSHIP.  Unless a comment says "host", every pointer is a DEVICE
+ * pointer on the context's device.  The caller allocates and owns every input and
+ * output; the library reads inputs and writes outputs only inside the work it
+ * enqueues on the given stream and keeps no reference after that work completes
+ * (rocket_compare re-reads the items passed to the last rocket_prepare, so they
+ * must stay alive and unchanged until compare's work is done).  The context owns
+ * its workspace (prepared item copies, split-K partials, work queue), grows it
+ * with hipMalloc on demand and frees it in rocket_destroy.
+ *
+ * STREAMS.  `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ * Every call is stream-ordered; calls return once the work is enqueued, except
+ * where a comment says the call synchronises.  A context must not be used from
+ * two host threads at once; calls on one context must not overlap on the device
+ * with different streams.
+ *
+ * ERRORS.  Every entry point returns a rocket_status.  Argument checks (null
+ * pointers, negative sizes, ld < dim, unknown function) happen before anything is
+ * enqueued.  Data checks that need the data (ragged offsets, sparse key order and
+ * range) run on the device in rocket_prepare, which then synchronises once to read
+ * the verdict.  After a failure the context stays usable; rocket_last_error
+ * returns a message describing the most recent failure.
+ */
+#ifndef ROCKET_H
+#define ROCKET_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ROCKET_OK = 0,
+    ROCKET_E_INVALID = -1,     /* bad argument: null pointer, negative size, ld < dim, bad offsets */
+    ROCKET_E_UNSUPPORTED = -2, /* unknown pair function or option */
+    ROCKET_E_OOM = -3,         /* workspace allocation failed (or exceeds ROCKET_OPT_WORKSPACE_CAP) */
+    ROCKET_E_HIP = -4,         /* a HIP runtime call failed; see rocket_last_error */
+    ROCKET_E_KEYRANGE = -5,    /* sparse key outside [0, 2^32) */
+    ROCKET_E_UNSORTED = -6,    /* sparse keys of an item not strictly ascending */
+    ROCKET_E_STATE = -7        /* rocket_compare without a matching rocket_prepare */
+} rocket_status;
+
+typedef enum {
+    /* NCC (Section V-A): rho_ij = <a_i - mean a_i, a_j - mean a_j> / (|a_i - mean a_i| |a_j - mean a_j|).
+     * Per-item mean and centred norm are reduced in FP64; the centred items are
+     * compared as a Gram matrix on the matrix cores with FP32 accumulation:
+     *   FP32   FP32 operands (v_mfma_f32_32x32x2_f32);
+     *   BF16X3 each centred value x split into bf16 h + m (x ~ h + m), products
+     *          h*h + h*m + m*h (bf16 MFMA);
+     *   BF16X6 three-way split h + m + l, products h*h + h*m + m*h + h*l + l*h + m*m.
+     * The Gram entry is rescaled by 1/(s_i s_j) in FP32.  A zero-variance item
+     * gives NaN in all its pairs. */
+    ROCKET_NCC_FP32 = 1,
+    ROCKET_NCC_BF16X3 = 2,
+    ROCKET_NCC_BF16X6 = 3,
+    /* Gaussian overlap (Section V-C): C_ij = sum_k sum_l exp(-|x_k - y_l|^2 / (4 sigma^2)),
+     * x the points of cloud i, y those of cloud j.  FP32 arithmetic, per-lane
+     * partial sums reduced by a fixed wavefront tree.  An empty cloud gives 0. */
+    ROCKET_GAUSS_OVERLAP = 4,
+    /* Sparse cosine (Section V-B): cos_ij = sum_{k in K_i & K_j} v_ik v_jk / (|v_i| |v_j|),
+     * norms over all entries of an item (FP64 reduction).  out_counts, when given,
+     * receives |K_i & K_j| exactly.  A zero-norm item gives NaN; m_ij = 0 gives 0. */
+    ROCKET_SPARSE_COSINE = 5
+} rocket_pair_fn;
+
+/* The item set.  Which fields are read depends on the pair function; unused
+ * fields are ignored.  All pointers are device pointers. */
+typedef struct {
+    /* NCC: row-major float32 [n][ld]; item i is dense[i*ld .. i*ld + dim). */
+    const float *dense;
+    int64_t dim;
+    int64_t ld;
+    /* Ragged sets (overlap, sparse): item i owns entries offsets[i] .. offsets[i+1]-1;
+     * int64 [n+1], offsets[0] = 0, non-decreasing. */
+    const int64_t *offsets;
+    /* Overlap: interleaved float32 (x, y) per point, [2 * offsets[n]]; sigma > 0. */
+    const float *xy;
+    double sigma;
+    /* Sparse: int64 keys [offsets[n]], strictly ascending within an item and in
+     * [0, 2^32); float32 values [offsets[n]]. */
+    const int64_t *keys;
+    const float *vals;
+} rocket_items;
+
+typedef struct rocket_ctx rocket_ctx;
+
+/* Create a context on HIP device `device` (host pointer out).  Allocates nothing on
+ * the device until the first prepare. */
+rocket_status rocket_create(rocket_ctx **out, int device);
+/* Free the context and its workspace (synchronises the device first).  NULL is a no-op. */
+void rocket_destroy(rocket_ctx *ctx);
+/* Static, human-readable name of a status code. */
+const char *rocket_status_str(rocket_status status);
+/* Message for the most recent failure on ctx (or on the default contexts if ctx is
+ * NULL); valid until the next call on that context. */
+const char *rocket_last_error(const rocket_ctx *ctx);
+
+/* Pre-process stage (the GPU part of l, Section III) for n items under pair function
+ * fn, enqueued on `stream`.  Keeps what compare needs in the context's workspace. */
+rocket_status rocket_prepare(rocket_ctx *ctx, const rocket_items *items, int64_t n, rocket_pair_fn fn,
+                             void *stream);
+
+/* Compare stage (the GPU part of f) for every pair of the last prepared set.
+ * out: float32 [P] packed upper triangle (required when P > 0).
+ * out_counts: uint32 [P] intersection sizes, sparse cosine only; may be NULL. */
+rocket_status rocket_compare(rocket_ctx *ctx, float *out, uint32_t *out_counts, void *stream);
+
+/* rocket_prepare followed by rocket_compare on `stream`. */
+rocket_status rocket_allpairs_ex(rocket_ctx *ctx, const rocket_items *items, int64_t n, rocket_pair_fn fn,
+                                 float *out, uint32_t *out_counts, void *stream);
+
+/* The whole all-pairs evaluation on the calling thread's current device, with a
+ * library-owned default context per device and the null stream; synchronises
+ * before returning.  out: float32 [n(n-1)/2]. */
+rocket_status rocket_allpairs(const rocket_items *items, int64_t n, rocket_pair_fn fn, float *out_upper_triangle);
+
+/* Registration gradient (Section V-C optimiser).  For every pair (i, j), i < j, and
+ * its transform q = params[idx(i,j)] = (theta, tx, ty), the second cloud is moved as
+ *     y'_l = R(theta) (y_l - c_j) + c_j + t,   c_j = centroids[j],
+ * and the overlap cost C = sum_k sum_l exp(-|y'_l - x_k|^2 / (4 sigma^2)) is returned
+ * with its gradient
+ *     dC/dt     = -(1/(2 sigma^2)) sum w_kl (y'_l - x_k)
+ *     dC/dtheta = -(1/(2 sigma^2)) sum w_kl <y'_l - x_k, dR/dtheta (y_l - c_j)>.
+ * clouds: offsets + xy + sigma as for ROCKET_GAUSS_OVERLAP (this call prepares them
+ * itself, reusing the last overlap preparation when the same arrays are passed).
+ * centroids: float32 [n][2].  params: float32 [P][3].  out_cost: float32 [P].
+ * out_grad: float32 [P][3] (theta, tx, ty), may be NULL for cost only.
+ * Outputs are in packed upper-triangle order.  Enqueued on `stream`. */
+rocket_status rocket_overlap_cost_grad(rocket_ctx *ctx, const rocket_items *clouds, int64_t n,
+                                       const float *centroids, const float *params, float *out_cost,
+                                       float *out_grad, void *stream);
+
+/* Tunables.  0 means "choose automatically" for every option. */
+typedef enum {
+    ROCKET_OPT_NCC_TILE = 1,        /* NCC output tile edge: 64, 128 or 256 items */
+    ROCKET_OPT_NCC_KCHUNK = 2,      /* NCC split-K chunk length, a multiple of 16 elements */
+    ROCKET_OPT_GRID = 3,            /* persistent grid size in workgroups */
+    ROCKET_OPT_QUEUE_ORDER = 4,     /* 0 planned (D&C order in per-XCD segments), 1 shuffled (by ROCKET_OPT_SEED),
+                                       2 planned order in one segment */
+    ROCKET_OPT_SEED = 5,            /* seed for the shuffled queue order */
+    ROCKET_OPT_LEDGER = 6,          /* 1: record how often each work item is popped (rocket_get_ledger) */
+    ROCKET_OPT_OVL_BLOCK = 7,       /* overlap: clouds per block of the tile grid */
+    ROCKET_OPT_OVL_VARIANT = 8,     /* overlap: inner-loop variant 1..3 (lanes per cloud chunk) */
+    ROCKET_OPT_SP_ROWS = 9,         /* sparse: items per row band */
+    ROCKET_OPT_SP_CHUNK = 10,       /* sparse: key-range chunk width (power of two) */
+    ROCKET_OPT_WORKSPACE_CAP = 11,  /* bytes; workspace growth beyond it fails with ROCKET_E_OOM */
+    ROCKET_OPT_AUTOTUNE = 12,       /* 1: rocket_prepare of ragged sets runs the tile-shape autotuner */
+    ROCKET_OPT_TIMING = 13          /* 1: bracket each compare's main persistent kernel with HIP events on the
+                                       launch stream; rocket_get_stats reports its duration */
+} rocket_option;
+
+rocket_status rocket_set_option(rocket_ctx *ctx, rocket_option opt, int64_t value);
+rocket_status rocket_get_option(const rocket_ctx *ctx, rocket_option opt, int64_t *value /* host */);
+
+/* Facts about the last prepare/compare, for benchmarks and tests. */
+typedef struct {
+    int64_t n;               /* items */
+    int64_t pairs;           /* n(n-1)/2 */
+    int64_t tiles;           /* leaves of the divide-and-conquer split */
+    int64_t work_items;      /* queue entries (tiles x split-K chunks, or tiles) */
+    int64_t grid;            /* persistent workgroups launched */
+    int64_t tile;            /* tile edge in items (NCC) or clouds/items per block */
+    int64_t kchunk;          /* NCC split-K chunk length (0 otherwise) */
+    int64_t workspace_bytes; /* device bytes currently held by the context */
+    int64_t variant;         /* kernel variant in use */
+    int64_t kernel_ns;       /* duration of the last main kernel (ROCKET_OPT_TIMING=1), else -1;
+                                reading it waits for that kernel to finish */
+} rocket_stats;
+
+rocket_status rocket_get_stats(const rocket_ctx *ctx, rocket_stats *out /* host */);
+
+/* Copy the pop counts of the last compare (ROCKET_OPT_LEDGER=1) into host array out
+ * [cap]; *count receives the number of work items.  Synchronises the device. */
+rocket_status rocket_get_ledger(rocket_ctx *ctx, int32_t *out /* host */, int64_t cap, int64_t *count /* host */);
+
+/* Autotuner (ragged pair functions): time candidate tile shapes on a subsample of
+ * the prepared set's tiles and keep the fastest in the context (synchronises).
+ * The chosen values are readable through rocket_get_option. */
+rocket_status rocket_autotune(rocket_ctx *ctx, void *stream);
+
+/* Host-only planner, no device needed: the divide-and-conquer leaves for n items
+ * with tiles of T items (Section IV-B: recursive quadrant split of the upper
+ * triangle, empty quadrants skipped), in visiting order (top-left, top-right,
+ * bottom-left, bottom-right).  Writes up to cap leaves to host arrays bi, bj and
+ * returns the number of leaves (negative status on bad arguments). */
+int64_t rocket_plan_tiles(int64_t n, int64_t T, int32_t *bi /* host */, int32_t *bj /* host */, int64_t cap);
+
+/* Packed upper-triangle index of pair (i, j), i < j < n (host helper). */
+int64_t rocket_pair_index(int64_t i, int64_t j, int64_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ROCKET_H */

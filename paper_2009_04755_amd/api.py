@@ -1,0 +1,250 @@
+"""Python binding over the C ABI: torch tensors in, torch tensors out.
+
+PyTorch provides device memory, streams and autograd only; every step of the
+all-pairs evaluation runs in the HIP library.  Work is enqueued on
+``torch.cuda.current_stream()``.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+
+NCC_FNS = ("ncc_fp32", "ncc_bf16x3", "ncc_bf16x6")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def num_pairs(n: int) -> int:
+    return n * (n - 1) // 2
+
+
+@dataclass
+class Clouds:
+    """Ragged 2-D point clouds: cloud i owns points offsets[i] .. offsets[i+1]-1 of xy."""
+    offsets: torch.Tensor  # int64 [n+1], device
+    xy: torch.Tensor       # float32 [2 * total] interleaved (x, y), device
+    sigma: float = 0.02
+
+    @property
+    def n(self) -> int:
+        return self.offsets.numel() - 1
+
+
+@dataclass
+class SparseSet:
+    """Ragged sparse vectors: item i owns keys/vals offsets[i] .. offsets[i+1]-1."""
+    offsets: torch.Tensor  # int64 [n+1], device
+    keys: torch.Tensor     # int64 [total], strictly ascending per item, device
+    vals: torch.Tensor     # float32 [total], device
+
+    @property
+    def n(self) -> int:
+        return self.offsets.numel() - 1
+
+
+class Context:
+    """One ``rocket_ctx``: workspace, plan cache and options on one device."""
+
+    def __init__(self, device=None):
+        L = _lib.load()
+        dev = torch.cuda.current_device() if device is None else torch.device(device).index or 0
+        self.device = dev
+        h = ctypes.c_void_p()
+        _lib.check(L.rocket_create(ctypes.byref(h), dev))
+        self.handle = h
+        self._n = 0
+
+    def close(self):
+        if self.handle:
+            _lib.load().rocket_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set(self, **opts):
+        L = _lib.load()
+        for k, v in opts.items():
+            _lib.check(L.rocket_set_option(self.handle, _lib.OPT[k], int(v)), self.handle)
+        return self
+
+    def get(self, name: str) -> int:
+        v = ctypes.c_int64()
+        _lib.check(_lib.load().rocket_get_option(self.handle, _lib.OPT[name], ctypes.byref(v)), self.handle)
+        return v.value
+
+    def stats(self) -> dict:
+        s = _lib.Stats()
+        _lib.check(_lib.load().rocket_get_stats(self.handle, ctypes.byref(s)), self.handle)
+        return {name: getattr(s, name) for name, _ in _lib.Stats._fields_}
+
+    def ledger(self):
+        import numpy as np
+        L = _lib.load()
+        cnt = ctypes.c_int64()
+        _lib.check(L.rocket_get_ledger(self.handle, None, 0, ctypes.byref(cnt)), self.handle)
+        out = np.zeros(cnt.value, dtype=np.int32)
+        _lib.check(L.rocket_get_ledger(self.handle, out.ctypes.data_as(ctypes.c_void_p), cnt.value,
+                                       ctypes.byref(cnt)), self.handle)
+        return out
+
+    # -- items ----------------------------------------------------------------------------
+    @staticmethod
+    def _items(x, fn: int):
+        it = _lib.Items()
+        if fn in (_lib.NCC_FP32, _lib.NCC_BF16X3, _lib.NCC_BF16X6):
+            assert x.dtype == torch.float32 and x.dim() == 2 and x.stride(1) == 1 and x.is_cuda
+            it.dense = x.data_ptr()
+            it.dim = x.shape[1]
+            it.ld = x.stride(0) if x.shape[0] > 1 else x.shape[1]
+            return it, x.shape[0]
+        if fn == _lib.GAUSS_OVERLAP:
+            assert isinstance(x, Clouds)
+            assert x.offsets.dtype == torch.int64 and x.xy.dtype == torch.float32 and x.xy.is_cuda
+            it.offsets = x.offsets.data_ptr()
+            it.xy = x.xy.data_ptr()
+            it.sigma = float(x.sigma)
+            return it, x.n
+        if fn == _lib.SPARSE_COSINE:
+            assert isinstance(x, SparseSet)
+            assert x.offsets.dtype == torch.int64 and x.keys.dtype == torch.int64 and x.vals.dtype == torch.float32
+            it.offsets = x.offsets.data_ptr()
+            it.keys = x.keys.data_ptr()
+            it.vals = x.vals.data_ptr()
+            return it, x.n
+        raise ValueError(fn)
+
+    def prepare(self, x, fn: str):
+        code = _lib.FN_BY_NAME[fn]
+        it, n = self._items(x, code)
+        self._keep = (x, it)
+        _lib.check(_lib.load().rocket_prepare(self.handle, ctypes.byref(it), n, code, _stream()), self.handle)
+        self._n = n
+        self._fn = fn
+        return self
+
+    def compare(self, out=None, counts: bool = False):
+        n = self._n
+        P = num_pairs(n)
+        dev = torch.device("cuda", self.device)
+        if out is None:
+            out = torch.empty(P, dtype=torch.float32, device=dev)
+        cnt = torch.empty(P, dtype=torch.int32, device=dev) if counts else None
+        _lib.check(_lib.load().rocket_compare(self.handle, _ptr(out), _ptr(cnt), _stream()), self.handle)
+        return (out, cnt) if counts else out
+
+    def allpairs(self, x, fn: str, out=None, counts: bool = False):
+        self.prepare(x, fn)
+        return self.compare(out=out, counts=counts)
+
+    def autotune(self):
+        _lib.check(_lib.load().rocket_autotune(self.handle, _stream()), self.handle)
+        return {k: self.get(k) for k in ("ovl_block", "ovl_variant")}
+
+    def overlap_cost_grad(self, clouds: Clouds, centroids, params, with_grad: bool = True):
+        n = clouds.n
+        P = num_pairs(n)
+        it, _ = self._items(clouds, _lib.GAUSS_OVERLAP)
+        assert params.shape == (P, 3) and params.dtype == torch.float32 and params.is_contiguous()
+        assert centroids.shape == (n, 2) and centroids.dtype == torch.float32 and centroids.is_contiguous()
+        cost = torch.empty(P, dtype=torch.float32, device=params.device)
+        grad = torch.empty((P, 3), dtype=torch.float32, device=params.device) if with_grad else None
+        _lib.check(_lib.load().rocket_overlap_cost_grad(self.handle, ctypes.byref(it), n, _ptr(centroids),
+                                                        _ptr(params), _ptr(cost), _ptr(grad), _stream()),
+                   self.handle)
+        return cost, grad
+
+
+_default = {}
+
+
+def default_context() -> Context:
+    dev = torch.cuda.current_device()
+    if dev not in _default:
+        _default[dev] = Context(dev)
+    return _default[dev]
+
+
+def allpairs(x, fn: str, counts: bool = False, ctx: Context | None = None):
+    """All n(n-1)/2 pair results in packed upper-triangle order (float32 on the device).
+
+    ``x``: float32 [n][d] for the NCC functions, :class:`Clouds` for ``gauss_overlap``,
+    :class:`SparseSet` for ``sparse_cosine`` (``counts=True`` also returns the exact
+    intersection sizes).
+    """
+    return (ctx or default_context()).allpairs(x, fn, counts=counts)
+
+
+def plan_tiles(n: int, T: int):
+    """Host-only divide-and-conquer leaves (bi, bj) for n items and tile T."""
+    import numpy as np
+    L = _lib.load()
+    m = L.rocket_plan_tiles(n, T, None, None, 0)
+    if m < 0:
+        raise ValueError("bad arguments")
+    bi = np.zeros(max(m, 1), dtype=np.int32)
+    bj = np.zeros(max(m, 1), dtype=np.int32)
+    L.rocket_plan_tiles(n, T, bi.ctypes.data_as(ctypes.c_void_p), bj.ctypes.data_as(ctypes.c_void_p), m)
+    return list(zip(bi[:m].tolist(), bj[:m].tolist()))
+
+
+def pair_index(i: int, j: int, n: int) -> int:
+    return int(_lib.load().rocket_pair_index(i, j, n))
+
+
+class OverlapCost(torch.autograd.Function):
+    """Per-pair overlap cost C(params) with the hand-written adjoint as its gradient.
+
+    forward(params [P,3], clouds, centroids) -> cost [P]; backward(g [P]) -> g[:,None] * dC/dparams.
+    """
+
+    @staticmethod
+    def forward(ctx_, params, clouds: Clouds, centroids, rctx: Context | None = None):
+        rc = rctx or default_context()
+        cost, grad = rc.overlap_cost_grad(clouds, centroids, params.detach().contiguous(), with_grad=True)
+        ctx_.save_for_backward(grad)
+        return cost
+
+    @staticmethod
+    def backward(ctx_, g):
+        (grad,) = ctx_.saved_tensors
+        return g[:, None] * grad, None, None, None
+
+
+def register(clouds: Clouds, centroids, params0, steps: int = 20, lr: float = 0.01, ctx: Context | None = None,
+             record: bool = False):
+    """Rigid registration of every pair by gradient descent on E = -C / (N_i N_j).
+
+    Each step evaluates the cost and its adjoint once (one persistent launch) and moves
+    params <- params - lr * dE/dparams.  Returns the final params (and, with ``record``,
+    the list of iterates params_0 .. params_steps).
+    """
+    n = clouds.n
+    counts = (clouds.offsets[1:] - clouds.offsets[:-1]).to(torch.float32)
+    iu = torch.triu_indices(n, n, offset=1, device=params0.device)
+    norm = (counts[iu[0]] * counts[iu[1]]).clamp_min(1.0)
+    p = params0.detach().clone().contiguous().requires_grad_(True)
+    hist = [p.detach().clone()] if record else None
+    for _ in range(steps):
+        cost = OverlapCost.apply(p, clouds, centroids, ctx)
+        energy = -(cost / norm).sum()
+        (g,) = torch.autograd.grad(energy, p)
+        with torch.no_grad():
+            p -= lr * g
+        if record:
+            hist.append(p.detach().clone())
+    out = p.detach()
+    return (out, hist) if record else out

@@ -1,0 +1,155 @@
+// Internal declarations shared by the host library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/rocket.h"
+
+namespace rk {
+
+// Named workspace slots owned by a context.
+enum Slot {
+    WS_QUEUE_ITEMS = 0,  // int4 work items
+    WS_QUEUE_HEADS,      // per-segment pop counters
+    WS_QUEUE_SEGS,       // segment boundaries
+    WS_LEDGER,           // per-item pop counts (debug)
+    WS_FLAGS,            // device error flags
+    WS_NCC_STATS,        // mean (f64), inverse norm (f32)
+    WS_NCC_PLANES,       // split / centred operand planes
+    WS_NCC_PARTIAL,      // split-K partial Gram tiles
+    WS_NCC_TILES,        // tile list (bi, bj) for the epilogue
+    WS_OVL_PACK,         // size-sorted packed clouds
+    WS_OVL_META,         // per sorted cloud: offset, count, original index
+    WS_SP_KEYS,          // packed u32 keys
+    WS_SP_META,          // per item: norm, offsets
+    WS_SP_CHUNKS,        // per item key-chunk offsets
+    WS_COUNT
+};
+
+struct Buffer {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+// Work queue description handed to persistent kernels.
+struct QueueArgs {
+    const int4 *items;  // work items, grouped by segment
+    int *heads;         // one counter per segment, HEAD_STRIDE ints apart
+    const int *seg;     // nseg + 1 segment boundaries into items
+    int *ledger;        // optional per-item pop counter
+    int nseg;
+};
+constexpr int HEAD_STRIDE = 32;  // 128 bytes between segment counters
+constexpr int MAX_SEG = 8;       // one segment per XCD
+enum { QOWN_NONE = 0, QOWN_NCC, QOWN_OVL, QOWN_SP };
+
+struct NccState {
+    int64_t n = 0, dim = 0, ld = 0, n_pad = 0, d_pad = 0;
+    int tile = 0, nkt = 0, kt_per_chunk = 0, nchunks = 0;
+    int64_t tiles = 0, items = 0;
+    const float *src = nullptr;
+    int scheme = 0;
+    // plan cache: the uploaded queue matches these parameters
+    QueueArgs qa{};
+    int64_t pc_n = -1, pc_tile = -1, pc_nchunks = -1, pc_order = -1, pc_seed = -1, pc_ledger = -1;
+    std::vector<int2> h_tiles;
+};
+
+struct OvlState {
+    int64_t n = 0, total = 0;
+    const int64_t *offsets = nullptr;
+    const float *xy = nullptr;
+    double sigma = 0;
+    int block = 0;
+    int64_t tiles = 0, max_block_pts = 0;
+    std::vector<int64_t> h_offsets;  // host copy of offsets
+    std::vector<int> perm;           // sorted position -> original cloud
+    QueueArgs qa{};
+    int64_t pc_block = -1, pc_order = -1, pc_seed = -1, pc_ledger = -1;
+    bool valid = false;
+};
+
+struct SpState {
+    int64_t n = 0, total = 0;
+    const int64_t *offsets = nullptr;
+    const int64_t *keys = nullptr;
+    const float *vals = nullptr;
+    int rows = 0, chunk_log2 = 0, nchunks = 0;
+    int64_t tiles = 0;
+    std::vector<int64_t> h_offsets;
+    bool valid = false;
+};
+
+}  // namespace rk
+
+struct rocket_ctx {
+    int device = 0;
+    int num_cu = 256;
+    int64_t opt[16] = {0};
+    rk::Buffer ws[rk::WS_COUNT];
+    int prepared_fn = 0;
+    int queue_owner = 0;  // which pair function's plan the device queue holds
+    rk::NccState ncc;
+    rk::OvlState ovl;
+    rk::SpState sp;
+    rocket_stats stats = {};
+    int64_t ledger_items = 0;
+    hipEvent_t ev_begin = nullptr, ev_end = nullptr;  // main-kernel timing (ROCKET_OPT_TIMING)
+    bool ev_pending = false;
+    std::string last_error;
+    // host staging for queue uploads (kept to avoid re-allocation)
+    std::vector<int4> h_items;
+    std::vector<int> h_seg;
+};
+
+namespace rk {
+
+rocket_status fail(rocket_ctx *ctx, rocket_status st, const std::string &msg);
+rocket_status hip_fail(rocket_ctx *ctx, hipError_t e, const char *what, const char *file, int line);
+rocket_status ws_get(rocket_ctx *ctx, Slot slot, size_t bytes, void **out);
+int64_t ws_total(const rocket_ctx *ctx);
+rocket_status upload_queue(rocket_ctx *ctx, hipStream_t s, QueueArgs *qa);
+rocket_status reset_queue(rocket_ctx *ctx, hipStream_t s, const QueueArgs &qa);
+int auto_grid(rocket_ctx *ctx, const void *kernel, int block, size_t dyn_lds, int64_t items);
+// Bracket the main kernel launch with events when ROCKET_OPT_TIMING is set.
+rocket_status timing_begin(rocket_ctx *ctx, hipStream_t s);
+rocket_status timing_end(rocket_ctx *ctx, hipStream_t s);
+
+// Planner (plan.cpp)
+void plan_leaves(int64_t n, int64_t T, std::vector<int2> &out);
+// Split `tiles` x `chunks` work items into per-XCD segments in chunk-major order.
+void plan_chunked(const std::vector<int2> &tiles, int nchunks, int nseg, std::vector<int4> &items,
+                  std::vector<int> &seg);
+// Cost-ordered (largest first) items dealt round-robin to segments.
+void plan_lpt(const std::vector<int4> &items_in, const std::vector<double> &cost, int nseg,
+              std::vector<int4> &items, std::vector<int> &seg);
+void shuffle_items(std::vector<int4> &items, std::vector<int> &seg, uint64_t seed);
+void single_segment(std::vector<int> &seg, int64_t nitems);
+
+// Per pair-function modules.
+rocket_status ncc_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, int scheme, hipStream_t s);
+rocket_status ncc_compare(rocket_ctx *ctx, float *out, hipStream_t s);
+rocket_status ovl_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, hipStream_t s);
+rocket_status ovl_compare(rocket_ctx *ctx, float *out, const float *centroids, const float *params, float *grad,
+                          hipStream_t s);
+rocket_status ovl_autotune(rocket_ctx *ctx, hipStream_t s);
+rocket_status sp_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, hipStream_t s);
+rocket_status sp_compare(rocket_ctx *ctx, float *out, uint32_t *counts, hipStream_t s);
+
+}  // namespace rk
+
+#define RK_HIP(expr)                                                                  \
+    do {                                                                              \
+        hipError_t rk_e_ = (expr);                                                    \
+        if (rk_e_ != hipSuccess) return rk::hip_fail(ctx, rk_e_, #expr, __FILE__, __LINE__); \
+    } while (0)
+
+#define RK_TRY(expr)                         \
+    do {                                     \
+        rocket_status rk_s_ = (expr);        \
+        if (rk_s_ != ROCKET_OK) return rk_s_; \
+    } while (0)

@@ -1,0 +1,564 @@
+// Normalised cross-correlation of dense items (Section V-A compare kernel) on gfx950.
+//
+// rho_ij = <a_i - mu_i, a_j - mu_j> / (s_i s_j), s = centred L2 norm.  Stages:
+//   k_ncc_stats   per item: mean and centred norm, FP64 (one pass with a shift)
+//   k_ncc_split   per item: centred values in FP32, split into bf16 planes (or kept FP32),
+//                 written K16-major: element (r, k) at ((k/16) * n_pad + r) * 16 + k%16, so the
+//                 16-deep K slice of any row block is one contiguous chunk
+//   k_ncc_gram    persistent: pops (tile, K chunk) items, stages both row blocks of every
+//                 16-deep K slice in LDS (double buffered) and accumulates the tile's Gram
+//                 block with MFMA, FP32 accumulation; writes one partial tile per item
+//   k_ncc_finish  per output pair: fixed-order sum of the K-chunk partials, rescale by
+//                 1/(s_i s_j), scatter to the packed upper triangle
+#include <cmath>
+
+#include "common.hpp"
+#include "queue.hpp"
+
+namespace rk {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int SCH_FP32 = ROCKET_NCC_FP32, SCH_X3 = ROCKET_NCC_BF16X3, SCH_X6 = ROCKET_NCC_BF16X6;
+
+template <int SCH>
+struct Scheme;
+template <>
+struct Scheme<SCH_FP32> {
+    static constexpr int NC = 1, ES = 4;
+};
+template <>
+struct Scheme<SCH_X3> {
+    static constexpr int NC = 2, ES = 2;
+};
+template <>
+struct Scheme<SCH_X6> {
+    static constexpr int NC = 3, ES = 2;
+};
+
+__device__ __forceinline__ uint32_t bf16_rne(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+__device__ __forceinline__ float bf16_val(uint32_t h) { return __uint_as_float(h << 16); }
+
+// ------------------------------------------------------------------------------------------
+// Per-item statistics.  Sums of (x - K) and (x - K)^2 in FP64 with K = the item's first
+// value; mean = K + S1/d, centred sum of squares = S2 - S1^2/d.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_ncc_stats(const float *__restrict__ X, int64_t ld, int64_t d,
+                                                   double *__restrict__ mu, float *__restrict__ inv_s)
+{
+    const int64_t row = blockIdx.x;
+    const float *a = X + row * ld;
+    const double K = (double)a[0];
+    double s1a = 0, s2a = 0, s1b = 0, s2b = 0;
+    const bool vec = ((ld & 3) == 0) && ((((uintptr_t)X) & 15) == 0);
+    int64_t k_tail = 0;
+    if (vec) {
+        const float4 *a4 = (const float4 *)a;
+        const int64_t d4 = d >> 2;
+        int64_t k = threadIdx.x;
+        for (; k + 256 < d4; k += 512) {
+            const float4 u = a4[k], v = a4[k + 256];
+            double t;
+            t = (double)u.x - K; s1a += t; s2a += t * t;
+            t = (double)u.y - K; s1a += t; s2a += t * t;
+            t = (double)u.z - K; s1a += t; s2a += t * t;
+            t = (double)u.w - K; s1a += t; s2a += t * t;
+            t = (double)v.x - K; s1b += t; s2b += t * t;
+            t = (double)v.y - K; s1b += t; s2b += t * t;
+            t = (double)v.z - K; s1b += t; s2b += t * t;
+            t = (double)v.w - K; s1b += t; s2b += t * t;
+        }
+        for (; k < d4; k += 256) {
+            const float4 u = a4[k];
+            double t;
+            t = (double)u.x - K; s1a += t; s2a += t * t;
+            t = (double)u.y - K; s1a += t; s2a += t * t;
+            t = (double)u.z - K; s1a += t; s2a += t * t;
+            t = (double)u.w - K; s1a += t; s2a += t * t;
+        }
+        k_tail = d4 << 2;
+    }
+    for (int64_t k = k_tail + threadIdx.x; k < d; k += 256) {
+        const double t = (double)a[k] - K;
+        s1a += t;
+        s2a += t * t;
+    }
+    double s1 = s1a + s1b, s2 = s2a + s2b;
+    for (int o = 32; o > 0; o >>= 1) {
+        s1 += __shfl_xor(s1, o);
+        s2 += __shfl_xor(s2, o);
+    }
+    __shared__ double r1[4], r2[4];
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        r1[w] = s1;
+        r2[w] = s2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s1 = (r1[0] + r1[1]) + (r1[2] + r1[3]);
+        s2 = (r2[0] + r2[1]) + (r2[2] + r2[3]);
+        const double dd = (double)d;
+        double ss = s2 - s1 * s1 / dd;
+        if (ss < 0) ss = 0;
+        mu[row] = K + s1 / dd;
+        inv_s[row] = ss > 0 ? (float)(1.0 / sqrt(ss)) : __builtin_nanf("");
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Centre and split.  grid.x covers the K dimension in groups of 4, grid.y strides rows.
+// Rows >= n and columns >= d are written as zeros.
+// ------------------------------------------------------------------------------------------
+template <int SCH>
+__global__ __launch_bounds__(256) void k_ncc_split(const float *__restrict__ X, int64_t ld, int64_t d, int64_t n,
+                                                   const double *__restrict__ mu, int64_t n_pad, int64_t d_pad,
+                                                   char *__restrict__ planes, int64_t plane_bytes)
+{
+    const int64_t k0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+    if (k0 >= d_pad) return;
+    const bool vec = ((ld & 3) == 0) && ((((uintptr_t)X) & 15) == 0);
+    for (int64_t r = blockIdx.y; r < n_pad; r += gridDim.y) {
+        float x[4] = {0.f, 0.f, 0.f, 0.f};
+        if (r < n) {
+            const double m = mu[r];
+            const float *a = X + r * ld;
+            if (vec && k0 + 3 < d) {
+                const float4 v = *(const float4 *)(a + k0);
+                x[0] = (float)((double)v.x - m);
+                x[1] = (float)((double)v.y - m);
+                x[2] = (float)((double)v.z - m);
+                x[3] = (float)((double)v.w - m);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (k0 + e < d) x[e] = (float)((double)a[k0 + e] - m);
+            }
+        }
+        const int64_t dst = ((k0 >> 4) * n_pad + r) * 16 + (k0 & 15);
+        if constexpr (SCH == SCH_FP32) {
+            *(float4 *)((float *)planes + dst) = make_float4(x[0], x[1], x[2], x[3]);
+        } else {
+            uint32_t h[4], m[4], l[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                h[e] = bf16_rne(x[e]);
+                const float r1 = x[e] - bf16_val(h[e]);
+                m[e] = bf16_rne(r1);
+                const float r2 = r1 - bf16_val(m[e]);
+                l[e] = bf16_rne(r2);
+            }
+            uint16_t *p0 = (uint16_t *)planes + dst;
+            *(uint2 *)p0 = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+            uint16_t *p1 = (uint16_t *)(planes + plane_bytes) + dst;
+            *(uint2 *)p1 = make_uint2(m[0] | (m[1] << 16), m[2] | (m[3] << 16));
+            if constexpr (SCH == SCH_X6) {
+                uint16_t *p2 = (uint16_t *)(planes + 2 * plane_bytes) + dst;
+                *(uint2 *)p2 = make_uint2(l[0] | (l[1] << 16), l[2] | (l[3] << 16));
+            }
+        }
+    }
+}
+
+// LDS segment swizzles (16-byte segments within a row of one K slice), chosen so that
+// the 16-byte fragment reads of 16 consecutive lanes hit distinct banks.
+template <int SEGS>
+__device__ __forceinline__ int swz(int row)
+{
+    if constexpr (SEGS == 2)
+        return ((row >> 2) ^ (row >> 3)) & 1;
+    else
+        return ((row >> 1) ^ (row >> 3)) & 3;
+}
+
+// ------------------------------------------------------------------------------------------
+// Persistent Gram kernel.  256 threads = 4 waves in a 2x2 arrangement; each wave owns a
+// (BM/2) x (BM/2) sub-tile made of 32x32 MFMA blocks.  One stage = a 16-deep K slice of
+// all NC operand planes for both row blocks (A = block bi, B = block bj), copied HBM -> LDS
+// with global_load_lds (no register staging), double buffered.
+//   bf16:  v_mfma_f32_32x32x16_bf16, lane l holds row l%32, k = 8*(l/32) .. +8
+//   fp32:  v_mfma_f32_32x32x2_f32 x 8 per stage; step s feeds k = s (lanes 0-31) and
+//          k = 8 + s (lanes 32-63), the same permutation for both operands
+// Output block layout (both): acc[r] of lane l is row 8*(r/4) + 4*(l/32) + r%4, col l%32.
+// ------------------------------------------------------------------------------------------
+typedef __attribute__((address_space(3))) void *lds_ptr_t;
+typedef __attribute__((address_space(1))) void *gbl_ptr_t;
+
+template <int BM, int SCH>
+__global__ __launch_bounds__(256, 1) void k_ncc_gram(const char *__restrict__ planes, int64_t plane_bytes,
+                                                     int64_t n_pad, int kt_per_chunk, int nkt, int nchunks,
+                                                     QueueArgs q, float *__restrict__ partial)
+{
+    constexpr int NC = Scheme<SCH>::NC, ES = Scheme<SCH>::ES;
+    constexpr int ROWB = 16 * ES;
+    constexpr int SEGS = ROWB / 16;
+    constexpr int TILEB = BM * ROWB;
+    constexpr int STAGEB = 2 * NC * TILEB;
+    constexpr int BLOCKS = STAGEB / 1024;      // 1 KiB wave-copies per stage
+    constexpr int BPW = (BLOCKS + 3) / 4;      // per wave
+    constexpr int ROWS_PER_BLOCK = 1024 / ROWB;
+    constexpr int WM = BM / 2;
+    constexpr int MB = WM / 32;
+    static_assert(TILEB % 1024 == 0, "tile side must be a whole number of 1 KiB blocks");
+
+    __shared__ __align__(1024) char lds[2 * STAGEB];
+    __shared__ int s_item;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    // this lane's slot inside every 1 KiB block: row and (swizzled) 16-byte segment
+    const int lrow = lane / SEGS, pseg = lane % SEGS;
+
+    for (;;) {
+        const int it = queue_pop_wg(q, &s_item);
+        if (it < 0) break;
+        const int4 w = q.items[it];
+        const int bi = w.x, bj = w.y, kc = w.z, tile = w.w;
+        const int kt0 = kc * kt_per_chunk;
+        const int kt1 = min(kt0 + kt_per_chunk, nkt);
+
+        f32x16 acc[MB][MB];
+#pragma unroll
+        for (int m = 0; m < MB; ++m)
+#pragma unroll
+            for (int n = 0; n < MB; ++n)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[m][n][r] = 0.f;
+
+        const int64_t rowA = (int64_t)bi * BM, rowB = (int64_t)bj * BM;
+
+        // issue the HBM -> LDS copies of K slice kt into buffer buf
+        auto issue = [&](int kt, int buf) {
+#pragma unroll
+            for (int c = 0; c < BPW; ++c) {
+                const int b = wave + 4 * c;
+                if (BLOCKS % 4 == 0 || b < BLOCKS) {
+                    const int cs = b / (TILEB / 1024);            // comp * 2 + side
+                    const int rb = (b % (TILEB / 1024)) * ROWS_PER_BLOCK;
+                    const int row = rb + lrow;
+                    const int seg = pseg ^ swz<SEGS>(row);
+                    const int comp = cs >> 1, side = cs & 1;
+                    const char *src = planes + comp * plane_bytes +
+                                      (((int64_t)kt * n_pad + (side ? rowB : rowA) + row) * ROWB) + seg * 16;
+                    __builtin_amdgcn_global_load_lds((gbl_ptr_t)src, (lds_ptr_t)(lds + buf * STAGEB + b * 1024), 16,
+                                                     0, 0);
+                }
+            }
+        };
+
+        issue(kt0, 0);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        for (int kt = kt0; kt < kt1; ++kt) {
+            const int buf = (kt - kt0) & 1;
+            const char *base = lds + buf * STAGEB;
+            const int h = lane >> 5;
+            if constexpr (SCH == SCH_FP32) {
+                float fa[MB][8], fb[MB][8];
+#pragma unroll
+                for (int m = 0; m < MB; ++m) {
+                    const int ra = wm * WM + m * 32 + (lane & 31);
+                    const int rb = wn * WM + m * 32 + (lane & 31);
+                    const char *pa = base + ra * ROWB;
+                    const char *pb = base + TILEB + rb * ROWB;
+                    const float4 a0 = *(const float4 *)(pa + (((2 * h) ^ swz<SEGS>(ra)) * 16));
+                    const float4 a1 = *(const float4 *)(pa + (((2 * h + 1) ^ swz<SEGS>(ra)) * 16));
+                    const float4 b0 = *(const float4 *)(pb + (((2 * h) ^ swz<SEGS>(rb)) * 16));
+                    const float4 b1 = *(const float4 *)(pb + (((2 * h + 1) ^ swz<SEGS>(rb)) * 16));
+                    fa[m][0] = a0.x; fa[m][1] = a0.y; fa[m][2] = a0.z; fa[m][3] = a0.w;
+                    fa[m][4] = a1.x; fa[m][5] = a1.y; fa[m][6] = a1.z; fa[m][7] = a1.w;
+                    fb[m][0] = b0.x; fb[m][1] = b0.y; fb[m][2] = b0.z; fb[m][3] = b0.w;
+                    fb[m][4] = b1.x; fb[m][5] = b1.y; fb[m][6] = b1.z; fb[m][7] = b1.w;
+                }
+                // fragments are in registers: the next slice may now stream into the other buffer
+                if (kt + 1 < kt1) issue(kt + 1, buf ^ 1);
+#pragma unroll
+                for (int s = 0; s < 8; ++s)
+#pragma unroll
+                    for (int m = 0; m < MB; ++m)
+#pragma unroll
+                        for (int n = 0; n < MB; ++n)
+                            acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[m][s], fb[n][s], acc[m][n], 0, 0, 0);
+            } else {
+                bf16x8 fa[NC][MB], fb[NC][MB];
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+#pragma unroll
+                    for (int m = 0; m < MB; ++m) {
+                        const int ra = wm * WM + m * 32 + (lane & 31);
+                        const int rb = wn * WM + m * 32 + (lane & 31);
+                        fa[c][m] = *(const bf16x8 *)(base + (2 * c) * TILEB + ra * ROWB + ((h ^ swz<SEGS>(ra)) * 16));
+                        fb[c][m] =
+                            *(const bf16x8 *)(base + (2 * c + 1) * TILEB + rb * ROWB + ((h ^ swz<SEGS>(rb)) * 16));
+                    }
+                if (kt + 1 < kt1) issue(kt + 1, buf ^ 1);
+                // products grouped by the A component: h*(h, m[, l]), m*(h[, m]), [l*h]
+#pragma unroll
+                for (int ca = 0; ca < NC; ++ca) {
+                    constexpr int NCB0 = SCH == SCH_X6 ? 3 : 2;
+                    const int ncb = SCH == SCH_X6 ? NC - ca : (ca == 0 ? 2 : 1);
+#pragma unroll
+                    for (int cb = 0; cb < NCB0; ++cb) {
+                        if (cb < ncb) {
+#pragma unroll
+                            for (int m = 0; m < MB; ++m)
+#pragma unroll
+                                for (int n = 0; n < MB; ++n)
+                                    acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[ca][m], fb[cb][n],
+                                                                                        acc[m][n], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+            // keep every MFMA of this slice ahead of the wait: the copy of the next slice
+            // then overlaps the whole slice's matrix work
+            __builtin_amdgcn_sched_barrier(0);
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+        }
+
+        // partial tile in MFMA-native order: float4 chunk ((m*MB + n)*4 + q)*256 + tid holds
+        // acc[m][n][4q .. 4q+3] of this thread (four consecutive rows, one column)
+        float4 *P = (float4 *)(partial + ((int64_t)tile * nchunks + kc) * (int64_t)BM * BM) + tid;
+#pragma unroll
+        for (int m = 0; m < MB; ++m)
+#pragma unroll
+            for (int n = 0; n < MB; ++n)
+#pragma unroll
+                for (int qq = 0; qq < 4; ++qq)
+                    P[((m * MB + n) * 4 + qq) * 256] =
+                        make_float4(acc[m][n][4 * qq], acc[m][n][4 * qq + 1], acc[m][n][4 * qq + 2], acc[m][n][4 * qq + 3]);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Epilogue: out[idx(i,j)] = (sum_c partial_c[i][j]) * inv_s[i] * inv_s[j], chunks summed in
+// ascending order.  One thread per float4 of the MFMA-native partial layout (four rows of
+// one column), so partial reads are 16-byte coalesced and output writes are 128-byte runs.
+// ------------------------------------------------------------------------------------------
+template <int BM>
+__global__ __launch_bounds__(256) void k_ncc_finish(const float *__restrict__ partial, const int2 *__restrict__ tiles,
+                                                    int nchunks, int64_t n, const float *__restrict__ inv_s,
+                                                    float *__restrict__ out)
+{
+    constexpr int BPT = BM * BM / 4 / 256;  // workgroups per tile
+    constexpr int WM = BM / 2, MB = WM / 32;
+    const int64_t tile = blockIdx.x / BPT;
+    const int t = (int)(blockIdx.x % BPT) * 256 + threadIdx.x;  // float4 index in the tile
+    const int tid = t & 255, lane = tid & 63, wave = tid >> 6;
+    const int qq = (t >> 8) & 3, mn = t >> 10;
+    const int m = mn / MB, nn = mn % MB;
+    const int row0 = (wave >> 1) * WM + m * 32 + 8 * qq + 4 * (lane >> 5);
+    const int col = (wave & 1) * WM + nn * 32 + (lane & 31);
+    const int2 tl = tiles[tile];
+    const int64_t j = (int64_t)tl.y * BM + col;
+    const int64_t i0 = (int64_t)tl.x * BM + row0;
+    if (j >= n || i0 >= j) return;
+    const float4 *p = (const float4 *)(partial + tile * nchunks * (int64_t)BM * BM) + t;
+    // fixed order: groups of 16 consecutive chunks, then the group sums
+    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int k0 = 0; k0 < nchunks; k0 += 16) {
+        float4 g = p[(int64_t)k0 * (BM * BM / 4)];
+        const int k1 = min(nchunks, k0 + 16);
+        for (int k = k0 + 1; k < k1; ++k) {
+            const float4 v = p[(int64_t)k * (BM * BM / 4)];
+            g.x += v.x;
+            g.y += v.y;
+            g.z += v.z;
+            g.w += v.w;
+        }
+        s.x += g.x;
+        s.y += g.y;
+        s.z += g.z;
+        s.w += g.w;
+    }
+    const float vals[4] = {s.x, s.y, s.z, s.w};
+    const float sj = inv_s[j];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t i = i0 + e;
+        if (i < j) out[i * n - i * (i + 1) / 2 + (j - i - 1)] = vals[e] * inv_s[i] * sj;
+    }
+}
+
+template <int BM, int SCH>
+const void *gram_ptr()
+{
+    return (const void *)&k_ncc_gram<BM, SCH>;
+}
+
+template <int SCH>
+const void *gram_ptr_bm(int bm)
+{
+    return bm == 64 ? gram_ptr<64, SCH>() : bm == 128 ? gram_ptr<128, SCH>() : gram_ptr<256, SCH>();
+}
+
+const void *gram_kernel(int bm, int sch)
+{
+    return sch == SCH_FP32 ? gram_ptr_bm<SCH_FP32>(bm) : sch == SCH_X3 ? gram_ptr_bm<SCH_X3>(bm)
+                                                                      : gram_ptr_bm<SCH_X6>(bm);
+}
+
+int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+int nc_of(int sch) { return sch == SCH_X6 ? 3 : sch == SCH_X3 ? 2 : 1; }
+int es_of(int sch) { return sch == SCH_FP32 ? 4 : 2; }
+
+}  // namespace
+
+rocket_status ncc_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, int scheme, hipStream_t s)
+{
+    if (n > 0 && !it->dense) return fail(ctx, ROCKET_E_INVALID, "dense is NULL");
+    if (it->dim < 1) return fail(ctx, ROCKET_E_INVALID, "dim < 1");
+    if (it->ld < it->dim) return fail(ctx, ROCKET_E_INVALID, "ld < dim");
+    if (n > (int64_t)1 << 24) return fail(ctx, ROCKET_E_INVALID, "n too large");
+    NccState &st = ctx->ncc;
+    st.n = n;
+    st.dim = it->dim;
+    st.ld = it->ld;
+    st.src = it->dense;
+    st.scheme = scheme;
+    int bm = (int)ctx->opt[ROCKET_OPT_NCC_TILE];
+    if (!bm) bm = n >= 1536 ? 256 : n >= 384 ? 128 : 64;
+    st.tile = bm;
+    st.n_pad = round_up(std::max<int64_t>(n, 1), bm);
+    st.d_pad = round_up(it->dim, 16);
+    st.nkt = (int)(st.d_pad / 16);
+
+    NccState &pc = st;
+    if (ctx->queue_owner != QOWN_NCC) pc.pc_nchunks = -1;
+    if (pc.pc_n != n || pc.pc_tile != bm) {
+        plan_leaves(n, bm, pc.h_tiles);
+        pc.pc_n = n;
+        pc.pc_tile = bm;
+        pc.pc_nchunks = -1;
+    }
+    st.tiles = (int64_t)pc.h_tiles.size();
+    int64_t kc = ctx->opt[ROCKET_OPT_NCC_KCHUNK];
+    if (!kc) {
+        const int64_t want_chunks = std::max<int64_t>(1, (2048 + st.tiles - 1) / std::max<int64_t>(st.tiles, 1));
+        kc = round_up((st.d_pad + want_chunks - 1) / want_chunks, 16);
+        // FP32 accumulation error of a chunk grows like sqrt(chunk length): 2048-element
+        // chunks keep it well inside 1e-5 of the dot product's error scale at 2^20 elements
+        kc = std::max<int64_t>(256, std::min<int64_t>(kc, 2048));
+    }
+    kc = std::min<int64_t>(kc, st.d_pad);
+    st.kt_per_chunk = (int)(kc / 16);
+    st.nchunks = (int)((st.nkt + st.kt_per_chunk - 1) / st.kt_per_chunk);
+    st.items = st.tiles * st.nchunks;
+    ctx->stats.tiles = st.tiles;
+    ctx->stats.work_items = st.items;
+    ctx->stats.tile = bm;
+    ctx->stats.kchunk = kc;
+    ctx->stats.variant = scheme;
+    if (st.items > INT32_MAX / 2) return fail(ctx, ROCKET_E_INVALID, "too many work items");
+
+    const int64_t order = ctx->opt[ROCKET_OPT_QUEUE_ORDER], seed = ctx->opt[ROCKET_OPT_SEED],
+                  ledger = ctx->opt[ROCKET_OPT_LEDGER];
+    if (st.tiles > 0 &&
+        (pc.pc_nchunks != st.nchunks || pc.pc_order != order || pc.pc_seed != seed || pc.pc_ledger != ledger)) {
+        plan_chunked(pc.h_tiles, st.nchunks, MAX_SEG, ctx->h_items, ctx->h_seg);
+        if (order == 1) shuffle_items(ctx->h_items, ctx->h_seg, (uint64_t)seed);
+        if (order == 2) single_segment(ctx->h_seg, (int64_t)ctx->h_items.size());
+        RK_TRY(upload_queue(ctx, s, &pc.qa));
+        void *tl = nullptr;
+        RK_TRY(ws_get(ctx, WS_NCC_TILES, sizeof(int2) * pc.h_tiles.size(), &tl));
+        RK_HIP(hipMemcpyAsync(tl, pc.h_tiles.data(), sizeof(int2) * pc.h_tiles.size(), hipMemcpyHostToDevice, s));
+        RK_HIP(hipStreamSynchronize(s));
+        ctx->queue_owner = QOWN_NCC;
+        pc.pc_nchunks = st.nchunks;
+        pc.pc_order = order;
+        pc.pc_seed = seed;
+        pc.pc_ledger = ledger;
+    }
+    if (n == 0) return ROCKET_OK;
+
+    void *stats = nullptr, *planes = nullptr;
+    RK_TRY(ws_get(ctx, WS_NCC_STATS, (size_t)n * 12 + 64, &stats));
+    const int64_t plane_bytes = st.n_pad * st.d_pad * es_of(scheme);
+    RK_TRY(ws_get(ctx, WS_NCC_PLANES, (size_t)(plane_bytes * nc_of(scheme)), &planes));
+    double *mu = (double *)stats;
+    float *inv_s = (float *)((char *)stats + (((size_t)n * 8 + 255) & ~(size_t)255));
+    hipLaunchKernelGGL(k_ncc_stats, dim3((unsigned)n), dim3(256), 0, s, it->dense, it->ld, it->dim, mu, inv_s);
+    RK_HIP(hipGetLastError());
+    const dim3 g((unsigned)((st.d_pad / 4 + 255) / 256), (unsigned)std::min<int64_t>(st.n_pad, 65535));
+    if (scheme == SCH_FP32)
+        hipLaunchKernelGGL(k_ncc_split<SCH_FP32>, g, dim3(256), 0, s, it->dense, it->ld, it->dim, n, mu, st.n_pad,
+                           st.d_pad, (char *)planes, plane_bytes);
+    else if (scheme == SCH_X3)
+        hipLaunchKernelGGL(k_ncc_split<SCH_X3>, g, dim3(256), 0, s, it->dense, it->ld, it->dim, n, mu, st.n_pad,
+                           st.d_pad, (char *)planes, plane_bytes);
+    else
+        hipLaunchKernelGGL(k_ncc_split<SCH_X6>, g, dim3(256), 0, s, it->dense, it->ld, it->dim, n, mu, st.n_pad,
+                           st.d_pad, (char *)planes, plane_bytes);
+    RK_HIP(hipGetLastError());
+    return ROCKET_OK;
+}
+
+template <int BM, int SCH>
+static void launch_gram(int grid, hipStream_t s, const char *planes, int64_t pb, const NccState &st,
+                        const QueueArgs &qa, float *partial)
+{
+    hipLaunchKernelGGL((k_ncc_gram<BM, SCH>), dim3(grid), dim3(256), 0, s, planes, pb, st.n_pad, st.kt_per_chunk,
+                       st.nkt, st.nchunks, qa, partial);
+}
+
+template <int SCH>
+static void launch_gram_bm(int grid, hipStream_t s, const char *planes, int64_t pb, const NccState &st,
+                           const QueueArgs &qa, float *partial)
+{
+    if (st.tile == 64)
+        launch_gram<64, SCH>(grid, s, planes, pb, st, qa, partial);
+    else if (st.tile == 128)
+        launch_gram<128, SCH>(grid, s, planes, pb, st, qa, partial);
+    else
+        launch_gram<256, SCH>(grid, s, planes, pb, st, qa, partial);
+}
+
+rocket_status ncc_compare(rocket_ctx *ctx, float *out, hipStream_t s)
+{
+    const NccState &st = ctx->ncc;
+    if (st.n < 2 || st.tiles == 0) return ROCKET_OK;
+    if (ctx->queue_owner != QOWN_NCC) return fail(ctx, ROCKET_E_STATE, "queue was replanned by another prepare");
+    const NccState &pc = st;
+    const int bm = st.tile;
+    void *partial = nullptr;
+    RK_TRY(ws_get(ctx, WS_NCC_PARTIAL, (size_t)(st.items * bm * bm * 4), &partial));
+    RK_TRY(reset_queue(ctx, s, pc.qa));
+    const int grid = auto_grid(ctx, gram_kernel(bm, st.scheme), 256, 0, st.items);
+    ctx->stats.grid = grid;
+    const char *planes = (const char *)ctx->ws[WS_NCC_PLANES].ptr;
+    const int64_t pb = st.n_pad * st.d_pad * es_of(st.scheme);
+    RK_TRY(timing_begin(ctx, s));
+    if (st.scheme == SCH_FP32)
+        launch_gram_bm<SCH_FP32>(grid, s, planes, pb, st, pc.qa, (float *)partial);
+    else if (st.scheme == SCH_X3)
+        launch_gram_bm<SCH_X3>(grid, s, planes, pb, st, pc.qa, (float *)partial);
+    else
+        launch_gram_bm<SCH_X6>(grid, s, planes, pb, st, pc.qa, (float *)partial);
+    RK_HIP(hipGetLastError());
+    RK_TRY(timing_end(ctx, s));
+    const float *inv_s = (const float *)((char *)ctx->ws[WS_NCC_STATS].ptr + (((size_t)st.n * 8 + 255) & ~(size_t)255));
+    const int2 *tiles = (const int2 *)ctx->ws[WS_NCC_TILES].ptr;
+    const int64_t blocks = st.tiles * (int64_t)bm * bm / 1024;
+    if (bm == 64)
+        hipLaunchKernelGGL(k_ncc_finish<64>, dim3((unsigned)blocks), dim3(256), 0, s, (const float *)partial, tiles,
+                           st.nchunks, st.n, inv_s, out);
+    else if (bm == 128)
+        hipLaunchKernelGGL(k_ncc_finish<128>, dim3((unsigned)blocks), dim3(256), 0, s, (const float *)partial, tiles,
+                           st.nchunks, st.n, inv_s, out);
+    else
+        hipLaunchKernelGGL(k_ncc_finish<256>, dim3((unsigned)blocks), dim3(256), 0, s, (const float *)partial, tiles,
+                           st.nchunks, st.n, inv_s, out);
+    RK_HIP(hipGetLastError());
+    return ROCKET_OK;
+}
+
+}  // namespace rk

@@ -1,0 +1,366 @@
+// C ABI entry points, context and workspace management, queue upload.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+
+#include "common.hpp"
+
+namespace {
+
+__global__ void k_fill_i32(int *p, int64_t n, int v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+rocket_ctx *g_default[64] = {nullptr};
+std::mutex g_default_mu;
+std::string g_null_error;
+
+bool valid_fn(int fn) { return fn >= ROCKET_NCC_FP32 && fn <= ROCKET_SPARSE_COSINE; }
+
+}  // namespace
+
+namespace rk {
+
+rocket_status fail(rocket_ctx *ctx, rocket_status st, const std::string &msg)
+{
+    (ctx ? ctx->last_error : g_null_error) = std::string(rocket_status_str(st)) + ": " + msg;
+    return st;
+}
+
+rocket_status hip_fail(rocket_ctx *ctx, hipError_t e, const char *what, const char *file, int line)
+{
+    char buf[512];
+    snprintf(buf, sizeof buf, "%s failed with %s (%s) at %s:%d", what, hipGetErrorName(e), hipGetErrorString(e), file,
+             line);
+    return fail(ctx, e == hipErrorOutOfMemory ? ROCKET_E_OOM : ROCKET_E_HIP, buf);
+}
+
+int64_t ws_total(const rocket_ctx *ctx)
+{
+    int64_t t = 0;
+    for (int k = 0; k < WS_COUNT; ++k) t += (int64_t)ctx->ws[k].bytes;
+    return t;
+}
+
+rocket_status ws_get(rocket_ctx *ctx, Slot slot, size_t bytes, void **out)
+{
+    Buffer &b = ctx->ws[slot];
+    if (bytes == 0) bytes = 256;
+    if (b.bytes < bytes) {
+        const size_t want = (bytes + (2u << 20) - 1) & ~(size_t)((2u << 20) - 1);
+        const int64_t cap = ctx->opt[ROCKET_OPT_WORKSPACE_CAP];
+        if (cap > 0 && ws_total(ctx) - (int64_t)b.bytes + (int64_t)want > cap)
+            return fail(ctx, ROCKET_E_OOM, "workspace cap exceeded");
+        if (b.ptr) {
+            RK_HIP(hipFree(b.ptr));
+            b.ptr = nullptr;
+            b.bytes = 0;
+        }
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, want);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(ctx, ROCKET_E_OOM, "hipMalloc of workspace failed");
+        }
+        b.ptr = p;
+        b.bytes = want;
+    }
+    *out = b.ptr;
+    return ROCKET_OK;
+}
+
+rocket_status upload_queue(rocket_ctx *ctx, hipStream_t s, QueueArgs *qa)
+{
+    const int64_t nitems = (int64_t)ctx->h_items.size();
+    const int nseg = (int)ctx->h_seg.size() - 1;
+    void *items = nullptr, *heads = nullptr, *seg = nullptr;
+    RK_TRY(ws_get(ctx, WS_QUEUE_ITEMS, sizeof(int4) * (size_t)std::max<int64_t>(nitems, 1), &items));
+    RK_TRY(ws_get(ctx, WS_QUEUE_HEADS, sizeof(int) * HEAD_STRIDE * MAX_SEG, &heads));
+    RK_TRY(ws_get(ctx, WS_QUEUE_SEGS, sizeof(int) * (MAX_SEG + 1), &seg));
+    if (nitems) RK_HIP(hipMemcpyAsync(items, ctx->h_items.data(), sizeof(int4) * nitems, hipMemcpyHostToDevice, s));
+    RK_HIP(hipMemcpyAsync(seg, ctx->h_seg.data(), sizeof(int) * (nseg + 1), hipMemcpyHostToDevice, s));
+    RK_HIP(hipStreamSynchronize(s));  // host staging vectors may be reused right after
+    qa->items = (const int4 *)items;
+    qa->heads = (int *)heads;
+    qa->seg = (const int *)seg;
+    qa->nseg = nseg;
+    qa->ledger = nullptr;
+    if (ctx->opt[ROCKET_OPT_LEDGER]) {
+        void *led = nullptr;
+        RK_TRY(ws_get(ctx, WS_LEDGER, sizeof(int) * (size_t)std::max<int64_t>(nitems, 1), &led));
+        qa->ledger = (int *)led;
+    }
+    ctx->ledger_items = nitems;
+    return ROCKET_OK;
+}
+
+rocket_status reset_queue(rocket_ctx *ctx, hipStream_t s, const QueueArgs &qa)
+{
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, s, qa.heads, (int64_t)HEAD_STRIDE * MAX_SEG, 0);
+    RK_HIP(hipGetLastError());
+    if (qa.ledger) {
+        const int64_t n = std::max<int64_t>(ctx->ledger_items, 1);
+        hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)), dim3(256), 0, s,
+                           qa.ledger, n, 0);
+        RK_HIP(hipGetLastError());
+    }
+    return ROCKET_OK;
+}
+
+rocket_status timing_begin(rocket_ctx *ctx, hipStream_t s)
+{
+    if (!ctx->opt[ROCKET_OPT_TIMING]) return ROCKET_OK;
+    if (!ctx->ev_begin) {
+        RK_HIP(hipEventCreate(&ctx->ev_begin));
+        RK_HIP(hipEventCreate(&ctx->ev_end));
+    }
+    RK_HIP(hipEventRecord(ctx->ev_begin, s));
+    return ROCKET_OK;
+}
+
+rocket_status timing_end(rocket_ctx *ctx, hipStream_t s)
+{
+    if (!ctx->opt[ROCKET_OPT_TIMING]) return ROCKET_OK;
+    RK_HIP(hipEventRecord(ctx->ev_end, s));
+    ctx->ev_pending = true;
+    return ROCKET_OK;
+}
+
+int auto_grid(rocket_ctx *ctx, const void *kernel, int block, size_t dyn_lds, int64_t items)
+{
+    int per_cu = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, dyn_lds) != hipSuccess || per_cu < 1) {
+        (void)hipGetLastError();
+        per_cu = 1;
+    }
+    int64_t g = ctx->opt[ROCKET_OPT_GRID] > 0 ? ctx->opt[ROCKET_OPT_GRID] : (int64_t)ctx->num_cu * per_cu;
+    if (g > items) g = std::max<int64_t>(items, 1);
+    return (int)g;
+}
+
+}  // namespace rk
+
+extern "C" {
+
+const char *rocket_status_str(rocket_status s)
+{
+    switch (s) {
+    case ROCKET_OK: return "ROCKET_OK";
+    case ROCKET_E_INVALID: return "ROCKET_E_INVALID";
+    case ROCKET_E_UNSUPPORTED: return "ROCKET_E_UNSUPPORTED";
+    case ROCKET_E_OOM: return "ROCKET_E_OOM";
+    case ROCKET_E_HIP: return "ROCKET_E_HIP";
+    case ROCKET_E_KEYRANGE: return "ROCKET_E_KEYRANGE";
+    case ROCKET_E_UNSORTED: return "ROCKET_E_UNSORTED";
+    case ROCKET_E_STATE: return "ROCKET_E_STATE";
+    }
+    return "ROCKET_E_UNKNOWN";
+}
+
+const char *rocket_last_error(const rocket_ctx *ctx) { return ctx ? ctx->last_error.c_str() : g_null_error.c_str(); }
+
+rocket_status rocket_create(rocket_ctx **out, int device)
+{
+    if (!out) return rk::fail(nullptr, ROCKET_E_INVALID, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess) return rk::hip_fail(nullptr, e, "hipGetDeviceCount", __FILE__, __LINE__);
+    if (device < 0 || device >= count) return rk::fail(nullptr, ROCKET_E_INVALID, "device out of range");
+    rocket_ctx *c = new rocket_ctx();
+    c->device = device;
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) {
+        delete c;
+        return rk::hip_fail(nullptr, e, "hipGetDeviceProperties", __FILE__, __LINE__);
+    }
+    c->num_cu = prop.multiProcessorCount;
+    *out = c;
+    return ROCKET_OK;
+}
+
+void rocket_destroy(rocket_ctx *ctx)
+{
+    if (!ctx) return;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (auto &b : ctx->ws)
+        if (b.ptr) (void)hipFree(b.ptr);
+    if (ctx->ev_begin) (void)hipEventDestroy(ctx->ev_begin);
+    if (ctx->ev_end) (void)hipEventDestroy(ctx->ev_end);
+    (void)hipSetDevice(prev);
+    delete ctx;
+}
+
+static rocket_status enter(rocket_ctx *ctx)
+{
+    if (!ctx) return rk::fail(nullptr, ROCKET_E_INVALID, "ctx is NULL");
+    int cur = -1;
+    RK_HIP(hipGetDevice(&cur));
+    if (cur != ctx->device) RK_HIP(hipSetDevice(ctx->device));
+    return ROCKET_OK;
+}
+
+rocket_status rocket_prepare(rocket_ctx *ctx, const rocket_items *items, int64_t n, rocket_pair_fn fn, void *stream)
+{
+    RK_TRY(enter(ctx));
+    if (!items) return rk::fail(ctx, ROCKET_E_INVALID, "items is NULL");
+    if (n < 0) return rk::fail(ctx, ROCKET_E_INVALID, "n < 0");
+    if (!valid_fn(fn)) return rk::fail(ctx, ROCKET_E_UNSUPPORTED, "unknown pair function");
+    hipStream_t s = (hipStream_t)stream;
+    ctx->prepared_fn = 0;
+    rocket_status st;
+    switch (fn) {
+    case ROCKET_NCC_FP32:
+    case ROCKET_NCC_BF16X3:
+    case ROCKET_NCC_BF16X6: st = rk::ncc_prepare(ctx, items, n, (int)fn, s); break;
+    case ROCKET_GAUSS_OVERLAP: st = rk::ovl_prepare(ctx, items, n, s); break;
+    case ROCKET_SPARSE_COSINE: st = rk::sp_prepare(ctx, items, n, s); break;
+    default: st = ROCKET_E_UNSUPPORTED;
+    }
+    if (st == ROCKET_OK) ctx->prepared_fn = (int)fn;
+    ctx->stats.n = n;
+    ctx->stats.pairs = n * (n - 1) / 2;
+    ctx->stats.workspace_bytes = rk::ws_total(ctx);
+    return st;
+}
+
+rocket_status rocket_compare(rocket_ctx *ctx, float *out, uint32_t *out_counts, void *stream)
+{
+    RK_TRY(enter(ctx));
+    hipStream_t s = (hipStream_t)stream;
+    const int fn = ctx->prepared_fn;
+    if (!fn) return rk::fail(ctx, ROCKET_E_STATE, "compare without a successful prepare");
+    if (!out && ctx->stats.pairs > 0) return rk::fail(ctx, ROCKET_E_INVALID, "out is NULL");
+    rocket_status st;
+    switch (fn) {
+    case ROCKET_NCC_FP32:
+    case ROCKET_NCC_BF16X3:
+    case ROCKET_NCC_BF16X6: st = rk::ncc_compare(ctx, out, s); break;
+    case ROCKET_GAUSS_OVERLAP: st = rk::ovl_compare(ctx, out, nullptr, nullptr, nullptr, s); break;
+    case ROCKET_SPARSE_COSINE: st = rk::sp_compare(ctx, out, out_counts, s); break;
+    default: st = ROCKET_E_STATE;
+    }
+    ctx->stats.workspace_bytes = rk::ws_total(ctx);
+    return st;
+}
+
+rocket_status rocket_allpairs_ex(rocket_ctx *ctx, const rocket_items *items, int64_t n, rocket_pair_fn fn, float *out,
+                                 uint32_t *out_counts, void *stream)
+{
+    RK_TRY(rocket_prepare(ctx, items, n, fn, stream));
+    return rocket_compare(ctx, out, out_counts, stream);
+}
+
+rocket_status rocket_allpairs(const rocket_items *items, int64_t n, rocket_pair_fn fn, float *out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return rk::hip_fail(nullptr, e, "hipGetDevice", __FILE__, __LINE__);
+    if (dev < 0 || dev >= 64) return rk::fail(nullptr, ROCKET_E_INVALID, "device index out of range");
+    rocket_ctx *ctx;
+    {
+        std::lock_guard<std::mutex> lk(g_default_mu);
+        if (!g_default[dev]) {
+            rocket_status st = rocket_create(&g_default[dev], dev);
+            if (st != ROCKET_OK) return st;
+        }
+        ctx = g_default[dev];
+    }
+    RK_TRY(rocket_allpairs_ex(ctx, items, n, fn, out, nullptr, nullptr));
+    RK_HIP(hipStreamSynchronize(nullptr));
+    return ROCKET_OK;
+}
+
+rocket_status rocket_overlap_cost_grad(rocket_ctx *ctx, const rocket_items *clouds, int64_t n, const float *centroids,
+                                       const float *params, float *out_cost, float *out_grad, void *stream)
+{
+    RK_TRY(enter(ctx));
+    if (!clouds) return rk::fail(ctx, ROCKET_E_INVALID, "clouds is NULL");
+    if (n < 0) return rk::fail(ctx, ROCKET_E_INVALID, "n < 0");
+    const int64_t P = n * (n - 1) / 2;
+    if (P > 0 && (!centroids || !params || !out_cost))
+        return rk::fail(ctx, ROCKET_E_INVALID, "centroids, params and out_cost are required");
+    hipStream_t s = (hipStream_t)stream;
+    const rk::OvlState &o = ctx->ovl;
+    const bool reuse = o.valid && o.n == n && o.offsets == clouds->offsets && o.xy == clouds->xy &&
+                       o.sigma == clouds->sigma;
+    if (!reuse) {
+        ctx->prepared_fn = 0;
+        RK_TRY(rk::ovl_prepare(ctx, clouds, n, s));
+        ctx->prepared_fn = ROCKET_GAUSS_OVERLAP;
+    }
+    ctx->stats.n = n;
+    ctx->stats.pairs = P;
+    RK_TRY(rk::ovl_compare(ctx, out_cost, centroids, params, out_grad, s));
+    ctx->stats.workspace_bytes = rk::ws_total(ctx);
+    return ROCKET_OK;
+}
+
+rocket_status rocket_set_option(rocket_ctx *ctx, rocket_option opt, int64_t value)
+{
+    if (!ctx) return rk::fail(nullptr, ROCKET_E_INVALID, "ctx is NULL");
+    if (opt < ROCKET_OPT_NCC_TILE || opt > ROCKET_OPT_TIMING) return rk::fail(ctx, ROCKET_E_UNSUPPORTED, "option");
+    if (value < 0) return rk::fail(ctx, ROCKET_E_INVALID, "negative option value");
+    if (opt == ROCKET_OPT_NCC_TILE && value != 0 && value != 64 && value != 128 && value != 256)
+        return rk::fail(ctx, ROCKET_E_INVALID, "NCC tile must be 0, 64, 128 or 256");
+    if (opt == ROCKET_OPT_NCC_KCHUNK && value % 16 != 0)
+        return rk::fail(ctx, ROCKET_E_INVALID, "NCC K chunk must be a multiple of 16");
+    if (opt == ROCKET_OPT_QUEUE_ORDER && value > 2) return rk::fail(ctx, ROCKET_E_INVALID, "queue order 0..2");
+    if (opt == ROCKET_OPT_OVL_VARIANT && value > 3) return rk::fail(ctx, ROCKET_E_INVALID, "overlap variant 0..3");
+    if (opt == ROCKET_OPT_OVL_BLOCK && value > 64) return rk::fail(ctx, ROCKET_E_INVALID, "overlap block <= 64");
+    ctx->opt[opt] = value;
+    return ROCKET_OK;
+}
+
+rocket_status rocket_get_option(const rocket_ctx *ctx, rocket_option opt, int64_t *value)
+{
+    if (!ctx || !value) return rk::fail(nullptr, ROCKET_E_INVALID, "NULL argument");
+    if (opt < ROCKET_OPT_NCC_TILE || opt > ROCKET_OPT_TIMING) return ROCKET_E_UNSUPPORTED;
+    *value = ctx->opt[opt];
+    return ROCKET_OK;
+}
+
+rocket_status rocket_get_stats(const rocket_ctx *ctx, rocket_stats *out)
+{
+    if (!ctx || !out) return rk::fail(nullptr, ROCKET_E_INVALID, "NULL argument");
+    *out = ctx->stats;
+    out->kernel_ns = -1;
+    if (ctx->ev_pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(ctx->ev_end) == hipSuccess && hipEventElapsedTime(&ms, ctx->ev_begin, ctx->ev_end) == hipSuccess)
+            out->kernel_ns = (int64_t)((double)ms * 1e6);
+        else
+            (void)hipGetLastError();
+    }
+    return ROCKET_OK;
+}
+
+rocket_status rocket_get_ledger(rocket_ctx *ctx, int32_t *out, int64_t cap, int64_t *count)
+{
+    RK_TRY(enter(ctx));
+    if (!count) return rk::fail(ctx, ROCKET_E_INVALID, "count is NULL");
+    *count = ctx->ledger_items;
+    if (!ctx->opt[ROCKET_OPT_LEDGER] || !ctx->ws[rk::WS_LEDGER].ptr)
+        return rk::fail(ctx, ROCKET_E_STATE, "ledger not enabled for the last compare");
+    const int64_t m = std::min(cap, ctx->ledger_items);
+    RK_HIP(hipDeviceSynchronize());
+    if (m > 0) RK_HIP(hipMemcpy(out, ctx->ws[rk::WS_LEDGER].ptr, sizeof(int32_t) * m, hipMemcpyDeviceToHost));
+    return ROCKET_OK;
+}
+
+rocket_status rocket_autotune(rocket_ctx *ctx, void *stream)
+{
+    RK_TRY(enter(ctx));
+    if (ctx->prepared_fn == ROCKET_GAUSS_OVERLAP) return rk::ovl_autotune(ctx, (hipStream_t)stream);
+    if (!ctx->prepared_fn) return rk::fail(ctx, ROCKET_E_STATE, "autotune needs a prepared set");
+    return ROCKET_OK;  // dense and sparse paths have fixed shapes
+}
+
+}  // extern "C"
