@@ -65,7 +65,7 @@ typedef enum {
     ROCKET_E_UNSUPPORTED = -2, /* unknown pair function or option */
     ROCKET_E_OOM = -3,         /* workspace allocation failed (or exceeds ROCKET_OPT_WORKSPACE_CAP) */
     ROCKET_E_HIP = -4,         /* a HIP runtime call failed; see rocket_last_error */
-    ROCKET_E_KEYRANGE = -5,    /* sparse key outside [0, 2^32) */
+    ROCKET_E_KEYRANGE = -5,    /* sparse key outside [0, 2^32 - 1) */
     ROCKET_E_UNSORTED = -6,    /* sparse keys of an item not strictly ascending */
     ROCKET_E_STATE = -7        /* rocket_compare without a matching rocket_prepare */
 } rocket_status;
@@ -107,7 +107,7 @@ typedef struct {
     const float *xy;
     double sigma;
     /* Sparse: int64 keys [offsets[n]], strictly ascending within an item and in
-     * [0, 2^32); float32 values [offsets[n]]. */
+     * [0, 2^32 - 1); float32 values [offsets[n]]. */
     const int64_t *keys;
     const float *vals;
 } rocket_items;

@@ -25,8 +25,10 @@ enum Slot {
     WS_OVL_PACK,         // size-sorted packed clouds
     WS_OVL_META,         // per sorted cloud: offset, count, original index
     WS_SP_KEYS,          // packed u32 keys
-    WS_SP_META,          // per item: norm, offsets
-    WS_SP_CHUNKS,        // per item key-chunk offsets
+    WS_SP_META,          // flags, inverse norms, sorted order
+    WS_SP_CHUNKS,        // band histogram over key micro-chunks + chunk counts
+    WS_SP_CSHIFT,        // per band start of its chunk boundaries
+    WS_SP_BOUNDS,        // chunk boundaries (micro-chunk indices)
     WS_COUNT
 };
 
@@ -78,9 +80,16 @@ struct SpState {
     const int64_t *offsets = nullptr;
     const int64_t *keys = nullptr;
     const float *vals = nullptr;
-    int rows = 0, chunk_log2 = 0, nchunks = 0;
-    int64_t tiles = 0;
+    int wlog = 0;
+    int64_t tiles = 0, nchunks_total = 0;
     std::vector<int64_t> h_offsets;
+    std::vector<int> perm;
+    const int64_t *cshift = nullptr;
+    const int *bounds = nullptr;
+    const float *inv_norm = nullptr;
+    const int *dperm = nullptr;
+    const uint32_t *k32 = nullptr;
+    QueueArgs qa{};
     bool valid = false;
 };
 

@@ -114,55 +114,74 @@ __global__ __launch_bounds__(256) void k_ncc_stats(const float *__restrict__ X, 
 }
 
 // ------------------------------------------------------------------------------------------
-// Centre and split.  grid.x covers the K dimension in groups of 4, grid.y strides rows.
-// Rows >= n and columns >= d are written as zeros.
+// Centre and split.  Thread = (row r, K slice kt): reads the slice's 16 values of row r
+// (64 contiguous bytes), writes 16 outputs per plane at ((kt * n_pad + r) * 16), so
+// consecutive threads write consecutive 32-byte (bf16) or 64-byte (fp32) runs.
+// grid.x = K slices, grid.y = groups of 256 rows.  Rows >= n and columns >= d become zeros.
 // ------------------------------------------------------------------------------------------
 template <int SCH>
 __global__ __launch_bounds__(256) void k_ncc_split(const float *__restrict__ X, int64_t ld, int64_t d, int64_t n,
                                                    const double *__restrict__ mu, int64_t n_pad, int64_t d_pad,
                                                    char *__restrict__ planes, int64_t plane_bytes)
 {
-    const int64_t k0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
-    if (k0 >= d_pad) return;
-    const bool vec = ((ld & 3) == 0) && ((((uintptr_t)X) & 15) == 0);
-    for (int64_t r = blockIdx.y; r < n_pad; r += gridDim.y) {
-        float x[4] = {0.f, 0.f, 0.f, 0.f};
-        if (r < n) {
-            const double m = mu[r];
-            const float *a = X + r * ld;
-            if (vec && k0 + 3 < d) {
-                const float4 v = *(const float4 *)(a + k0);
-                x[0] = (float)((double)v.x - m);
-                x[1] = (float)((double)v.y - m);
-                x[2] = (float)((double)v.z - m);
-                x[3] = (float)((double)v.w - m);
-            } else {
+    const int64_t kt = blockIdx.x;
+    const int64_t r = (int64_t)blockIdx.y * 256 + threadIdx.x;
+    if (r >= n_pad) return;
+    const int64_t k0 = kt * 16;
+    float x[16];
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if (k0 + e < d) x[e] = (float)((double)a[k0 + e] - m);
+    for (int e = 0; e < 16; ++e) x[e] = 0.f;
+    if (r < n) {
+        const double m = mu[r];
+        const float *a = X + r * ld + k0;
+        const bool vec = ((ld & 3) == 0) && ((((uintptr_t)X) & 15) == 0) && k0 + 16 <= d;
+        if (vec) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float4 v = ((const float4 *)a)[q];
+                x[4 * q] = (float)((double)v.x - m);
+                x[4 * q + 1] = (float)((double)v.y - m);
+                x[4 * q + 2] = (float)((double)v.z - m);
+                x[4 * q + 3] = (float)((double)v.w - m);
             }
-        }
-        const int64_t dst = ((k0 >> 4) * n_pad + r) * 16 + (k0 & 15);
-        if constexpr (SCH == SCH_FP32) {
-            *(float4 *)((float *)planes + dst) = make_float4(x[0], x[1], x[2], x[3]);
         } else {
-            uint32_t h[4], m[4], l[4];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                h[e] = bf16_rne(x[e]);
-                const float r1 = x[e] - bf16_val(h[e]);
-                m[e] = bf16_rne(r1);
-                const float r2 = r1 - bf16_val(m[e]);
-                l[e] = bf16_rne(r2);
+            for (int e = 0; e < 16; ++e)
+                if (k0 + e < d) x[e] = (float)((double)a[e] - m);
+        }
+    }
+    const int64_t dst = (kt * n_pad + r) * 16;
+    if constexpr (SCH == SCH_FP32) {
+        float4 *p = (float4 *)((float *)planes + dst);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) p[q] = make_float4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
+    } else {
+        uint32_t hw[8], mw[8], lw[8];
+#pragma unroll
+        for (int e = 0; e < 16; e += 2) {
+            uint32_t h2[2], m2[2], l2[2];
+#pragma unroll
+            for (int f = 0; f < 2; ++f) {
+                h2[f] = bf16_rne(x[e + f]);
+                const float r1 = x[e + f] - bf16_val(h2[f]);
+                m2[f] = bf16_rne(r1);
+                const float r2 = r1 - bf16_val(m2[f]);
+                l2[f] = bf16_rne(r2);
             }
-            uint16_t *p0 = (uint16_t *)planes + dst;
-            *(uint2 *)p0 = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
-            uint16_t *p1 = (uint16_t *)(planes + plane_bytes) + dst;
-            *(uint2 *)p1 = make_uint2(m[0] | (m[1] << 16), m[2] | (m[3] << 16));
-            if constexpr (SCH == SCH_X6) {
-                uint16_t *p2 = (uint16_t *)(planes + 2 * plane_bytes) + dst;
-                *(uint2 *)p2 = make_uint2(l[0] | (l[1] << 16), l[2] | (l[3] << 16));
-            }
+            hw[e / 2] = h2[0] | (h2[1] << 16);
+            mw[e / 2] = m2[0] | (m2[1] << 16);
+            lw[e / 2] = l2[0] | (l2[1] << 16);
+        }
+        uint4 *p0 = (uint4 *)((uint16_t *)planes + dst);
+        p0[0] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+        p0[1] = make_uint4(hw[4], hw[5], hw[6], hw[7]);
+        uint4 *p1 = (uint4 *)((uint16_t *)(planes + plane_bytes) + dst);
+        p1[0] = make_uint4(mw[0], mw[1], mw[2], mw[3]);
+        p1[1] = make_uint4(mw[4], mw[5], mw[6], mw[7]);
+        if constexpr (SCH == SCH_X6) {
+            uint4 *p2 = (uint4 *)((uint16_t *)(planes + 2 * plane_bytes) + dst);
+            p2[0] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+            p2[1] = make_uint4(lw[4], lw[5], lw[6], lw[7]);
         }
     }
 }
@@ -488,7 +507,7 @@ rocket_status ncc_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, in
     float *inv_s = (float *)((char *)stats + (((size_t)n * 8 + 255) & ~(size_t)255));
     hipLaunchKernelGGL(k_ncc_stats, dim3((unsigned)n), dim3(256), 0, s, it->dense, it->ld, it->dim, mu, inv_s);
     RK_HIP(hipGetLastError());
-    const dim3 g((unsigned)((st.d_pad / 4 + 255) / 256), (unsigned)std::min<int64_t>(st.n_pad, 65535));
+    const dim3 g((unsigned)st.nkt, (unsigned)((st.n_pad + 255) / 256));
     if (scheme == SCH_FP32)
         hipLaunchKernelGGL(k_ncc_split<SCH_FP32>, g, dim3(256), 0, s, it->dense, it->ld, it->dim, n, mu, st.n_pad,
                            st.d_pad, (char *)planes, plane_bytes);

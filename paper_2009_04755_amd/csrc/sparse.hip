@@ -1,0 +1,448 @@
+// Cosine similarity of sparse key/value vectors with the exact key-intersection size
+// (Section V-B compare kernel: the dot product of two sparse composition vectors), gfx950.
+//
+//   m_ij = |K_i & K_j|,  cos_ij = sum_{k in K_i & K_j} v_ik v_jk / (|v_i| |v_j|).
+//
+// Prepare validates the keys (strictly ascending per item, in [0, 2^32 - 1)), packs them to
+// u32, reduces every item's L2 norm in FP64, and sorts items by nnz (largest first) so the
+// streams processed side by side have similar lengths.  Work item = (band of RB=16 sorted
+// row items) x (block of CB=128 sorted column items).  The key space is cut, per band, into
+// chunks holding at most UMAX row entries (counted on a histogram of the band's keys over
+// fixed-width micro-chunks).  For every chunk the workgroup builds in LDS a hash table of the
+// band's keys whose slots carry the 16 row values (zero when absent) and 16 presence bytes;
+// then each column streams its keys of that chunk (8 lanes per column, coalesced), probes the
+// table and accumulates 16 dot products and 16 counts in registers.  Keys match by integer
+// equality, so counts are exact; chunk sums are added with compensation and the 8 lanes of a
+// column combine in a fixed butterfly, so results do not depend on scheduling.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "common.hpp"
+#include "queue.hpp"
+
+namespace rk {
+namespace {
+
+constexpr int RB = 16;          // rows per band
+constexpr int LPC = 8;          // lanes per column
+constexpr int SP_THREADS = 1024;
+constexpr int CB = SP_THREADS / LPC;  // columns per block
+constexpr int UMAX = 1536;      // union capacity of one chunk (row entries)
+constexpr int HBITS = 12;
+constexpr int HSIZE = 1 << HBITS;
+constexpr uint32_t EMPTY = 0xFFFFFFFFu;
+
+enum { FLAG_UNSORTED = 1, FLAG_RANGE = 2, FLAG_OVERFLOW = 4 };
+
+__device__ __forceinline__ uint32_t hslot(uint32_t key) { return (key * 2654435761u) >> (32 - HBITS); }
+
+// Validate, pack to u32, FP64 norm.  One workgroup per item.
+__global__ __launch_bounds__(256) void k_sp_validate(const int64_t *__restrict__ keys, const float *__restrict__ vals,
+                                                     const int64_t *__restrict__ off, int n,
+                                                     uint32_t *__restrict__ k32, float *__restrict__ inv_norm,
+                                                     unsigned *__restrict__ flags, unsigned *__restrict__ maxkey)
+{
+    const int i = blockIdx.x;
+    const int64_t b = off[i], e = off[i + 1];
+    double ss = 0.0;
+    unsigned bad = 0, mx = 0;
+    for (int64_t p = b + threadIdx.x; p < e; p += 256) {
+        const int64_t k = keys[p];
+        if (k < 0 || k >= 0xFFFFFFFFll) bad |= FLAG_RANGE;  // 0xFFFFFFFF marks an empty hash slot
+        if (p > b && keys[p - 1] >= k) bad |= FLAG_UNSORTED;
+        k32[p] = (uint32_t)k;
+        mx = max(mx, (unsigned)(k & 0xFFFFFFFFll));
+        const double v = vals[p];
+        ss += v * v;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        ss += __shfl_xor(ss, o);
+        bad |= __shfl_xor(bad, o);
+        mx = max(mx, (unsigned)__shfl_xor((int)mx, o));
+    }
+    __shared__ double red[4];
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[w] = ss;
+        if (bad) atomicOr(flags, bad);
+        atomicMax(maxkey, mx);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double t = (red[0] + red[1]) + (red[2] + red[3]);
+        inv_norm[i] = t > 0 ? (float)(1.0 / sqrt(t)) : __builtin_nanf("");
+    }
+}
+
+// Histogram of every band's keys over micro-chunks of width 2^wlog.
+__global__ __launch_bounds__(256) void k_sp_hist(const uint32_t *__restrict__ k32, const int64_t *__restrict__ off,
+                                                 const int *__restrict__ perm, int n, int wlog, int64_t nmc,
+                                                 unsigned *__restrict__ hist)
+{
+    const int s = blockIdx.x;  // sorted position
+    const int i = perm[s];
+    unsigned *h = hist + (int64_t)(s / RB) * nmc;
+    for (int64_t p = off[i] + threadIdx.x; p < off[i + 1]; p += 256) atomicAdd(h + (k32[p] >> wlog), 1u);
+}
+
+// Greedy cut of each band's micro-chunks into chunks of at most UMAX entries.  Pass 0 counts
+// chunks per band, pass 1 writes their starting micro-chunk.  One workgroup per band; the
+// counts are staged through LDS and scanned by one thread.
+__global__ __launch_bounds__(256) void k_sp_cut(const unsigned *__restrict__ hist, int64_t nmc, int pass,
+                                                int *__restrict__ nchunks, const int64_t *__restrict__ cstart,
+                                                int *__restrict__ bounds, unsigned *__restrict__ flags)
+{
+    const int band = blockIdx.x;
+    const unsigned *h = hist + (int64_t)band * nmc;
+    __shared__ unsigned buf[1024];
+    unsigned acc = 0;
+    int cnt = 0;
+    int *out = pass ? bounds + cstart[band] : nullptr;
+    if (pass && threadIdx.x == 0) out[0] = 0;
+    for (int64_t m0 = 0; m0 < nmc; m0 += 1024) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < 1024; k += 256) buf[k] = m0 + k < nmc ? h[m0 + k] : 0u;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const int lim = (int)min<int64_t>(1024, nmc - m0);
+            for (int k = 0; k < lim; ++k) {
+                const unsigned c = buf[k];
+                if (c > (unsigned)UMAX) atomicOr(flags, (unsigned)FLAG_OVERFLOW);
+                if (acc + c > (unsigned)UMAX && acc > 0) {
+                    ++cnt;
+                    if (pass) out[cnt] = (int)(m0 + k);
+                    acc = 0;
+                }
+                acc += c;
+            }
+        }
+    }
+    if (threadIdx.x == 0) {
+        ++cnt;  // the last (possibly empty) chunk
+        if (pass)
+            out[cnt] = (int)nmc;
+        else
+            nchunks[band] = cnt;
+    }
+}
+
+__global__ __launch_bounds__(SP_THREADS, 1) void k_sparse(const uint32_t *__restrict__ k32, const float *__restrict__ vals,
+                                                         const int64_t *__restrict__ off, const int *__restrict__ perm,
+                                                         const float *__restrict__ inv_norm, int n, int wlog,
+                                                         const int64_t *__restrict__ cshift,
+                                                         const int *__restrict__ bounds, QueueArgs q,
+                                                         float *__restrict__ out, uint32_t *__restrict__ counts)
+{
+    __shared__ uint32_t hkey[HSIZE];
+    __shared__ uint16_t hidx[HSIZE];
+    __shared__ __align__(16) float uval[UMAX * RB];       // row values per union entry
+    __shared__ __align__(16) uint32_t upres[UMAX * RB / 4];  // presence bytes per union entry
+    __shared__ int s_item, s_ucount;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int sub = lane & (LPC - 1);        // lane within the column group
+    const int col = tid / LPC;               // column within the block
+    const uint64_t gmask = 0xFFull << (lane & ~(LPC - 1));
+
+    for (;;) {
+        const int it = queue_pop_wg(q, &s_item);
+        if (it < 0) break;
+        const int4 w = q.items[it];
+        const int band = w.x, cblk = w.y;
+        const int r0 = band * RB, c0 = cblk * CB;
+        // this wave stages row r0 + wave (16 waves, 16 rows)
+        const int srow = r0 + wave;
+        const bool row_ok = srow < n;
+        const int irow = row_ok ? perm[srow] : 0;
+        int64_t rpos = row_ok ? off[irow] : 0;
+        const int64_t rend = row_ok ? off[irow + 1] : 0;
+        // this lane group's column
+        const int scol = c0 + col;
+        const bool col_ok = scol < n;
+        const int icol = col_ok ? perm[scol] : 0;
+        int64_t cpos = col_ok ? off[icol] : 0;
+        const int64_t cend = col_ok ? off[icol + 1] : 0;
+
+        float dot[RB], comp[RB];
+        uint32_t cnt[RB];
+#pragma unroll
+        for (int t = 0; t < RB; ++t) {
+            dot[t] = 0.f;
+            comp[t] = 0.f;
+            cnt[t] = 0;
+        }
+        // band b's nch + 1 chunk boundaries (micro-chunk indices) start at cshift[b]
+        const int nch = (int)(cshift[band + 1] - cshift[band]) - 1;
+        const int *bnd = bounds + cshift[band];
+        int prev_u = UMAX;
+        for (int ch = 0; ch < nch; ++ch) {
+            const uint64_t K1 = (uint64_t)bnd[ch + 1] << wlog;
+            // 1. clear the table
+            for (int k = tid; k < HSIZE; k += SP_THREADS) hkey[k] = EMPTY;
+            for (int k = tid; k < prev_u * RB / 4; k += SP_THREADS) {
+                upres[k] = 0u;
+                *(float4 *)&uval[4 * k] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+            if (tid == 0) s_ucount = 0;
+            __syncthreads();
+            // 2a. insert the band's keys of this chunk
+            int64_t rp = rpos;
+            while (true) {
+                const int64_t p = rp + lane;
+                const bool in = p < rend && (uint64_t)k32[p] < K1;
+                if (in) {
+                    const uint32_t key = k32[p];
+                    uint32_t h = hslot(key);
+                    while (true) {
+                        const uint32_t old = atomicCAS(&hkey[h], EMPTY, key);
+                        if (old == EMPTY) {
+                            hidx[h] = (uint16_t)atomicAdd(&s_ucount, 1);
+                            break;
+                        }
+                        if (old == key) break;
+                        h = (h + 1) & (HSIZE - 1);
+                    }
+                }
+                const int nin = __popcll(__ballot(in));
+                rp += nin;
+                if (nin < 64) break;
+            }
+            __syncthreads();
+            // 2b. scatter the row values and presence bytes
+            while (true) {
+                const int64_t p = rpos + lane;
+                const bool in = p < rend && (uint64_t)k32[p] < K1;
+                if (in) {
+                    const uint32_t key = k32[p];
+                    uint32_t h = hslot(key);
+                    while (hkey[h] != key) h = (h + 1) & (HSIZE - 1);
+                    const int u = hidx[h];
+                    uval[u * RB + wave] = vals[p];
+                    atomicOr(&upres[u * (RB / 4) + (wave >> 2)], 1u << (8 * (wave & 3)));
+                }
+                const int nin = __popcll(__ballot(in));
+                rpos += nin;
+                if (nin < 64) break;
+            }
+            __syncthreads();
+            prev_u = min(s_ucount, UMAX);
+            // 3. stream this column's keys of the chunk and probe
+            float cd[RB];
+#pragma unroll
+            for (int t = 0; t < RB; ++t) cd[t] = 0.f;
+            uint32_t pk[RB / 4] = {0u, 0u, 0u, 0u};
+            int since = 0;
+            while (true) {
+                const int64_t p = cpos + sub;
+                const bool in = p < cend && (uint64_t)k32[p] < K1;
+                if (in) {
+                    const uint32_t key = k32[p];
+                    const float vj = vals[p];
+                    uint32_t h = hslot(key);
+                    uint32_t hk;
+                    while ((hk = hkey[h]) != key && hk != EMPTY) h = (h + 1) & (HSIZE - 1);
+                    if (hk == key) {
+                        const int u = hidx[h];
+                        const float4 *uv = (const float4 *)&uval[u * RB];
+#pragma unroll
+                        for (int qd = 0; qd < RB / 4; ++qd) {
+                            const float4 v4 = uv[qd];
+                            cd[4 * qd] = fmaf(v4.x, vj, cd[4 * qd]);
+                            cd[4 * qd + 1] = fmaf(v4.y, vj, cd[4 * qd + 1]);
+                            cd[4 * qd + 2] = fmaf(v4.z, vj, cd[4 * qd + 2]);
+                            cd[4 * qd + 3] = fmaf(v4.w, vj, cd[4 * qd + 3]);
+                        }
+                        const uint4 pr = *(const uint4 *)&upres[u * (RB / 4)];
+                        pk[0] += pr.x;
+                        pk[1] += pr.y;
+                        pk[2] += pr.z;
+                        pk[3] += pr.w;
+                        if (++since == 255) {  // unpack before a byte counter can wrap
+#pragma unroll
+                            for (int t = 0; t < RB; ++t) cnt[t] += (pk[t >> 2] >> (8 * (t & 3))) & 0xFFu;
+                            pk[0] = pk[1] = pk[2] = pk[3] = 0u;
+                            since = 0;
+                        }
+                    }
+                }
+                const int nin = __popcll(__ballot(in) & gmask);
+                cpos += nin;
+                if (nin < LPC) break;
+            }
+#pragma unroll
+            for (int t = 0; t < RB; ++t) {
+                cnt[t] += (pk[t >> 2] >> (8 * (t & 3))) & 0xFFu;
+                // compensated add of the chunk sum
+                const float y = cd[t] - comp[t];
+                const float s = dot[t] + y;
+                comp[t] = (s - dot[t]) - y;
+                dot[t] = s;
+            }
+            __syncthreads();
+        }
+        // combine the 8 lanes of each column (fixed butterfly) and write
+#pragma unroll
+        for (int t = 0; t < RB; ++t) {
+#pragma unroll
+            for (int o = 1; o < LPC; o <<= 1) {
+                dot[t] += __shfl_xor(dot[t], o);
+                cnt[t] += __shfl_xor(cnt[t], o);
+            }
+        }
+        if (col_ok) {
+#pragma unroll
+            for (int t = 0; t < RB; ++t) {
+                if ((t >> 1) != sub) continue;  // lane sub writes rows 2*sub, 2*sub+1
+                const int srow2 = r0 + t;
+                if (srow2 >= n || srow2 >= scol) continue;
+                const int a = perm[srow2], b = icol;
+                const int64_t i = min(a, b), j = max(a, b);
+                const int64_t idx = i * n - i * (i + 1) / 2 + (j - i - 1);
+                out[idx] = dot[t] * inv_norm[a] * inv_norm[b];
+                if (counts) counts[idx] = cnt[t];
+            }
+        }
+    }
+}
+
+}  // namespace
+
+rocket_status sp_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, hipStream_t s)
+{
+    SpState &sp = ctx->sp;
+    sp.valid = false;
+    if (n > 0 && (!it->offsets || !it->keys || !it->vals)) return fail(ctx, ROCKET_E_INVALID, "offsets/keys/vals NULL");
+    if (n >= (1 << 30)) return fail(ctx, ROCKET_E_INVALID, "n too large");
+    sp.n = n;
+    sp.offsets = it->offsets;
+    sp.keys = it->keys;
+    sp.vals = it->vals;
+    sp.h_offsets.assign((size_t)n + 1, 0);
+    if (n > 0) {
+        RK_HIP(hipMemcpyAsync(sp.h_offsets.data(), it->offsets, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, s));
+        RK_HIP(hipStreamSynchronize(s));
+    }
+    if (sp.h_offsets[0] != 0) return fail(ctx, ROCKET_E_INVALID, "offsets[0] != 0");
+    for (int64_t i = 0; i < n; ++i)
+        if (sp.h_offsets[i + 1] < sp.h_offsets[i]) return fail(ctx, ROCKET_E_INVALID, "offsets decrease");
+    sp.total = sp.h_offsets[n];
+    if (n < 2) {
+        sp.tiles = 0;
+        sp.valid = true;
+        return ROCKET_OK;
+    }
+    // size sort
+    sp.perm.resize(n);
+    std::iota(sp.perm.begin(), sp.perm.end(), 0);
+    std::stable_sort(sp.perm.begin(), sp.perm.end(), [&](int a, int b) {
+        return sp.h_offsets[a + 1] - sp.h_offsets[a] > sp.h_offsets[b + 1] - sp.h_offsets[b];
+    });
+    const int64_t nbands = (n + RB - 1) / RB, nblk = (n + CB - 1) / CB;
+    // device buffers: u32 keys; meta = flags (2 words) | inverse norms | sorted-position -> item
+    void *kp = nullptr, *meta = nullptr;
+    RK_TRY(ws_get(ctx, WS_SP_KEYS, sizeof(uint32_t) * (size_t)std::max<int64_t>(sp.total, 1), &kp));
+    RK_TRY(ws_get(ctx, WS_SP_META, 256 + (sizeof(float) + sizeof(int)) * (size_t)n, &meta));
+    unsigned *flags = (unsigned *)meta;  // [0] error flags, [1] max key
+    float *inv_norm = (float *)((char *)meta + 256);
+    int *perm = (int *)(inv_norm + n);
+    RK_HIP(hipMemsetAsync(flags, 0, 8, s));
+    RK_HIP(hipMemcpyAsync(perm, sp.perm.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_sp_validate, dim3((unsigned)n), dim3(256), 0, s, it->keys, it->vals, it->offsets, (int)n,
+                       (uint32_t *)kp, inv_norm, flags, flags + 1);
+    RK_HIP(hipGetLastError());
+    unsigned hf[2] = {0, 0};
+    RK_HIP(hipMemcpyAsync(hf, flags, 8, hipMemcpyDeviceToHost, s));
+    RK_HIP(hipStreamSynchronize(s));
+    if (hf[0] & FLAG_RANGE) return fail(ctx, ROCKET_E_KEYRANGE, "a key is outside [0, 2^32 - 1)");
+    if (hf[0] & FLAG_UNSORTED) return fail(ctx, ROCKET_E_UNSORTED, "keys of an item are not strictly ascending");
+    // micro-chunk width 2^wlog: at most 2^20 micro-chunks and a histogram of at most 4 GiB
+    const uint64_t maxkey = hf[1];
+    int wlog = 0;
+    while (((maxkey >> wlog) + 1) > (uint64_t)(1 << 20)) ++wlog;
+    while ((uint64_t)nbands * ((maxkey >> wlog) + 1) * 4 > ((uint64_t)4 << 30)) ++wlog;
+    const int64_t nmc = (int64_t)(maxkey >> wlog) + 1;
+    void *hp = nullptr;
+    RK_TRY(ws_get(ctx, WS_SP_CHUNKS, sizeof(unsigned) * (size_t)(nbands * nmc) + sizeof(int) * (nbands + 1), &hp));
+    unsigned *hist = (unsigned *)hp;
+    int *nchunks = (int *)(hist + nbands * nmc);
+    RK_HIP(hipMemsetAsync(hist, 0, sizeof(unsigned) * (size_t)(nbands * nmc), s));
+    hipLaunchKernelGGL(k_sp_hist, dim3((unsigned)n), dim3(256), 0, s, (const uint32_t *)kp, it->offsets,
+                       (const int *)perm, (int)n, wlog, nmc, hist);
+    RK_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_sp_cut, dim3((unsigned)nbands), dim3(256), 0, s, (const unsigned *)hist, nmc, 0, nchunks,
+                       (const int64_t *)nullptr, (int *)nullptr, flags);
+    RK_HIP(hipGetLastError());
+    std::vector<int> hn(nbands);
+    RK_HIP(hipMemcpyAsync(hn.data(), nchunks, sizeof(int) * nbands, hipMemcpyDeviceToHost, s));
+    RK_HIP(hipMemcpyAsync(hf, flags, 4, hipMemcpyDeviceToHost, s));
+    RK_HIP(hipStreamSynchronize(s));
+    if (hf[0] & FLAG_OVERFLOW)
+        return fail(ctx, ROCKET_E_UNSUPPORTED, "more than 1536 keys of one 16-item band fall in one micro-chunk");
+    // band b's nch_b + 1 boundaries live at cshift[b] = sum_{c<b} (nch_c + 1)
+    std::vector<int64_t> cshift(nbands + 1, 0);
+    for (int64_t b = 0; b < nbands; ++b) cshift[b + 1] = cshift[b] + hn[b] + 1;
+    void *csp = nullptr, *bp = nullptr;
+    RK_TRY(ws_get(ctx, WS_SP_CSHIFT, sizeof(int64_t) * (size_t)(nbands + 1), &csp));
+    RK_TRY(ws_get(ctx, WS_SP_BOUNDS, sizeof(int) * (size_t)cshift[nbands], &bp));
+    RK_HIP(hipMemcpyAsync(csp, cshift.data(), sizeof(int64_t) * (nbands + 1), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_sp_cut, dim3((unsigned)nbands), dim3(256), 0, s, (const unsigned *)hist, nmc, 1, nchunks,
+                       (const int64_t *)csp, (int *)bp, flags);
+    RK_HIP(hipGetLastError());
+    RK_HIP(hipStreamSynchronize(s));  // cshift staging vector goes out of scope
+    sp.wlog = wlog;
+    sp.cshift = (const int64_t *)csp;
+    sp.bounds = (const int *)bp;
+    sp.inv_norm = inv_norm;
+    sp.dperm = perm;
+    sp.k32 = (const uint32_t *)kp;
+    sp.nchunks_total = cshift[nbands] - nbands;
+    // tiles: (band, column block) with at least one pair a < b; cost = streamed entries
+    std::vector<int64_t> bnnz(nblk, 0), rnnz(nbands, 0);
+    for (int64_t s2 = 0; s2 < n; ++s2) {
+        const int64_t c = sp.h_offsets[sp.perm[s2] + 1] - sp.h_offsets[sp.perm[s2]];
+        bnnz[s2 / CB] += c;
+        rnnz[s2 / RB] += c;
+    }
+    std::vector<int4> raw;
+    std::vector<double> cost;
+    for (int64_t b = 0; b < nbands; ++b)
+        for (int64_t c = 0; c < nblk; ++c) {
+            const int64_t rlo = b * RB, chi = std::min<int64_t>(n, (c + 1) * CB) - 1;
+            if (rlo >= chi) continue;  // no pair a < b
+            raw.push_back(make_int4((int)b, (int)c, 0, (int)raw.size()));
+            cost.push_back((double)bnnz[c] + (double)rnnz[b] + 2048.0 * hn[b]);
+        }
+    plan_lpt(raw, cost, MAX_SEG, ctx->h_items, ctx->h_seg);
+    if (ctx->opt[ROCKET_OPT_QUEUE_ORDER] == 1) shuffle_items(ctx->h_items, ctx->h_seg, (uint64_t)ctx->opt[ROCKET_OPT_SEED]);
+    if (ctx->opt[ROCKET_OPT_QUEUE_ORDER] == 2) single_segment(ctx->h_seg, (int64_t)ctx->h_items.size());
+    sp.tiles = (int64_t)ctx->h_items.size();
+    if (sp.tiles) RK_TRY(upload_queue(ctx, s, &sp.qa));
+    ctx->queue_owner = QOWN_SP;
+    ctx->stats.tiles = sp.tiles;
+    ctx->stats.work_items = sp.tiles;
+    ctx->stats.tile = RB;
+    ctx->stats.kchunk = sp.nchunks_total;
+    sp.valid = true;
+    return ROCKET_OK;
+}
+
+rocket_status sp_compare(rocket_ctx *ctx, float *out, uint32_t *counts, hipStream_t s)
+{
+    SpState &sp = ctx->sp;
+    if (!sp.valid) return fail(ctx, ROCKET_E_STATE, "sparse set not prepared");
+    if (sp.n < 2 || sp.tiles == 0) return ROCKET_OK;
+    if (ctx->queue_owner != QOWN_SP) return fail(ctx, ROCKET_E_STATE, "queue was replanned by another prepare");
+    RK_TRY(reset_queue(ctx, s, sp.qa));
+    const int grid = auto_grid(ctx, (const void *)&k_sparse, SP_THREADS, 0, sp.tiles);
+    ctx->stats.grid = grid;
+    RK_TRY(timing_begin(ctx, s));
+    hipLaunchKernelGGL(k_sparse, dim3(grid), dim3(SP_THREADS), 0, s, sp.k32, sp.vals, sp.offsets, sp.dperm, sp.inv_norm,
+                       (int)sp.n, sp.wlog, sp.cshift, sp.bounds, sp.qa,
+                       out, counts);
+    RK_HIP(hipGetLastError());
+    RK_TRY(timing_end(ctx, s));
+    return ROCKET_OK;
+}
+
+}  // namespace rk

@@ -1,0 +1,119 @@
+"""GPU parity of the sparse cosine against the FP64 oracle.
+
+Intersection sizes must be bit-exact.  Cosines: all products are positive, so no floor is
+needed: |g - r| <= 1e-5 * r, and a pair with no shared key must give exactly 0.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2009_04755_amd import synth
+
+from gpu_util import announce, device_or_skip
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    device_or_skip()
+    from paper_2009_04755_amd import Context
+    return Context(0)
+
+
+def _dev(off, keys, vals):
+    import torch
+    from paper_2009_04755_amd import SparseSet
+    return SparseSet(torch.from_numpy(off).cuda(), torch.from_numpy(keys).cuda(), torch.from_numpy(vals).cuda())
+
+
+def _check(got, cnt, off, keys, vals, pi, pj):
+    ref, rcnt, _ = oracle.sparse_cosine(off, keys, vals, pi, pj)
+    assert np.array_equal(cnt.astype(np.int64), rcnt), np.nonzero(cnt != rcnt)[0][:5]
+    zero = rcnt == 0
+    nanref = np.isnan(ref)
+    assert np.all(np.isnan(got[nanref]))
+    ok = ~nanref
+    assert np.all(got[ok & zero] == 0.0)
+    err = np.abs(got[ok] - ref[ok]) / np.maximum(np.abs(ref[ok]), 1e-300)
+    err[zero[ok]] = 0
+    assert err.max() <= 1e-5, err.max()
+    return err.max()
+
+
+@pytest.mark.parametrize("n,nnz_mean,nnz_max,key_space", [
+    (2, 50, 200, 1000), (17, 300, 2000, 5000), (40, 500, 3000, 20 ** 4), (130, 800, 5000, 20 ** 4),
+    (300, 2000, 20000, 20 ** 6),
+])
+def test_all_pairs_small(ctx, n, nnz_mean, nnz_max, key_space):
+    announce("sparse all pairs n=%d nnz~%d keys<%d" % (n, nnz_mean, key_space))
+    off, keys, vals = synth.sparse_vectors(n, key_space=key_space, nnz_mean=nnz_mean, nnz_min=1, nnz_max=nnz_max,
+                                           config=4, salt=n)
+    ctx.set(queue_order=0)
+    got, cnt = ctx.allpairs(_dev(off, keys, vals), "sparse_cosine", counts=True)
+    pi, pj = oracle.all_pairs(n)
+    _check(got.cpu().numpy(), cnt.cpu().numpy(), off, keys, vals, pi, pj)
+
+
+def test_edge_items(ctx):
+    announce("sparse edge items")
+    items = [
+        ([], []),                                    # empty: zero norm -> NaN
+        ([0, 5, 9, 2 ** 32 - 2], [0.5, 0.25, 0.125, 2.0]),
+        ([0, 5, 9, 2 ** 32 - 2], [0.5, 0.25, 0.125, 2.0]),  # duplicate: cos 1, count 4
+        ([1, 6, 10], [1.0, 2.0, 3.0]),               # disjoint from the above
+        ([5], [0.0]),                                # zero norm, but shares key 5
+        ([9, 10, 11, 12, 13], [1.0, 1.0, 1.0, 1.0, 1.0]),
+    ]
+    off = np.zeros(len(items) + 1, dtype=np.int64)
+    off[1:] = np.cumsum([len(k) for k, _ in items])
+    keys = np.concatenate([np.asarray(k, dtype=np.int64) for k, _ in items])
+    vals = np.concatenate([np.asarray(v, dtype=np.float32) for _, v in items])
+    got, cnt = ctx.allpairs(_dev(off, keys, vals), "sparse_cosine", counts=True)
+    got, cnt = got.cpu().numpy(), cnt.cpu().numpy()
+    n = len(items)
+    pi, pj = oracle.all_pairs(n)
+    _check(got, cnt, off, keys, vals, pi, pj)
+    from paper_2009_04755_amd import pair_index
+    assert cnt[pair_index(1, 2, n)] == 4 and abs(got[pair_index(1, 2, n)] - 1.0) < 1e-6
+    assert cnt[pair_index(1, 4, n)] == 1 and np.isnan(got[pair_index(1, 4, n)])
+
+
+def test_workload_shaped_sampled_and_deterministic(ctx):
+    # 600 items over 20^6 keys, lognormal nnz (mean 20,000, clipped to [2,000, 100,000]), Zipf(1.1)
+    import torch
+    announce("sparse n=600 workload-shaped sampled + determinism")
+    off, keys, vals = synth.sparse_vectors(600, nnz_mean=20_000, nnz_min=2_000, nnz_max=100_000, config=4, salt=77)
+    S = _dev(off, keys, vals)
+    ctx.set(queue_order=0, ledger=1)
+    a, ca = ctx.allpairs(S, "sparse_cosine", counts=True)
+    assert np.all(ctx.ledger() == 1)
+    ctx.set(queue_order=1, seed=5, ledger=0)
+    b, cb = ctx.allpairs(S, "sparse_cosine", counts=True)
+    ctx.set(queue_order=0, seed=0)
+    assert torch.equal(a, b) and torch.equal(ca, cb)
+    g = np.random.default_rng(1)
+    i = g.integers(0, 600, 4000)
+    j = g.integers(0, 600, 4000)
+    pi, pj = np.minimum(i, j), np.maximum(i, j)
+    keep = pi < pj
+    pi, pj = pi[keep], pj[keep]
+    idx = pi * 600 - pi * (pi + 1) // 2 + (pj - pi - 1)
+    err = _check(a.cpu().numpy()[idx], ca.cpu().numpy()[idx], off, keys, vals, pi, pj)
+    announce("max rel err %.2e" % err)
+
+
+def test_errors(ctx):
+    from paper_2009_04755_amd._lib import RocketError, E_KEYRANGE, E_UNSORTED
+    announce("sparse errors")
+    off = np.array([0, 3, 5], dtype=np.int64)
+    vals = np.ones(5, dtype=np.float32)
+    with pytest.raises(RocketError) as e:
+        ctx.allpairs(_dev(off, np.array([1, 3, 3, 0, 1], dtype=np.int64), vals), "sparse_cosine")
+    assert e.value.status == E_UNSORTED
+    with pytest.raises(RocketError) as e:
+        ctx.allpairs(_dev(off, np.array([1, 3, 2 ** 32 - 1, 0, 1], dtype=np.int64), vals), "sparse_cosine")
+    assert e.value.status == E_KEYRANGE
+    with pytest.raises(RocketError) as e:
+        ctx.allpairs(_dev(off, np.array([-1, 3, 4, 0, 1], dtype=np.int64), vals), "sparse_cosine")
+    assert e.value.status == E_KEYRANGE
