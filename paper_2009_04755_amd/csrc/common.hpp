@@ -132,7 +132,7 @@ rocket_status timing_end(rocket_ctx *ctx, hipStream_t s);
 void plan_leaves(int64_t n, int64_t T, std::vector<int2> &out);
 // Split `tiles` x `chunks` work items into per-XCD segments in chunk-major order.
 void plan_chunked(const std::vector<int2> &tiles, int nchunks, int nseg, std::vector<int4> &items,
-                  std::vector<int> &seg);
+                  std::vector<int> &seg, int halves = 1);
 // Cost-ordered (largest first) items dealt round-robin to segments.
 void plan_lpt(const std::vector<int4> &items_in, const std::vector<double> &cost, int nseg,
               std::vector<int4> &items, std::vector<int> &seg);

@@ -11,6 +11,7 @@
 //   k_ncc_finish  per output pair: fixed-order sum of the K-chunk partials, rescale by
 //                 1/(s_i s_j), scatter to the packed upper triangle
 #include <cmath>
+#include <type_traits>
 
 #include "common.hpp"
 #include "queue.hpp"
@@ -114,74 +115,79 @@ __global__ __launch_bounds__(256) void k_ncc_stats(const float *__restrict__ X, 
 }
 
 // ------------------------------------------------------------------------------------------
-// Centre and split.  Thread = (row r, K slice kt): reads the slice's 16 values of row r
-// (64 contiguous bytes), writes 16 outputs per plane at ((kt * n_pad + r) * 16), so
-// consecutive threads write consecutive 32-byte (bf16) or 64-byte (fp32) runs.
-// grid.x = K slices, grid.y = groups of 256 rows.  Rows >= n and columns >= d become zeros.
+// Centre and split.  Thread = (row r, four consecutive K slices): reads 64 contiguous values
+// of row r (256 bytes), writes for each slice kt 16 outputs per plane at ((kt * n_pad + r) *
+// 16), so consecutive threads write consecutive 32-byte (bf16) or 64-byte (fp32) runs.
+// grid.x = groups of four K slices, grid.y = groups of 256 rows.  Rows >= n and columns >= d
+// become zeros.
 // ------------------------------------------------------------------------------------------
 template <int SCH>
 __global__ __launch_bounds__(256) void k_ncc_split(const float *__restrict__ X, int64_t ld, int64_t d, int64_t n,
-                                                   const double *__restrict__ mu, int64_t n_pad, int64_t d_pad,
+                                                   const double *__restrict__ mu, int64_t n_pad, int64_t nkt,
                                                    char *__restrict__ planes, int64_t plane_bytes)
 {
-    const int64_t kt = blockIdx.x;
     const int64_t r = (int64_t)blockIdx.y * 256 + threadIdx.x;
     if (r >= n_pad) return;
-    const int64_t k0 = kt * 16;
-    float x[16];
+    const bool vec = ((ld & 3) == 0) && ((((uintptr_t)X) & 15) == 0);
+    const double m = r < n ? mu[r] : 0.0;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) x[e] = 0.f;
-    if (r < n) {
-        const double m = mu[r];
-        const float *a = X + r * ld + k0;
-        const bool vec = ((ld & 3) == 0) && ((((uintptr_t)X) & 15) == 0) && k0 + 16 <= d;
-        if (vec) {
+    for (int sl = 0; sl < 4; ++sl) {
+        const int64_t kt = (int64_t)blockIdx.x * 4 + sl;
+        if (kt >= nkt) break;
+        const int64_t k0 = kt * 16;
+        float x[16];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const float4 v = ((const float4 *)a)[q];
-                x[4 * q] = (float)((double)v.x - m);
-                x[4 * q + 1] = (float)((double)v.y - m);
-                x[4 * q + 2] = (float)((double)v.z - m);
-                x[4 * q + 3] = (float)((double)v.w - m);
+        for (int e = 0; e < 16; ++e) x[e] = 0.f;
+        if (r < n) {
+            const float *a = X + r * ld + k0;
+            if (vec && k0 + 16 <= d) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float4 v = ((const float4 *)a)[q];
+                    x[4 * q] = (float)((double)v.x - m);
+                    x[4 * q + 1] = (float)((double)v.y - m);
+                    x[4 * q + 2] = (float)((double)v.z - m);
+                    x[4 * q + 3] = (float)((double)v.w - m);
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    if (k0 + e < d) x[e] = (float)((double)a[e] - m);
             }
+        }
+        const int64_t dst = (kt * n_pad + r) * 16;
+        if constexpr (SCH == SCH_FP32) {
+            float4 *p = (float4 *)((float *)planes + dst);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) p[q] = make_float4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
         } else {
+            uint32_t hw[8], mw[8], lw[8];
 #pragma unroll
-            for (int e = 0; e < 16; ++e)
-                if (k0 + e < d) x[e] = (float)((double)a[e] - m);
-        }
-    }
-    const int64_t dst = (kt * n_pad + r) * 16;
-    if constexpr (SCH == SCH_FP32) {
-        float4 *p = (float4 *)((float *)planes + dst);
+            for (int e = 0; e < 16; e += 2) {
+                uint32_t h2[2], m2[2], l2[2];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) p[q] = make_float4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
-    } else {
-        uint32_t hw[8], mw[8], lw[8];
-#pragma unroll
-        for (int e = 0; e < 16; e += 2) {
-            uint32_t h2[2], m2[2], l2[2];
-#pragma unroll
-            for (int f = 0; f < 2; ++f) {
-                h2[f] = bf16_rne(x[e + f]);
-                const float r1 = x[e + f] - bf16_val(h2[f]);
-                m2[f] = bf16_rne(r1);
-                const float r2 = r1 - bf16_val(m2[f]);
-                l2[f] = bf16_rne(r2);
+                for (int f = 0; f < 2; ++f) {
+                    h2[f] = bf16_rne(x[e + f]);
+                    const float r1 = x[e + f] - bf16_val(h2[f]);
+                    m2[f] = bf16_rne(r1);
+                    const float r2 = r1 - bf16_val(m2[f]);
+                    l2[f] = bf16_rne(r2);
+                }
+                hw[e / 2] = h2[0] | (h2[1] << 16);
+                mw[e / 2] = m2[0] | (m2[1] << 16);
+                lw[e / 2] = l2[0] | (l2[1] << 16);
             }
-            hw[e / 2] = h2[0] | (h2[1] << 16);
-            mw[e / 2] = m2[0] | (m2[1] << 16);
-            lw[e / 2] = l2[0] | (l2[1] << 16);
-        }
-        uint4 *p0 = (uint4 *)((uint16_t *)planes + dst);
-        p0[0] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
-        p0[1] = make_uint4(hw[4], hw[5], hw[6], hw[7]);
-        uint4 *p1 = (uint4 *)((uint16_t *)(planes + plane_bytes) + dst);
-        p1[0] = make_uint4(mw[0], mw[1], mw[2], mw[3]);
-        p1[1] = make_uint4(mw[4], mw[5], mw[6], mw[7]);
-        if constexpr (SCH == SCH_X6) {
-            uint4 *p2 = (uint4 *)((uint16_t *)(planes + 2 * plane_bytes) + dst);
-            p2[0] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
-            p2[1] = make_uint4(lw[4], lw[5], lw[6], lw[7]);
+            uint4 *p0 = (uint4 *)((uint16_t *)planes + dst);
+            p0[0] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+            p0[1] = make_uint4(hw[4], hw[5], hw[6], hw[7]);
+            uint4 *p1 = (uint4 *)((uint16_t *)(planes + plane_bytes) + dst);
+            p1[0] = make_uint4(mw[0], mw[1], mw[2], mw[3]);
+            p1[1] = make_uint4(mw[4], mw[5], mw[6], mw[7]);
+            if constexpr (SCH == SCH_X6) {
+                uint4 *p2 = (uint4 *)((uint16_t *)(planes + 2 * plane_bytes) + dst);
+                p2[0] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+                p2[1] = make_uint4(lw[4], lw[5], lw[6], lw[7]);
+            }
         }
     }
 }
@@ -197,162 +203,279 @@ __device__ __forceinline__ int swz(int row)
         return ((row >> 1) ^ (row >> 3)) & 3;
 }
 
+// Wait until at most N vector-memory operations of this wave are outstanding (gfx9
+// s_waitcnt encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4 and lgkmcnt 11:8 left at max).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+typedef __attribute__((address_space(3))) void *lds_ptr_t;
+typedef __attribute__((address_space(1))) void *gbl_ptr_t;
+
 // ------------------------------------------------------------------------------------------
-// Persistent Gram kernel.  256 threads = 4 waves in a 2x2 arrangement; each wave owns a
-// (BM/2) x (BM/2) sub-tile made of 32x32 MFMA blocks.  One stage = a 16-deep K slice of
-// all NC operand planes for both row blocks (A = block bi, B = block bj), copied HBM -> LDS
-// with global_load_lds (no register staging), double buffered.
+// Persistent Gram kernel.  256 threads = 4 waves in a 2x2 arrangement over a BM x BN
+// output block; each wave owns (BM/2) x (BN/2) made of 32x32 MFMA blocks.  One stage = a
+// 16-deep K slice of all NC operand planes for both row blocks (A = BM rows of block bi,
+// B = BN rows of block bj), copied HBM -> LDS with global_load_lds (no register staging)
+// two slices ahead through three LDS buffers, so a copy has two slices of matrix work to
+// land.
 //   bf16:  v_mfma_f32_32x32x16_bf16, lane l holds row l%32, k = 8*(l/32) .. +8
 //   fp32:  v_mfma_f32_32x32x2_f32 x 8 per stage; step s feeds k = s (lanes 0-31) and
 //          k = 8 + s (lanes 32-63), the same permutation for both operands
 // Output block layout (both): acc[r] of lane l is row 8*(r/4) + 4*(l/32) + r%4, col l%32.
 // ------------------------------------------------------------------------------------------
-typedef __attribute__((address_space(3))) void *lds_ptr_t;
-typedef __attribute__((address_space(1))) void *gbl_ptr_t;
-
-template <int BM, int SCH>
-__global__ __launch_bounds__(256, 1) void k_ncc_gram(const char *__restrict__ planes, int64_t plane_bytes,
-                                                     int64_t n_pad, int kt_per_chunk, int nkt, int nchunks,
-                                                     QueueArgs q, float *__restrict__ partial)
+template <int BM, int BN, int SCH>
+__global__ __launch_bounds__(256, 1) void k_ncc_gram(const char *__restrict__ planes,
+                                                                     int64_t plane_bytes, int64_t n_pad,
+                                                                     int kt_per_chunk, int nkt, int nchunks,
+                                                                     QueueArgs q, float *__restrict__ partial)
 {
     constexpr int NC = Scheme<SCH>::NC, ES = Scheme<SCH>::ES;
     constexpr int ROWB = 16 * ES;
     constexpr int SEGS = ROWB / 16;
-    constexpr int TILEB = BM * ROWB;
-    constexpr int STAGEB = 2 * NC * TILEB;
-    constexpr int BLOCKS = STAGEB / 1024;      // 1 KiB wave-copies per stage
-    constexpr int BPW = (BLOCKS + 3) / 4;      // per wave
+    constexpr int TA = BM * ROWB, TB = BN * ROWB;  // bytes of one component, side A / side B
+    constexpr int CSB = TA + TB;                     // bytes of one component, both sides
+    constexpr int STAGEB = NC * CSB;
+    constexpr int BLOCKS = STAGEB / 1024;            // 1 KiB wave-copies per stage
+    constexpr int BPW = BLOCKS / 4;                  // per wave
     constexpr int ROWS_PER_BLOCK = 1024 / ROWB;
-    constexpr int WM = BM / 2;
-    constexpr int MB = WM / 32;
-    static_assert(TILEB % 1024 == 0, "tile side must be a whole number of 1 KiB blocks");
+    constexpr int HALVES = BM / BN;
+    constexpr int WM = BM / 2, WN = BN / 2;
+    constexpr int MA = WM / 32, MBN = WN / 32;
+    // products (A component, B component): h*h, h*m, m*h [, h*l, l*h, m*m]
+    constexpr int NP = SCH == SCH_X6 ? 6 : SCH == SCH_X3 ? 3 : 0;
+    constexpr int PA[6] = {0, 0, 1, 0, 2, 1};
+    constexpr int PB[6] = {0, 1, 0, 2, 0, 1};
+    static_assert(TA % 1024 == 0 && TB % 1024 == 0, "tile sides must be whole 1 KiB blocks");
+    static_assert(BLOCKS % 4 == 0, "every wave issues the same number of copies");
 
-    __shared__ __align__(1024) char lds[2 * STAGEB];
+    // three separately declared stage buffers: slice s is read from one while the copies of
+    // slices s+1 and s+2 land in the others (the compiler can tell them apart and does not
+    // serialise a copy with the fragment reads of another buffer)
+    __shared__ __align__(1024) char lds0[STAGEB];
+    __shared__ __align__(1024) char lds1[STAGEB];
+    __shared__ __align__(1024) char lds2[STAGEB];
     __shared__ int s_item;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
     const int wm = wave >> 1, wn = wave & 1;
-    // this lane's slot inside every 1 KiB block: row and (swizzled) 16-byte segment
+    const int h = lane >> 5;
     const int lrow = lane / SEGS, pseg = lane % SEGS;
 
     for (;;) {
-        const int it = queue_pop_wg(q, &s_item);
+        const int it = __builtin_amdgcn_readfirstlane(queue_pop_wg(q, &s_item));
         if (it < 0) break;
         const int4 w = q.items[it];
-        const int bi = w.x, bj = w.y, kc = w.z, tile = w.w;
+        // slot = tile * HALVES + half; all work-item fields are wave-uniform
+        const int bi = __builtin_amdgcn_readfirstlane(w.x), bj = __builtin_amdgcn_readfirstlane(w.y);
+        const int kc = __builtin_amdgcn_readfirstlane(w.z), slot = __builtin_amdgcn_readfirstlane(w.w);
         const int kt0 = kc * kt_per_chunk;
         const int kt1 = min(kt0 + kt_per_chunk, nkt);
 
-        f32x16 acc[MB][MB];
+        f32x16 acc[MA][MBN];
 #pragma unroll
-        for (int m = 0; m < MB; ++m)
+        for (int m = 0; m < MA; ++m)
 #pragma unroll
-            for (int n = 0; n < MB; ++n)
+            for (int n = 0; n < MBN; ++n)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[m][n][r] = 0.f;
 
-        const int64_t rowA = (int64_t)bi * BM, rowB = (int64_t)bj * BM;
+        const int64_t rowA = (int64_t)bi * BM, rowB = (int64_t)bj * BM + (int64_t)(slot % HALVES) * BN;
 
-        // issue the HBM -> LDS copies of K slice kt into buffer buf
-        auto issue = [&](int kt, int buf) {
+        // Copy of K slice kt into dstbuf: this wave moves 1 KiB blocks wv, wv+4, ...; the
+        // block's source base is wave-uniform (scalar registers), the lane adds its own
+        // 32-bit offset (row within the block, swizzled 16-byte segment).
+        auto issue = [&](int kt, char *dstbuf) {
 #pragma unroll
             for (int c = 0; c < BPW; ++c) {
-                const int b = wave + 4 * c;
-                if (BLOCKS % 4 == 0 || b < BLOCKS) {
-                    const int cs = b / (TILEB / 1024);            // comp * 2 + side
-                    const int rb = (b % (TILEB / 1024)) * ROWS_PER_BLOCK;
-                    const int row = rb + lrow;
-                    const int seg = pseg ^ swz<SEGS>(row);
-                    const int comp = cs >> 1, side = cs & 1;
-                    const char *src = planes + comp * plane_bytes +
-                                      (((int64_t)kt * n_pad + (side ? rowB : rowA) + row) * ROWB) + seg * 16;
-                    __builtin_amdgcn_global_load_lds((gbl_ptr_t)src, (lds_ptr_t)(lds + buf * STAGEB + b * 1024), 16,
-                                                     0, 0);
-                }
+                const int b = wv + 4 * c;
+                const int comp = (b * 1024) / CSB;
+                const int inb = b * 1024 - comp * CSB;  // byte offset inside the component
+                const int side = inb >= TA;
+                const int rb = (side ? inb - TA : inb) / ROWB;
+                const int row = rb + lrow;
+                const int loff = lrow * ROWB + ((pseg ^ swz<SEGS>(row)) * 16);
+                const char *sbase = planes + comp * plane_bytes + (((int64_t)kt * n_pad + (side ? rowB : rowA) + rb) * ROWB);
+                __builtin_amdgcn_global_load_lds((gbl_ptr_t)(sbase + loff), (lds_ptr_t)(dstbuf + b * 1024), 16, 0, 0);
             }
         };
-
-        issue(kt0, 0);
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        for (int kt = kt0; kt < kt1; ++kt) {
-            const int buf = (kt - kt0) & 1;
-            const char *base = lds + buf * STAGEB;
-            const int h = lane >> 5;
+        // one 16-deep K slice from `base`; the copy of slice kt + 2 into `nbuf` starts first
+        auto stage = [&](int kt, const char *base, char *nbuf) {
+            const bool ahead2 = kt + 2 < kt1;
+            if (ahead2) issue(kt + 2, nbuf);
             if constexpr (SCH == SCH_FP32) {
-                float fa[MB][8], fb[MB][8];
+                float fa[MA][8], fb[MBN][8];
 #pragma unroll
-                for (int m = 0; m < MB; ++m) {
+                for (int m = 0; m < MA; ++m) {
                     const int ra = wm * WM + m * 32 + (lane & 31);
-                    const int rb = wn * WM + m * 32 + (lane & 31);
                     const char *pa = base + ra * ROWB;
-                    const char *pb = base + TILEB + rb * ROWB;
                     const float4 a0 = *(const float4 *)(pa + (((2 * h) ^ swz<SEGS>(ra)) * 16));
                     const float4 a1 = *(const float4 *)(pa + (((2 * h + 1) ^ swz<SEGS>(ra)) * 16));
-                    const float4 b0 = *(const float4 *)(pb + (((2 * h) ^ swz<SEGS>(rb)) * 16));
-                    const float4 b1 = *(const float4 *)(pb + (((2 * h + 1) ^ swz<SEGS>(rb)) * 16));
                     fa[m][0] = a0.x; fa[m][1] = a0.y; fa[m][2] = a0.z; fa[m][3] = a0.w;
                     fa[m][4] = a1.x; fa[m][5] = a1.y; fa[m][6] = a1.z; fa[m][7] = a1.w;
-                    fb[m][0] = b0.x; fb[m][1] = b0.y; fb[m][2] = b0.z; fb[m][3] = b0.w;
-                    fb[m][4] = b1.x; fb[m][5] = b1.y; fb[m][6] = b1.z; fb[m][7] = b1.w;
                 }
-                // fragments are in registers: the next slice may now stream into the other buffer
-                if (kt + 1 < kt1) issue(kt + 1, buf ^ 1);
 #pragma unroll
-                for (int s = 0; s < 8; ++s)
+                for (int n = 0; n < MBN; ++n) {
+                    const int rb = wn * WN + n * 32 + (lane & 31);
+                    const char *pb = base + TA + rb * ROWB;
+                    const float4 b0 = *(const float4 *)(pb + (((2 * h) ^ swz<SEGS>(rb)) * 16));
+                    const float4 b1 = *(const float4 *)(pb + (((2 * h + 1) ^ swz<SEGS>(rb)) * 16));
+                    fb[n][0] = b0.x; fb[n][1] = b0.y; fb[n][2] = b0.z; fb[n][3] = b0.w;
+                    fb[n][4] = b1.x; fb[n][5] = b1.y; fb[n][6] = b1.z; fb[n][7] = b1.w;
+                }
 #pragma unroll
-                    for (int m = 0; m < MB; ++m)
+                for (int ss = 0; ss < 8; ++ss)
 #pragma unroll
-                        for (int n = 0; n < MB; ++n)
-                            acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[m][s], fb[n][s], acc[m][n], 0, 0, 0);
+                    for (int m = 0; m < MA; ++m)
+#pragma unroll
+                        for (int n = 0; n < MBN; ++n)
+                            acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[m][ss], fb[n][ss], acc[m][n], 0, 0, 0);
             } else {
-                bf16x8 fa[NC][MB], fb[NC][MB];
+                bf16x8 fb[NC][MBN];
 #pragma unroll
                 for (int c = 0; c < NC; ++c)
 #pragma unroll
-                    for (int m = 0; m < MB; ++m) {
-                        const int ra = wm * WM + m * 32 + (lane & 31);
-                        const int rb = wn * WM + m * 32 + (lane & 31);
-                        fa[c][m] = *(const bf16x8 *)(base + (2 * c) * TILEB + ra * ROWB + ((h ^ swz<SEGS>(ra)) * 16));
-                        fb[c][m] =
-                            *(const bf16x8 *)(base + (2 * c + 1) * TILEB + rb * ROWB + ((h ^ swz<SEGS>(rb)) * 16));
+                    for (int n = 0; n < MBN; ++n) {
+                        const int rb = wn * WN + n * 32 + (lane & 31);
+                        fb[c][n] = *(const bf16x8 *)(base + c * CSB + TA + rb * ROWB + ((h ^ swz<SEGS>(rb)) * 16));
                     }
-                if (kt + 1 < kt1) issue(kt + 1, buf ^ 1);
                 // products grouped by the A component: h*(h, m[, l]), m*(h[, m]), [l*h]
 #pragma unroll
                 for (int ca = 0; ca < NC; ++ca) {
-                    constexpr int NCB0 = SCH == SCH_X6 ? 3 : 2;
-                    const int ncb = SCH == SCH_X6 ? NC - ca : (ca == 0 ? 2 : 1);
+                    bf16x8 fa[MA];
 #pragma unroll
-                    for (int cb = 0; cb < NCB0; ++cb) {
-                        if (cb < ncb) {
+                    for (int m = 0; m < MA; ++m) {
+                        const int ra = wm * WM + m * 32 + (lane & 31);
+                        fa[m] = *(const bf16x8 *)(base + ca * CSB + ra * ROWB + ((h ^ swz<SEGS>(ra)) * 16));
+                    }
 #pragma unroll
-                            for (int m = 0; m < MB; ++m)
+                    for (int p = 0; p < NP; ++p) {
+                        if (PA[p] != ca) continue;
 #pragma unroll
-                                for (int n = 0; n < MB; ++n)
-                                    acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[ca][m], fb[cb][n],
-                                                                                        acc[m][n], 0, 0, 0);
-                        }
+                        for (int m = 0; m < MA; ++m)
+#pragma unroll
+                            for (int n = 0; n < MBN; ++n)
+                                acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[m], fb[PB[p]][n], acc[m][n], 0,
+                                                                                    0, 0);
                     }
                 }
             }
-            // keep every MFMA of this slice ahead of the wait: the copy of the next slice
-            // then overlaps the whole slice's matrix work
+            // every MFMA of this slice stays ahead of the wait; the wait needs only the copy
+            // of slice kt + 1 (issued one slice earlier), the copy of kt + 2 may stay in flight
             __builtin_amdgcn_sched_barrier(0);
-            __builtin_amdgcn_s_waitcnt(0);
+            if (ahead2)
+                wait_vmcnt<BPW>();
+            else
+                wait_vmcnt<0>();
             __syncthreads();
+        };
+
+        if constexpr (SCH == SCH_FP32) {
+            issue(kt0, lds0);
+            if (kt0 + 1 < kt1) {
+                issue(kt0 + 1, lds1);
+                wait_vmcnt<BPW>();
+            } else {
+                wait_vmcnt<0>();
+            }
+            __syncthreads();
+            for (int kt = kt0; kt < kt1; kt += 3) {
+                stage(kt, lds0, lds2);
+                if (kt + 1 < kt1) stage(kt + 1, lds1, lds0);
+                if (kt + 2 < kt1) stage(kt + 2, lds2, lds1);
+            }
+        } else {
+            // Split-phase pipeline.  The B fragments and the h fragments of A for slice s are
+            // already in registers when slice s starts; its m (and l) fragments of A are read
+            // at the start and used in the second half.  Between the halves every wave waits
+            // for its copy of slice s+1, one barrier publishes all copies, and the B and h
+            // fragments of s+1 are read while the second half of the MFMAs of s runs.
+            bf16x8 fbA[NC][MBN], faA[MA], fbB[NC][MBN], faB[MA];
+            auto frag_a = [&](bf16x8 (&fa)[MA], const char *base, int c) {
+#pragma unroll
+                for (int m = 0; m < MA; ++m) {
+                    const int ra = wm * WM + m * 32 + (lane & 31);
+                    fa[m] = *(const bf16x8 *)(base + c * CSB + ra * ROWB + ((h ^ swz<SEGS>(ra)) * 16));
+                }
+            };
+            auto frag_b = [&](bf16x8 (&fb)[NC][MBN], const char *base) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+#pragma unroll
+                    for (int n = 0; n < MBN; ++n) {
+                        const int rb = wn * WN + n * 32 + (lane & 31);
+                        fb[c][n] = *(const bf16x8 *)(base + c * CSB + TA + rb * ROWB + ((h ^ swz<SEGS>(rb)) * 16));
+                    }
+            };
+            auto mfma_row = [&](const bf16x8 (&fa)[MA], const bf16x8 (&fbc)[MBN]) {
+#pragma unroll
+                for (int m = 0; m < MA; ++m)
+#pragma unroll
+                    for (int n = 0; n < MBN; ++n)
+                        acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[m], fbc[n], acc[m][n], 0, 0, 0);
+            };
+            auto pstage = [&](int kt, const char *cur, const char *nxt, char *dma, bf16x8 (&fbc)[NC][MBN],
+                              bf16x8 (&fa0c)[MA], bf16x8 (&fbn)[NC][MBN], bf16x8 (&fa0n)[MA]) {
+                bf16x8 fa1[MA], fa2[MA];
+                frag_a(fa1, cur, 1);
+                if constexpr (NC == 3) frag_a(fa2, cur, 2);
+                const bool ahead1 = kt + 1 < kt1, ahead2 = kt + 2 < kt1;
+                if (ahead2) issue(kt + 2, dma);
+                // first half: h x (h, m[, l])
+                mfma_row(fa0c, fbc[0]);
+                mfma_row(fa0c, fbc[1]);
+                if constexpr (NC == 3) mfma_row(fa0c, fbc[2]);
+                if (ahead1) {
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (ahead2)
+                        wait_vmcnt<BPW>();
+                    else
+                        wait_vmcnt<0>();
+                    __syncthreads();
+                    frag_b(fbn, nxt);
+                    frag_a(fa0n, nxt, 0);
+                }
+                // second half: m x (h[, m]) [, l x h]
+                mfma_row(fa1, fbc[0]);
+                if constexpr (NC == 3) {
+                    mfma_row(fa1, fbc[1]);
+                    mfma_row(fa2, fbc[0]);
+                }
+            };
+            issue(kt0, lds0);
+            if (kt0 + 1 < kt1) {
+                issue(kt0 + 1, lds1);
+                wait_vmcnt<BPW>();
+            } else {
+                wait_vmcnt<0>();
+            }
+            __syncthreads();
+            frag_b(fbA, lds0);
+            frag_a(faA, lds0, 0);
+            for (int kt = kt0; kt < kt1; kt += 6) {
+                pstage(kt, lds0, lds1, lds2, fbA, faA, fbB, faB);
+                if (kt + 1 < kt1) pstage(kt + 1, lds1, lds2, lds0, fbB, faB, fbA, faA);
+                if (kt + 2 < kt1) pstage(kt + 2, lds2, lds0, lds1, fbA, faA, fbB, faB);
+                if (kt + 3 < kt1) pstage(kt + 3, lds0, lds1, lds2, fbB, faB, fbA, faA);
+                if (kt + 4 < kt1) pstage(kt + 4, lds1, lds2, lds0, fbA, faA, fbB, faB);
+                if (kt + 5 < kt1) pstage(kt + 5, lds2, lds0, lds1, fbB, faB, fbA, faA);
+            }
         }
 
-        // partial tile in MFMA-native order: float4 chunk ((m*MB + n)*4 + q)*256 + tid holds
+        // partial block in MFMA-native order: float4 chunk ((m*MBN + n)*4 + q)*256 + tid holds
         // acc[m][n][4q .. 4q+3] of this thread (four consecutive rows, one column)
-        float4 *P = (float4 *)(partial + ((int64_t)tile * nchunks + kc) * (int64_t)BM * BM) + tid;
+        float4 *P = (float4 *)(partial + ((int64_t)slot * nchunks + kc) * (int64_t)BM * BN) + tid;
 #pragma unroll
-        for (int m = 0; m < MB; ++m)
+        for (int m = 0; m < MA; ++m)
 #pragma unroll
-            for (int n = 0; n < MB; ++n)
+            for (int n = 0; n < MBN; ++n)
 #pragma unroll
                 for (int qq = 0; qq < 4; ++qq)
-                    P[((m * MB + n) * 4 + qq) * 256] =
+                    P[((m * MBN + n) * 4 + qq) * 256] =
                         make_float4(acc[m][n][4 * qq], acc[m][n][4 * qq + 1], acc[m][n][4 * qq + 2], acc[m][n][4 * qq + 3]);
     }
 }
@@ -362,32 +485,33 @@ __global__ __launch_bounds__(256, 1) void k_ncc_gram(const char *__restrict__ pl
 // ascending order.  One thread per float4 of the MFMA-native partial layout (four rows of
 // one column), so partial reads are 16-byte coalesced and output writes are 128-byte runs.
 // ------------------------------------------------------------------------------------------
-template <int BM>
+template <int BM, int BN>
 __global__ __launch_bounds__(256) void k_ncc_finish(const float *__restrict__ partial, const int2 *__restrict__ tiles,
                                                     int nchunks, int64_t n, const float *__restrict__ inv_s,
                                                     float *__restrict__ out)
 {
-    constexpr int BPT = BM * BM / 4 / 256;  // workgroups per tile
-    constexpr int WM = BM / 2, MB = WM / 32;
-    const int64_t tile = blockIdx.x / BPT;
-    const int t = (int)(blockIdx.x % BPT) * 256 + threadIdx.x;  // float4 index in the tile
+    constexpr int BPB = BM * BN / 4 / 256;  // workgroups per output block
+    constexpr int HALVES = BM / BN;
+    constexpr int WM = BM / 2, WN = BN / 2, MBN = WN / 32;
+    const int64_t slot = blockIdx.x / BPB;
+    const int t = (int)(blockIdx.x % BPB) * 256 + threadIdx.x;  // float4 index in the block
     const int tid = t & 255, lane = tid & 63, wave = tid >> 6;
     const int qq = (t >> 8) & 3, mn = t >> 10;
-    const int m = mn / MB, nn = mn % MB;
+    const int m = mn / MBN, nn = mn % MBN;
     const int row0 = (wave >> 1) * WM + m * 32 + 8 * qq + 4 * (lane >> 5);
-    const int col = (wave & 1) * WM + nn * 32 + (lane & 31);
-    const int2 tl = tiles[tile];
-    const int64_t j = (int64_t)tl.y * BM + col;
+    const int col = (wave & 1) * WN + nn * 32 + (lane & 31);
+    const int2 tl = tiles[slot / HALVES];
+    const int64_t j = (int64_t)tl.y * BM + (slot % HALVES) * BN + col;
     const int64_t i0 = (int64_t)tl.x * BM + row0;
     if (j >= n || i0 >= j) return;
-    const float4 *p = (const float4 *)(partial + tile * nchunks * (int64_t)BM * BM) + t;
+    const float4 *p = (const float4 *)(partial + slot * nchunks * (int64_t)BM * BN) + t;
     // fixed order: groups of 16 consecutive chunks, then the group sums
     float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int k0 = 0; k0 < nchunks; k0 += 16) {
-        float4 g = p[(int64_t)k0 * (BM * BM / 4)];
+        float4 g = p[(int64_t)k0 * (BM * BN / 4)];
         const int k1 = min(nchunks, k0 + 16);
         for (int k = k0 + 1; k < k1; ++k) {
-            const float4 v = p[(int64_t)k * (BM * BM / 4)];
+            const float4 v = p[(int64_t)k * (BM * BN / 4)];
             g.x += v.x;
             g.y += v.y;
             g.z += v.z;
@@ -407,10 +531,16 @@ __global__ __launch_bounds__(256) void k_ncc_finish(const float *__restrict__ pa
     }
 }
 
+template <int BM>
+constexpr int bn_of()
+{
+    return BM;
+}
+
 template <int BM, int SCH>
 const void *gram_ptr()
 {
-    return (const void *)&k_ncc_gram<BM, SCH>;
+    return (const void *)&k_ncc_gram<BM, bn_of<BM>(), SCH>;
 }
 
 template <int SCH>
@@ -471,7 +601,8 @@ rocket_status ncc_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, in
     kc = std::min<int64_t>(kc, st.d_pad);
     st.kt_per_chunk = (int)(kc / 16);
     st.nchunks = (int)((st.nkt + st.kt_per_chunk - 1) / st.kt_per_chunk);
-    st.items = st.tiles * st.nchunks;
+    const int halves = 1;  // column slices per tile (the kernels use square blocks)
+    st.items = st.tiles * halves * st.nchunks;
     ctx->stats.tiles = st.tiles;
     ctx->stats.work_items = st.items;
     ctx->stats.tile = bm;
@@ -483,7 +614,7 @@ rocket_status ncc_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, in
                   ledger = ctx->opt[ROCKET_OPT_LEDGER];
     if (st.tiles > 0 &&
         (pc.pc_nchunks != st.nchunks || pc.pc_order != order || pc.pc_seed != seed || pc.pc_ledger != ledger)) {
-        plan_chunked(pc.h_tiles, st.nchunks, MAX_SEG, ctx->h_items, ctx->h_seg);
+        plan_chunked(pc.h_tiles, st.nchunks, MAX_SEG, ctx->h_items, ctx->h_seg, halves);
         if (order == 1) shuffle_items(ctx->h_items, ctx->h_seg, (uint64_t)seed);
         if (order == 2) single_segment(ctx->h_seg, (int64_t)ctx->h_items.size());
         RK_TRY(upload_queue(ctx, s, &pc.qa));
@@ -507,16 +638,16 @@ rocket_status ncc_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, in
     float *inv_s = (float *)((char *)stats + (((size_t)n * 8 + 255) & ~(size_t)255));
     hipLaunchKernelGGL(k_ncc_stats, dim3((unsigned)n), dim3(256), 0, s, it->dense, it->ld, it->dim, mu, inv_s);
     RK_HIP(hipGetLastError());
-    const dim3 g((unsigned)st.nkt, (unsigned)((st.n_pad + 255) / 256));
+    const dim3 g((unsigned)((st.nkt + 3) / 4), (unsigned)((st.n_pad + 255) / 256));
     if (scheme == SCH_FP32)
         hipLaunchKernelGGL(k_ncc_split<SCH_FP32>, g, dim3(256), 0, s, it->dense, it->ld, it->dim, n, mu, st.n_pad,
-                           st.d_pad, (char *)planes, plane_bytes);
+                           (int64_t)st.nkt, (char *)planes, plane_bytes);
     else if (scheme == SCH_X3)
         hipLaunchKernelGGL(k_ncc_split<SCH_X3>, g, dim3(256), 0, s, it->dense, it->ld, it->dim, n, mu, st.n_pad,
-                           st.d_pad, (char *)planes, plane_bytes);
+                           (int64_t)st.nkt, (char *)planes, plane_bytes);
     else
         hipLaunchKernelGGL(k_ncc_split<SCH_X6>, g, dim3(256), 0, s, it->dense, it->ld, it->dim, n, mu, st.n_pad,
-                           st.d_pad, (char *)planes, plane_bytes);
+                           (int64_t)st.nkt, (char *)planes, plane_bytes);
     RK_HIP(hipGetLastError());
     return ROCKET_OK;
 }
@@ -525,7 +656,7 @@ template <int BM, int SCH>
 static void launch_gram(int grid, hipStream_t s, const char *planes, int64_t pb, const NccState &st,
                         const QueueArgs &qa, float *partial)
 {
-    hipLaunchKernelGGL((k_ncc_gram<BM, SCH>), dim3(grid), dim3(256), 0, s, planes, pb, st.n_pad, st.kt_per_chunk,
+    hipLaunchKernelGGL((k_ncc_gram<BM, bn_of<BM>(), SCH>), dim3(grid), dim3(256), 0, s, planes, pb, st.n_pad, st.kt_per_chunk,
                        st.nkt, st.nchunks, qa, partial);
 }
 
@@ -549,7 +680,8 @@ rocket_status ncc_compare(rocket_ctx *ctx, float *out, hipStream_t s)
     const NccState &pc = st;
     const int bm = st.tile;
     void *partial = nullptr;
-    RK_TRY(ws_get(ctx, WS_NCC_PARTIAL, (size_t)(st.items * bm * bm * 4), &partial));
+    const int bn = bm;
+    RK_TRY(ws_get(ctx, WS_NCC_PARTIAL, (size_t)(st.items * bm * bn * 4), &partial));
     RK_TRY(reset_queue(ctx, s, pc.qa));
     const int grid = auto_grid(ctx, gram_kernel(bm, st.scheme), 256, 0, st.items);
     ctx->stats.grid = grid;
@@ -566,15 +698,15 @@ rocket_status ncc_compare(rocket_ctx *ctx, float *out, hipStream_t s)
     RK_TRY(timing_end(ctx, s));
     const float *inv_s = (const float *)((char *)ctx->ws[WS_NCC_STATS].ptr + (((size_t)st.n * 8 + 255) & ~(size_t)255));
     const int2 *tiles = (const int2 *)ctx->ws[WS_NCC_TILES].ptr;
-    const int64_t blocks = st.tiles * (int64_t)bm * bm / 1024;
+    const int64_t blocks = st.tiles * (int64_t)bm * bm / 1024;  // every slice of every tile
     if (bm == 64)
-        hipLaunchKernelGGL(k_ncc_finish<64>, dim3((unsigned)blocks), dim3(256), 0, s, (const float *)partial, tiles,
+        hipLaunchKernelGGL((k_ncc_finish<64, 64>), dim3((unsigned)blocks), dim3(256), 0, s, (const float *)partial, tiles,
                            st.nchunks, st.n, inv_s, out);
     else if (bm == 128)
-        hipLaunchKernelGGL(k_ncc_finish<128>, dim3((unsigned)blocks), dim3(256), 0, s, (const float *)partial, tiles,
+        hipLaunchKernelGGL((k_ncc_finish<128, 128>), dim3((unsigned)blocks), dim3(256), 0, s, (const float *)partial, tiles,
                            st.nchunks, st.n, inv_s, out);
     else
-        hipLaunchKernelGGL(k_ncc_finish<256>, dim3((unsigned)blocks), dim3(256), 0, s, (const float *)partial, tiles,
+        hipLaunchKernelGGL((k_ncc_finish<256, 256>), dim3((unsigned)blocks), dim3(256), 0, s, (const float *)partial, tiles,
                            st.nchunks, st.n, inv_s, out);
     RK_HIP(hipGetLastError());
     return ROCKET_OK;

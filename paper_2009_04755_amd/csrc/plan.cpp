@@ -53,17 +53,19 @@ void plan_leaves(int64_t n, int64_t T, std::vector<int2> &out)
 // operands stay in the shared last-level cache); within a chunk the D&C leaf list is
 // cut into nseg contiguous pieces, piece x feeding segment x (one per XCD), so that
 // the workgroups of one XCD share item blocks through that XCD's L2.
+// A tile may be processed as `halves` column slices (item .w = tile * halves + slice).
 void plan_chunked(const std::vector<int2> &tiles, int nchunks, int nseg, std::vector<int4> &items,
-                  std::vector<int> &seg)
+                  std::vector<int> &seg, int halves)
 {
-    const int64_t nt = (int64_t)tiles.size();
+    const int64_t nt = (int64_t)tiles.size() * halves;
     items.clear();
     items.reserve((size_t)(nt * nchunks));
     seg.assign((size_t)nseg + 1, 0);
     for (int s = 0; s < nseg; ++s) {
         const int64_t t0 = nt * s / nseg, t1 = nt * (s + 1) / nseg;
         for (int c = 0; c < nchunks; ++c)
-            for (int64_t t = t0; t < t1; ++t) items.push_back(make_int4(tiles[t].x, tiles[t].y, c, (int)t));
+            for (int64_t t = t0; t < t1; ++t)
+                items.push_back(make_int4(tiles[t / halves].x, tiles[t / halves].y, c, (int)t));
         seg[s + 1] = (int)items.size();
     }
 }

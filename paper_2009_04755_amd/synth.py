@@ -207,3 +207,60 @@ def sparse_vectors(n: int, key_space: int = 20 ** 6, zipf_a: float = 1.1, nnz_me
         keys[a:b] = k[order]
         vals[a:b] = (cnt[order].astype(np.float64) / float(draws.size)).astype(np.float32)
     return offsets, keys, vals
+
+
+def sparse_vectors_device(n: int, key_space: int = 20 ** 6, zipf_a: float = 1.1, nnz_mean: float = 200_000,
+                          nnz_min: int = 20_000, nnz_max: int = 1_000_000, sigma_ln: float = 1.0, seed: int = 0,
+                          device="cuda"):
+    """Device-side version of :func:`sparse_vectors` for multi-GB sets (same recipe).
+
+    nnz and the key bijection come from the host PCG64 stream; Zipf ranks are drawn on the
+    device by inverse-CDF lookup in the truncated distribution's FP64 CDF, from a seeded
+    ``torch.Generator``.  Returns device tensors ``(offsets int64[n+1], keys int64[total],
+    vals f32[total])``.
+    """
+    import torch
+
+    g = rng(4, 1000 + seed)
+    mu = np.log(nnz_mean) - 0.5 * sigma_ln ** 2
+    nnz = np.clip(np.rint(g.lognormal(mu, sigma_ln, n)), nnz_min, nnz_max).astype(np.int64)
+    nnz = np.minimum(nnz, key_space)
+    while True:
+        mult = int(g.integers(1, key_space))
+        if np.gcd(mult, key_space) == 1:
+            break
+    add = int(g.integers(0, key_space))
+    tg = torch.Generator(device=device)
+    tg.manual_seed(SEED_BASE * 1000 + 4000 + int(seed))
+    ranks = torch.arange(1, key_space + 1, device=device, dtype=torch.float64)
+    cdf = torch.cumsum(ranks.pow_(-zipf_a), 0)
+    cdf /= cdf[-1].clone()
+    del ranks
+    offsets = np.zeros(n + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum(nnz)
+    keys = torch.empty(int(offsets[-1]), dtype=torch.int64, device=device)
+    vals = torch.empty(int(offsets[-1]), dtype=torch.float32, device=device)
+    for i in range(n):
+        want = int(nnz[i])
+        draws = torch.empty(0, dtype=torch.int64, device=device)
+        batch = 6 * want + 4096
+        while True:
+            u = torch.rand(batch, generator=tg, device=device, dtype=torch.float64)
+            r = torch.searchsorted(cdf, u).clamp_(max=key_space - 1)  # rank - 1
+            draws = torch.cat([draws, r])
+            uniq, inv = torch.unique(draws, return_inverse=True)
+            if uniq.numel() >= want:
+                pos = torch.arange(draws.numel(), device=device)
+                first = torch.full((uniq.numel(),), draws.numel(), dtype=torch.int64, device=device)
+                first.scatter_reduce_(0, inv, pos, reduce="amin")
+                cut = int(torch.kthvalue(first, want).values)
+                draws = draws[: cut + 1]
+                break
+            batch *= 2
+        rk, cnt = torch.unique(draws, return_counts=True)
+        k = (mult * rk + add) % key_space
+        order = torch.argsort(k)
+        a, b = int(offsets[i]), int(offsets[i + 1])
+        keys[a:b] = k[order]
+        vals[a:b] = (cnt[order].to(torch.float64) / float(draws.numel())).to(torch.float32)
+    return torch.from_numpy(offsets).to(device), keys, vals
