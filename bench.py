@@ -112,8 +112,9 @@ def cpu_baseline(X, out, n, budget_s=15.0):
             {"pairs": int(m), "max_floored_rel_err": float(err.max())})
 
 
-def other_pair_fns(ctx):
-    """Gaussian overlap (2048 uneven clouds), its 20-step registration, one line each."""
+def other_pair_fns(ctx, with_cpu=True):
+    """Gaussian overlap (2048 uneven clouds), the two per-point-sigma scores and the
+    20-step registration, one entry each."""
     import numpy as np
     import torch
     from paper_2009_04755_amd import Clouds, register, synth
@@ -133,6 +134,37 @@ def other_pair_fns(ctx):
                             "kernel_ms": kern * 1e3, "terms_per_s": terms / kern,
                             "roofline": {"bound": "alu", "achieved": terms / kern, "peak": peak_terms,
                                          "unit": "terms/s", "frac": terms / kern / peak_terms}}
+    if with_cpu:
+        import oracle
+        g = np.random.default_rng(5)
+        pi = g.integers(0, 2047, 3000)
+        pj = np.minimum(2047, pi + 1 + g.integers(0, 2047, 3000) % (2047 - pi))
+        t0 = time.perf_counter()
+        oracle.overlap(off, xy, pi, pj, 0.02)
+        dto = time.perf_counter() - t0
+        res["gauss_overlap"]["cpu_baseline"] = {"value": pi.size / dto, "unit": "pairs/s", "cores": oracle.num_threads(),
+                                                "kind": "oracle", "sample": "3000 random pairs of the 2048 clouds"}
+    # per-localisation-uncertainty scores on the same clouds, sigma_k ~ U[0.01, 0.03]
+    sig = synth.point_sigmas(off)
+    clg = Clouds(cl.offsets, cl.xy, 0.02, torch.from_numpy(sig).cuda())
+    for fn, mode, slots in (("gmm_l2", "l2", 14.0), ("gmm_bhattacharya", "bhattacharya", 15.0)):
+        # per term: 2 sub, mul, fma, fma, mul, fma (+ one mul for Bhattacharya) VALU, rcp + exp2 (4 slots each)
+        dtg, kg = _time_fn(ctx, clg, fn, out, 5, 1)
+        peak_g = VALU_LANE_OPS / slots
+        res[fn] = {"workload": "2048 clouds, 50..400 points, per-point sigma U[0.01, 0.03]",
+                   "pairs_per_s": 5 * P / dtg, "kernel_ms": kg * 1e3, "terms_per_s": terms / kg,
+                   "roofline": {"bound": "alu", "achieved": terms / kg, "peak": peak_g, "unit": "terms/s",
+                                "frac": terms / kg / peak_g}}
+        if with_cpu:
+            import oracle
+            g = np.random.default_rng(6)
+            pi = g.integers(0, 2047, 2000)
+            pj = np.minimum(2047, pi + 1 + g.integers(0, 2047, 2000) % (2047 - pi))
+            t0 = time.perf_counter()
+            oracle.gmm(off, xy, sig, pi, pj, mode)
+            dto = time.perf_counter() - t0
+            res[fn]["cpu_baseline"] = {"value": pi.size / dto, "unit": "pairs/s", "cores": oracle.num_threads(),
+                                       "kind": "oracle", "sample": "2000 random pairs of the 2048 clouds"}
     cen = torch.from_numpy(synth.cloud_centroids(off, xy)).cuda()
     p0 = torch.from_numpy(synth.rigid_starts(P, config=3)).cuda()
     register(cl, cen, p0, steps=1, ctx=ctx)
@@ -147,6 +179,53 @@ def other_pair_fns(ctx):
                                     "pair_steps_per_s": 20 * P / dt, "kernel_ms": kern * 1e3,
                                     "roofline": {"bound": "alu", "achieved": terms / kern, "peak": peak_g,
                                                  "unit": "terms/s", "frac": terms / kern / peak_g}}
+    return res
+
+
+def sparse_pair_fn(ctx, with_cpu=True):
+    """Sparse cosine over 8192 composition-vector-like items (about 1.56e9 entries)."""
+    import numpy as np
+    import torch
+    from paper_2009_04755_amd import SparseSet, synth
+
+    off, keys, vals = synth.sparse_vectors_device(8192, seed=0, device="cuda")
+    S = SparseSet(off, keys, vals)
+    n = 8192
+    P = n * (n - 1) // 2
+    out = torch.empty(P, device="cuda")
+    ctx.prepare(S, "sparse_cosine")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.compare(out=out)
+    kern = ctx.stats()["kernel_ns"] * 1e-9
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    # streamed bytes: every (16-item band, 128-item column block) work item reads the u32 keys
+    # and f32 values of its 16 rows and 128 columns once
+    nnz = np.sort(np.diff(off.cpu().numpy()))[::-1].astype(np.float64)
+    band = np.add.reduceat(nnz, np.arange(0, n, 16))
+    blk = np.add.reduceat(nnz, np.arange(0, n, 128))
+    byts = 0.0
+    for b in range(band.size):
+        for c in range(blk.size):
+            if b * 16 < min(n, (c + 1) * 128) - 1:
+                byts += 8.0 * (band[b] + blk[c])
+    res = {"workload": "8192 sparse vectors over 20^6 keys, lognormal nnz (mean 2e5), Zipf(1.1) keys",
+           "entries": int(nnz.sum()), "pairs_per_s": P / dt, "kernel_ms": kern * 1e3,
+           "roofline": {"bound": "hbm", "achieved": byts / kern / 1e9, "peak": PEAK_HBM, "unit": "GB/s",
+                        "frac": byts / kern / 1e9 / PEAK_HBM, "algorithmic_bytes_per_launch": byts}}
+    if with_cpu:
+        import oracle
+        m = 24  # all pairs among the first 24 items
+        offh = off.cpu().numpy()
+        e = int(offh[m])
+        kh, vh = keys[:e].cpu().numpy(), vals[:e].cpu().numpy()
+        pi, pj = oracle.all_pairs(m)
+        t0 = time.perf_counter()
+        oracle.sparse_cosine(offh[: m + 1], kh, vh, pi, pj)
+        dto = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": pi.size / dto, "unit": "pairs/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "sample": "all 276 pairs among the first 24 items"}
     return res
 
 
@@ -222,7 +301,8 @@ def main():
     if not args.no_extras:
         del X
         torch.cuda.empty_cache()
-        rec["pair_fns"] = other_pair_fns(ctx)
+        rec["pair_fns"] = other_pair_fns(ctx, not args.no_cpu_baseline)
+        rec["pair_fns"]["sparse_cosine"] = sparse_pair_fn(ctx, not args.no_cpu_baseline)
     print(json.dumps(rec))
     sys.stdout.flush()
 

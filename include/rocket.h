@@ -21,6 +21,8 @@
  *   ROCKET_GAUSS_OVERLAP  Gaussian-mixture overlap of 2-D point clouds (V-C);
  *   ROCKET_SPARSE_COSINE  cosine of sparse key/value vectors plus the exact size
  *                         of the key intersection (V-B);
+ *   ROCKET_GMM_L2, ROCKET_GMM_BHATTACHARYA  the two particle scores of V-C for
+ *                         clouds whose points carry their own uncertainty;
  * and rocket_overlap_cost_grad gives the overlap cost's gradient with respect to a
  * rigid transform per pair (the registration optimiser of V-C).
  *
@@ -90,7 +92,20 @@ typedef enum {
     /* Sparse cosine (Section V-B): cos_ij = sum_{k in K_i & K_j} v_ik v_jk / (|v_i| |v_j|),
      * norms over all entries of an item (FP64 reduction).  out_counts, when given,
      * receives |K_i & K_j| exactly.  A zero-norm item gives NaN; m_ij = 0 gives 0. */
-    ROCKET_SPARSE_COSINE = 5
+    ROCKET_SPARSE_COSINE = 5,
+    /* Per-localisation-uncertainty scores (Section V-C names the GMM L2 distance and the
+     * Bhattacharya distance between particles).  Point k of cloud i is the isotropic
+     * Gaussian N(x_k, s_k^2 I), point l of cloud j is N(y_l, t_l^2 I); v = s_k^2 + t_l^2,
+     * D = |x_k - y_l|^2.
+     *   GMM_L2:            sum_kl exp(-D / (2 v)) / (2 pi v), the cross term
+     *                      integral of f_i f_j of the L2 distance between the mixtures;
+     *   GMM_BHATTACHARYA:  sum_kl (2 s_k t_l / v) exp(-D / (4 v)), the sum of the
+     *                      components' Bhattacharya coefficients.
+     * FP32 with one reciprocal and one exp2 per term.  Deviations come from
+     * point_sigma and must lie in [1e-18, 1e18] (checked in rocket_prepare, else
+     * ROCKET_E_INVALID); the scalar sigma is ignored.  An empty cloud gives 0. */
+    ROCKET_GMM_L2 = 6,
+    ROCKET_GMM_BHATTACHARYA = 7
 } rocket_pair_fn;
 
 /* The item set.  Which fields are read depends on the pair function; unused
@@ -110,6 +125,8 @@ typedef struct {
      * [0, 2^32 - 1); float32 values [offsets[n]]. */
     const int64_t *keys;
     const float *vals;
+    /* GMM scores: float32 standard deviation per point, [offsets[n]], same order as xy. */
+    const float *point_sigma;
 } rocket_items;
 
 typedef struct rocket_ctx rocket_ctx;
@@ -170,7 +187,8 @@ typedef enum {
     ROCKET_OPT_SEED = 5,            /* seed for the shuffled queue order */
     ROCKET_OPT_LEDGER = 6,          /* 1: record how often each work item is popped (rocket_get_ledger) */
     ROCKET_OPT_OVL_BLOCK = 7,       /* overlap: clouds per block of the tile grid */
-    ROCKET_OPT_OVL_VARIANT = 8,     /* overlap: inner-loop variant 1..3 (lanes per cloud chunk) */
+    ROCKET_OPT_OVL_VARIANT = 8,     /* overlap: inner-loop variant 1..4: lanes x points per lane of cloud j =
+                                       64x1, 32x2, 16x2, 16x4 */
     ROCKET_OPT_SP_ROWS = 9,         /* sparse: items per row band */
     ROCKET_OPT_SP_CHUNK = 10,       /* sparse: key-range chunk width (power of two) */
     ROCKET_OPT_WORKSPACE_CAP = 11,  /* bytes; workspace growth beyond it fails with ROCKET_E_OOM */
@@ -203,9 +221,10 @@ rocket_status rocket_get_stats(const rocket_ctx *ctx, rocket_stats *out /* host 
  * [cap]; *count receives the number of work items.  Synchronises the device. */
 rocket_status rocket_get_ledger(rocket_ctx *ctx, int32_t *out /* host */, int64_t cap, int64_t *count /* host */);
 
-/* Autotuner (ragged pair functions): time candidate tile shapes on a subsample of
- * the prepared set's tiles and keep the fastest in the context (synchronises).
- * The chosen values are readable through rocket_get_option. */
+/* Autotuner (cloud pair functions): time every candidate (block size, inner-loop
+ * variant) on the whole prepared set and keep the fastest in the context
+ * (synchronises; allocates one scratch output).  The chosen values are readable
+ * through rocket_get_option.  A no-op for the dense and sparse functions. */
 rocket_status rocket_autotune(rocket_ctx *ctx, void *stream);
 
 /* Host-only planner, no device needed: the divide-and-conquer leaves for n items

@@ -47,6 +47,7 @@ def lib():
         L.oracle_overlap_pairs.argtypes = [P, P, D, P, P, I64, P, P]
         L.oracle_overlap_grad_pairs.argtypes = [P, P, P, D, P, P, P, I64, P, P, P, P]
         L.oracle_sparse_pairs.argtypes = [P, P, P, P, P, I64, P, P, P]
+        L.oracle_gmm_pairs.argtypes = [P, P, P, ctypes.c_int, P, P, I64, P, P]
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -125,6 +126,22 @@ def overlap_grad(offsets, xy, centroids, pi, pj, params, sigma: float = 0.02):
     lib().oracle_overlap_grad_pairs(_p(xy), _p(offsets), _p(cen), float(sigma), _p(pi), _p(pj), _p(params),
                                     pi.size, _p(cost), _p(grad), _p(tau), _p(kappa))
     return cost, grad, tau, kappa
+
+
+def gmm(offsets, xy, sig, pi, pj, mode: str = "l2", with_kappa: bool = False):
+    """Per-localisation-uncertainty mixture score for the listed pairs: ``mode='l2'`` is the
+    L2 cross term sum N(x_k - y_l; 0, (s_k^2 + t_l^2) I), ``'bhattacharya'`` the sum of the
+    components' Bhattacharya coefficients.  With ``with_kappa`` also the cost-weighted mean
+    exponent of each pair."""
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    xy = np.ascontiguousarray(xy, dtype=np.float32)
+    sig = np.ascontiguousarray(sig, dtype=np.float32)
+    pi, pj = _pairs(pi, pj)
+    cost = np.empty(pi.size)
+    kappa = np.empty(pi.size)
+    lib().oracle_gmm_pairs(_p(xy), _p(sig), _p(offsets), {"l2": 0, "bhattacharya": 1}[mode], _p(pi), _p(pj),
+                           pi.size, _p(cost), _p(kappa))
+    return (cost, kappa) if with_kappa else cost
 
 
 def sparse_cosine(offsets, keys, vals, pi, pj):

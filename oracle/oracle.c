@@ -120,6 +120,50 @@ void oracle_overlap_pairs(const float *xy, const int64_t *off, double sigma, con
 }
 
 /* ---------------------------------------------------------------------------------------
+ * Gaussian mixtures with a per-localisation uncertainty (Section V-C names the GMM L2
+ * distance and the Bhattacharya distance as the two particle scores).  Point k of cloud i
+ * is the isotropic component N(x_k, s_k^2 I), point l of cloud j is N(y_l, t_l^2 I);
+ * v = s_k^2 + t_l^2, D = |x_k - y_l|^2.
+ *   mode 0 (L2 cross term):  sum_kl  integral N(z; x_k, s_k^2) N(z; y_l, t_l^2) dz
+ *                          = sum_kl  exp(-D / (2 v)) / (2 pi v)
+ *   mode 1 (Bhattacharya):   sum_kl  integral sqrt(N(z; x_k, s_k^2) N(z; y_l, t_l^2)) dz
+ *                          = sum_kl  (2 s_k t_l / v) exp(-D / (4 v))
+ * ------------------------------------------------------------------------------------- */
+void oracle_gmm_pairs(const float *xy, const float *sig, const int64_t *off, int mode, const int64_t *pi,
+                      const int64_t *pj, int64_t np, double *cost, double *kappa)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t p = 0; p < np; ++p) {
+        const int64_t i = pi[p], j = pj[p];
+        double c = 0.0, ce = 0.0;
+        for (int64_t k = off[i]; k < off[i + 1]; ++k) {
+            const double xk = xy[2 * k], yk = xy[2 * k + 1], sk = sig[k];
+            for (int64_t l = off[j]; l < off[j + 1]; ++l) {
+                const double dx = xk - (double)xy[2 * l];
+                const double dy = yk - (double)xy[2 * l + 1];
+                const double tl = sig[l];
+                const double v = sk * sk + tl * tl;
+                const double D = dx * dx + dy * dy;
+                double e, w;
+                if (mode == 0) {
+                    e = D / (2.0 * v);
+                    w = exp(-e) / (two_pi * v);
+                } else {
+                    e = D / (4.0 * v);
+                    w = (2.0 * sk * tl / v) * exp(-e);
+                }
+                c += w;
+                ce += e * w;
+            }
+        }
+        cost[p] = c;
+        /* cost-weighted mean exponent, as for the plain overlap */
+        if (kappa) kappa[p] = c > 0.0 ? ce / c : 0.0;
+    }
+}
+
+/* ---------------------------------------------------------------------------------------
  * Registration gradient.  For pair p = (i, j) and transform q = (theta, tx, ty):
  *   y'_l = R(theta) (y_l - c_j) + c_j + t,   u_kl = y'_l - x_k,
  *   w_kl = exp(-|u_kl|^2 / (4 sigma^2)),     C = sum w_kl,

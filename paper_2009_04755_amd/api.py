@@ -30,10 +30,14 @@ def num_pairs(n: int) -> int:
 
 @dataclass
 class Clouds:
-    """Ragged 2-D point clouds: cloud i owns points offsets[i] .. offsets[i+1]-1 of xy."""
+    """Ragged 2-D point clouds: cloud i owns points offsets[i] .. offsets[i+1]-1 of xy.
+
+    ``sigma`` is the common scale of ``gauss_overlap``; ``point_sigma`` the per-point
+    standard deviation read by ``gmm_l2`` and ``gmm_bhattacharya``."""
     offsets: torch.Tensor  # int64 [n+1], device
     xy: torch.Tensor       # float32 [2 * total] interleaved (x, y), device
     sigma: float = 0.02
+    point_sigma: torch.Tensor | None = None  # float32 [total], device
 
     @property
     def n(self) -> int:
@@ -111,12 +115,16 @@ class Context:
             it.dim = x.shape[1]
             it.ld = x.stride(0) if x.shape[0] > 1 else x.shape[1]
             return it, x.shape[0]
-        if fn == _lib.GAUSS_OVERLAP:
+        if fn in (_lib.GAUSS_OVERLAP, _lib.GMM_L2, _lib.GMM_BHATTACHARYA):
             assert isinstance(x, Clouds)
             assert x.offsets.dtype == torch.int64 and x.xy.dtype == torch.float32 and x.xy.is_cuda
             it.offsets = x.offsets.data_ptr()
             it.xy = x.xy.data_ptr()
             it.sigma = float(x.sigma)
+            if fn != _lib.GAUSS_OVERLAP and x.point_sigma is not None:
+                ps = x.point_sigma
+                assert ps.dtype == torch.float32 and ps.is_cuda and ps.is_contiguous() and ps.numel() * 2 == x.xy.numel()
+                it.point_sigma = ps.data_ptr()
             return it, x.n
         if fn == _lib.SPARSE_COSINE:
             assert isinstance(x, SparseSet)
@@ -182,6 +190,7 @@ def allpairs(x, fn: str, counts: bool = False, ctx: Context | None = None):
     """All n(n-1)/2 pair results in packed upper-triangle order (float32 on the device).
 
     ``x``: float32 [n][d] for the NCC functions, :class:`Clouds` for ``gauss_overlap``,
+    ``gmm_l2`` and ``gmm_bhattacharya`` (the latter two read ``Clouds.point_sigma``),
     :class:`SparseSet` for ``sparse_cosine`` (``counts=True`` also returns the exact
     intersection sizes).
     """

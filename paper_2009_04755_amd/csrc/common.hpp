@@ -24,6 +24,7 @@ enum Slot {
     WS_NCC_TILES,        // tile list (bi, bj) for the epilogue
     WS_OVL_PACK,         // size-sorted packed clouds
     WS_OVL_META,         // per sorted cloud: offset, count, original index
+    WS_OVL_SIG,          // packed scaled per-point deviations (GMM scores)
     WS_SP_KEYS,          // packed u32 keys
     WS_SP_META,          // flags, inverse norms, sorted order
     WS_SP_CHUNKS,        // band histogram over key micro-chunks + chunk counts
@@ -66,6 +67,7 @@ struct OvlState {
     const int64_t *offsets = nullptr;
     const float *xy = nullptr;
     double sigma = 0;
+    int mode = 0;  // 0 fixed-sigma overlap, 1 GMM L2, 2 Bhattacharya
     int block = 0;
     int64_t tiles = 0, max_block_pts = 0;
     std::vector<int64_t> h_offsets;  // host copy of offsets
@@ -142,7 +144,7 @@ void single_segment(std::vector<int> &seg, int64_t nitems);
 // Per pair-function modules.
 rocket_status ncc_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, int scheme, hipStream_t s);
 rocket_status ncc_compare(rocket_ctx *ctx, float *out, hipStream_t s);
-rocket_status ovl_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, hipStream_t s);
+rocket_status ovl_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, int mode, hipStream_t s);
 rocket_status ovl_compare(rocket_ctx *ctx, float *out, const float *centroids, const float *params, float *grad,
                           hipStream_t s);
 rocket_status ovl_autotune(rocket_ctx *ctx, hipStream_t s);

@@ -6,12 +6,20 @@
 //   dC/dt     = -(1/(2 sigma^2)) sum_kl w_kl (y'_l - x_k)
 //   dC/dtheta = -(1/(2 sigma^2)) sum_l < sum_k w_kl (y'_l - x_k), J R(theta)(y_l - c_j) >
 //
+// The same kernel evaluates the two per-localisation-uncertainty scores of Section V-C, where
+// point k carries its own standard deviation s_k (v = s_k^2 + t_l^2, D = |x_k - y_l|^2):
+//   GMM L2 cross term   sum_kl exp(-D / (2 v)) / (2 pi v)
+//   Bhattacharya        sum_kl (2 s_k t_l / v) exp(-D / (4 v))
+// Prepare stores s~ = s sqrt(2 ln 2) (L2) or s sqrt(4 ln 2) (Bhattacharya) per packed point,
+// so that with r = 1 / (s~_k^2 + t~_l^2) a term is exp2(-D r) r (L2, times ln2/pi per pair) or
+// exp2(-D r) s~_k r t~_l (Bhattacharya, times 2 per pair): one reciprocal and one exp2 per term.
+//
 // Clouds have uneven sizes.  Prepare sorts them by size (largest first) and packs them
 // contiguously, so that a tile of T x T sorted clouds holds pairs of similar cost; tiles are
 // queued largest estimated cost first (sum of N_a N_b) and dealt to per-XCD segments.  One
 // persistent workgroup per CU stages the two cloud blocks of its tile in LDS and gives each
 // pair to one wavefront: lanes own points of cloud j (S lanes x R registers per chunk, 64/S
-// phases over the points of cloud i), every lane keeps FP32 partial sums, and the wavefront
+// phases, each over a contiguous run of the points of cloud i), every lane keeps FP32 partial sums, and the wavefront
 // reduces them with a fixed xor-butterfly, so results do not depend on scheduling.
 #include <algorithm>
 #include <cmath>
@@ -26,6 +34,10 @@ namespace {
 constexpr int OVL_THREADS = 512;
 constexpr int OVL_WAVES = OVL_THREADS / 64;
 constexpr int OVL_MAX_BLOCK_PTS = 10000;  // per staged block (80 KB)
+constexpr int GMM_MAX_BLOCK_PTS = 6800;   // with one f32 deviation per point (81.6 KB)
+constexpr float GMM_SIG_MIN = 1e-18f, GMM_SIG_MAX = 1e18f;
+
+enum { MODE_OVERLAP = 0, MODE_GMM_L2 = 1, MODE_GMM_BH = 2 };
 
 __device__ __forceinline__ float wave_sum(float v)
 {
@@ -36,27 +48,46 @@ __device__ __forceinline__ float wave_sum(float v)
 
 // Gather sorted clouds into one packed array: cloud s of the sorted order owns packed
 // points coff[s] .. coff[s+1]-1.
+__global__ void k_ovl_zero(int *flag) { flag[threadIdx.x] = 0; }
+
+// With per-point deviations (sig != nullptr) also pack s~ = s * sscale and raise *flag when a
+// deviation lies outside [GMM_SIG_MIN, GMM_SIG_MAX] (or is NaN).
 __global__ void k_ovl_pack(const float2 *__restrict__ xy, const int64_t *__restrict__ offsets,
-                           const int *__restrict__ perm, const int *__restrict__ coff, float2 *__restrict__ packed, int n)
+                           const int *__restrict__ perm, const int *__restrict__ coff, float2 *__restrict__ packed, int n,
+                           const float *__restrict__ sig, double sscale, float *__restrict__ psig, int *__restrict__ flag)
 {
     for (int s = blockIdx.x; s < n; s += gridDim.x) {
         const int64_t src = offsets[perm[s]];
         const int dst = coff[s], cnt = coff[s + 1] - coff[s];
-        for (int k = threadIdx.x; k < cnt; k += blockDim.x) packed[dst + k] = xy[src + k];
+        for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
+            packed[dst + k] = xy[src + k];
+            if (sig) {
+                const float v = sig[src + k];
+                if (!(v >= GMM_SIG_MIN && v <= GMM_SIG_MAX)) *flag = 1;
+                psig[dst + k] = (float)((double)v * sscale);
+            }
+        }
     }
 }
 
-template <bool GRAD, int S, int R>
+// MODE_OVERLAP: cexp = log2(e) / (4 sigma^2), cpost unused.  GMM modes: psig holds the packed
+// scaled deviations, LDS holds them behind the points at float offset sig_at, cpost is the
+// per-pair factor.
+template <int MODE, bool GRAD, int S, int R>
 __global__ __launch_bounds__(OVL_THREADS, 1) void k_overlap(const float2 *__restrict__ pts, const int *__restrict__ coff,
                                                             const int *__restrict__ perm, int n, int T, float cexp,
                                                             QueueArgs q, float *__restrict__ out,
                                                             const float *__restrict__ cen,
                                                             const float *__restrict__ params, float *__restrict__ grad,
-                                                            float gscale)
+                                                            float gscale, const float *__restrict__ psig, int sig_at,
+                                                            float cpost)
 {
+    static_assert(MODE == MODE_OVERLAP || !GRAD, "the adjoint exists for the fixed-sigma cost only");
+    constexpr bool GMM = MODE != MODE_OVERLAP;
     constexpr int P = 64 / S;  // phases over the points of cloud i
     constexpr int CH = S * R;  // points of cloud j per chunk
     extern __shared__ float2 lds_pts[];
+    float *lds_sig = reinterpret_cast<float *>(lds_pts) + sig_at;
     __shared__ int s_item;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int slot = lane % S, phase = lane / S;
@@ -74,6 +105,10 @@ __global__ __launch_bounds__(OVL_THREADS, 1) void k_overlap(const float2 *__rest
         const int nI = pI1 - pI0, nJ = diag ? 0 : pJ1 - pJ0;
         for (int k = tid; k < nI; k += OVL_THREADS) lds_pts[k] = pts[pI0 + k];
         for (int k = tid; k < nJ; k += OVL_THREADS) lds_pts[nI + k] = pts[pJ0 + k];
+        if constexpr (GMM) {
+            for (int k = tid; k < nI; k += OVL_THREADS) lds_sig[k] = psig[pI0 + k];
+            for (int k = tid; k < nJ; k += OVL_THREADS) lds_sig[nI + k] = psig[pJ0 + k];
+        }
         __syncthreads();
 
         const int na = a1 - a0, nb = b1 - b0;
@@ -104,12 +139,16 @@ __global__ __launch_bounds__(OVL_THREADS, 1) void k_overlap(const float2 *__rest
                 // y'_l as an unevaluated FP32 pair (hi + lo): rounding the transformed point to
                 // one FP32 would move every exponent by ~1250 |u| 2^-24, which is 1e-5 of a
                 // term already at |u| ~ 0.25
-                float yx[R], yy[R], lx[R], ly[R], vx[R], vy[R];
+                float yx[R], yy[R], lx[R], ly[R], vx[R], vy[R], tt[R], tq[R];
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const int l = c0 + r * S + slot;
                     if (l < Nj) {
                         const float2 y = lds_pts[base_j + l];
+                        if constexpr (GMM) {
+                            tq[r] = lds_sig[base_j + l];
+                            tt[r] = tq[r] * tq[r];
+                        }
                         if constexpr (GRAD) {
                             // transform in FP64, rounded once to FP32
                             const double rx = (double)y.x - cx, ry = (double)y.y - cy;
@@ -131,36 +170,80 @@ __global__ __launch_bounds__(OVL_THREADS, 1) void k_overlap(const float2 *__rest
                         lx[r] = ly[r] = 0.f;
                         vx[r] = 0.f;
                         vy[r] = 0.f;
+                        tt[r] = 1.f;
+                        tq[r] = 0.f;
                     }
                 }
-                float sc[R], sx[R], sy[R];
+                // this lane's phase covers a contiguous run of cloud i's points, four per step
+                float sc[R][2], sx[R][2], sy[R][2];
 #pragma unroll
-                for (int r = 0; r < R; ++r) sc[r] = sx[r] = sy[r] = 0.f;
-                for (int k = phase; k < Ni; k += P) {
-                    const float2 x = lds_pts[base_i + k];
+                for (int r = 0; r < R; ++r)
 #pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        float ux = yx[r] - x.x, uy = yy[r] - x.y;
-                        if constexpr (GRAD) {
-                            ux += lx[r];
-                            uy += ly[r];
-                        }
-                        const float d2 = fmaf(uy, uy, ux * ux);
+                    for (int e = 0; e < 2; ++e) sc[r][e] = sx[r][e] = sy[r][e] = 0.f;
+                auto term = [&](const float2 x, const float s, int r, int e) {
+                    float ux = yx[r] - x.x, uy = yy[r] - x.y;
+                    if constexpr (GRAD) {
+                        ux += lx[r];
+                        uy += ly[r];
+                    }
+                    const float d2 = fmaf(uy, uy, ux * ux);
+                    if constexpr (GMM) {
+                        const float rv = __builtin_amdgcn_rcpf(fmaf(s, s, tt[r]));
+                        const float wkl = __builtin_amdgcn_exp2f(-(d2 * rv));
+                        sc[r][e] = fmaf(wkl, MODE == MODE_GMM_L2 ? rv : s * rv, sc[r][e]);
+                    } else {
                         const float wkl = __builtin_amdgcn_exp2f(-(d2 * cexp));
-                        sc[r] += wkl;
+                        sc[r][e] += wkl;
                         if constexpr (GRAD) {
-                            sx[r] = fmaf(wkl, ux, sx[r]);
-                            sy[r] = fmaf(wkl, uy, sy[r]);
+                            sx[r][e] = fmaf(wkl, ux, sx[r][e]);
+                            sy[r][e] = fmaf(wkl, uy, sy[r][e]);
                         }
                     }
+                };
+                const int per = (Ni + P - 1) / P;
+                const int k0 = min(Ni, phase * per), k1 = min(Ni, k0 + per);
+                const float2 *xs = lds_pts + base_i;
+                const float *ss = lds_sig + base_i;
+                int k = k0;
+                for (; k + 4 <= k1; k += 4) {
+                    const float2 x0 = xs[k], x1 = xs[k + 1], x2 = xs[k + 2], x3 = xs[k + 3];
+                    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+                    if constexpr (GMM) {
+                        s0 = ss[k];
+                        s1 = ss[k + 1];
+                        s2 = ss[k + 2];
+                        s3 = ss[k + 3];
+                    }
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        term(x0, s0, r, 0);
+                        term(x1, s1, r, 1);
+                        term(x2, s2, r, 0);
+                        term(x3, s3, r, 1);
+                    }
+                }
+                for (; k < k1; ++k) {
+                    const float2 x0 = xs[k];
+                    const float s0 = GMM ? ss[k] : 0.f;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) term(x0, s0, r, 0);
                 }
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    accC += sc[r];
+                    sc[r][0] += sc[r][1];
+                    sx[r][0] += sx[r][1];
+                    sy[r][0] += sy[r][1];
+                }
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if constexpr (MODE == MODE_GMM_BH)
+                        accC = fmaf(sc[r][0], tq[r], accC);
+                    else
+                        accC += sc[r][0];
                     if constexpr (GRAD) {
-                        accX += sx[r];
-                        accY += sy[r];
-                        accT = fmaf(vx[r], sx[r], fmaf(vy[r], sy[r], accT));
+                        accX += sx[r][0];
+                        accY += sy[r][0];
+                        accT = fmaf(vx[r], sx[r][0], fmaf(vy[r], sy[r][0], accT));
                     }
                 }
             }
@@ -175,6 +258,8 @@ __global__ __launch_bounds__(OVL_THREADS, 1) void k_overlap(const float2 *__rest
                         grad[3 * pidx + 2] = gscale * GY;
                     }
                 }
+            } else if constexpr (GMM) {
+                if (lane == 0) out[pidx] = C * cpost;
             } else {
                 if (lane == 0) out[pidx] = C;
             }
@@ -183,39 +268,73 @@ __global__ __launch_bounds__(OVL_THREADS, 1) void k_overlap(const float2 *__rest
     }
 }
 
-template <bool GRAD>
-const void *ovl_kernel(int variant)
+template <int MODE, bool GRAD>
+const void *ovl_kernel_m(int variant)
 {
     switch (variant) {
-    case 1: return (const void *)&k_overlap<GRAD, 64, 1>;
-    case 2: return (const void *)&k_overlap<GRAD, 32, 2>;
-    default: return (const void *)&k_overlap<GRAD, 16, 2>;
+    case 1: return (const void *)&k_overlap<MODE, GRAD, 64, 1>;
+    case 2: return (const void *)&k_overlap<MODE, GRAD, 32, 2>;
+    case 4: return (const void *)&k_overlap<MODE, GRAD, 16, 4>;
+    default: return (const void *)&k_overlap<MODE, GRAD, 16, 2>;
     }
 }
 
-template <bool GRAD>
-void launch_ovl(int variant, int grid, size_t lds, hipStream_t s, const float2 *pts, const int *coff, const int *perm,
-                int n, int T, float cexp, const QueueArgs &qa, float *out, const float *cen, const float *params,
-                float *grad, float gscale)
+const void *ovl_kernel(int mode, bool grad, int variant)
+{
+    if (grad) return ovl_kernel_m<MODE_OVERLAP, true>(variant);
+    switch (mode) {
+    case MODE_GMM_L2: return ovl_kernel_m<MODE_GMM_L2, false>(variant);
+    case MODE_GMM_BH: return ovl_kernel_m<MODE_GMM_BH, false>(variant);
+    default: return ovl_kernel_m<MODE_OVERLAP, false>(variant);
+    }
+}
+
+struct OvlLaunch {
+    const float2 *pts;
+    const int *coff, *perm;
+    int n, T;
+    float cexp;
+    QueueArgs qa;
+    float *out;
+    const float *cen, *params;
+    float *grad;
+    float gscale;
+    const float *psig;
+    int sig_at;
+    float cpost;
+};
+
+template <int MODE, bool GRAD, int S, int R>
+void launch_one(int grid, size_t lds, hipStream_t s, const OvlLaunch &a)
+{
+    hipLaunchKernelGGL((k_overlap<MODE, GRAD, S, R>), dim3(grid), dim3(OVL_THREADS), lds, s, a.pts, a.coff, a.perm,
+                       a.n, a.T, a.cexp, a.qa, a.out, a.cen, a.params, a.grad, a.gscale, a.psig, a.sig_at, a.cpost);
+}
+
+template <int MODE, bool GRAD>
+void launch_m(int variant, int grid, size_t lds, hipStream_t s, const OvlLaunch &a)
 {
     switch (variant) {
-    case 1:
-        hipLaunchKernelGGL((k_overlap<GRAD, 64, 1>), dim3(grid), dim3(OVL_THREADS), lds, s, pts, coff, perm, n, T,
-                           cexp, qa, out, cen, params, grad, gscale);
-        break;
-    case 2:
-        hipLaunchKernelGGL((k_overlap<GRAD, 32, 2>), dim3(grid), dim3(OVL_THREADS), lds, s, pts, coff, perm, n, T,
-                           cexp, qa, out, cen, params, grad, gscale);
-        break;
-    default:
-        hipLaunchKernelGGL((k_overlap<GRAD, 16, 2>), dim3(grid), dim3(OVL_THREADS), lds, s, pts, coff, perm, n, T,
-                           cexp, qa, out, cen, params, grad, gscale);
-        break;
+    case 1: launch_one<MODE, GRAD, 64, 1>(grid, lds, s, a); break;
+    case 2: launch_one<MODE, GRAD, 32, 2>(grid, lds, s, a); break;
+    case 4: launch_one<MODE, GRAD, 16, 4>(grid, lds, s, a); break;
+    default: launch_one<MODE, GRAD, 16, 2>(grid, lds, s, a); break;
+    }
+}
+
+void launch_ovl(int mode, bool grad, int variant, int grid, size_t lds, hipStream_t s, const OvlLaunch &a)
+{
+    if (grad) return launch_m<MODE_OVERLAP, true>(variant, grid, lds, s, a);
+    switch (mode) {
+    case MODE_GMM_L2: launch_m<MODE_GMM_L2, false>(variant, grid, lds, s, a); break;
+    case MODE_GMM_BH: launch_m<MODE_GMM_BH, false>(variant, grid, lds, s, a); break;
+    default: launch_m<MODE_OVERLAP, false>(variant, grid, lds, s, a); break;
     }
 }
 
 struct OvlDev {
     float2 *pts;
+    float *sig;
     int *coff, *perm;
 };
 
@@ -223,9 +342,17 @@ OvlDev dev_ptrs(rocket_ctx *ctx, int64_t n)
 {
     OvlDev d;
     d.pts = (float2 *)ctx->ws[WS_OVL_PACK].ptr;
+    d.sig = (float *)ctx->ws[WS_OVL_SIG].ptr;
     d.coff = (int *)ctx->ws[WS_OVL_META].ptr;
     d.perm = d.coff + ((n + 1 + 63) / 64) * 64;
     return d;
+}
+
+int max_block_pts(int mode) { return mode == MODE_OVERLAP ? OVL_MAX_BLOCK_PTS : GMM_MAX_BLOCK_PTS; }
+
+size_t ovl_lds_bytes(int mode, int64_t mx)
+{
+    return (size_t)2 * mx * (sizeof(float2) + (mode == MODE_OVERLAP ? 0 : sizeof(float))) + 16;
 }
 
 }  // namespace
@@ -291,10 +418,10 @@ static rocket_status ovl_replan(rocket_ctx *ctx, hipStream_t s)
     int64_t mx = 0;
     for (;;) {
         ovl_plan(ctx, T, ctx->h_items, ctx->h_seg, &mx);
-        if (mx <= OVL_MAX_BLOCK_PTS || T == 1) break;
+        if (mx <= max_block_pts(o.mode) || T == 1) break;
         T = std::max(1, T / 2);
     }
-    if (mx > OVL_MAX_BLOCK_PTS) return fail(ctx, ROCKET_E_UNSUPPORTED, "a single cloud exceeds the LDS capacity");
+    if (mx > max_block_pts(o.mode)) return fail(ctx, ROCKET_E_UNSUPPORTED, "a single cloud exceeds the LDS capacity");
     o.block = T;
     o.max_block_pts = mx;
     o.tiles = (int64_t)ctx->h_items.size();
@@ -307,12 +434,16 @@ static rocket_status ovl_replan(rocket_ctx *ctx, hipStream_t s)
     return ROCKET_OK;
 }
 
-rocket_status ovl_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, hipStream_t s)
+rocket_status ovl_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, int mode, hipStream_t s)
 {
     OvlState &o = ctx->ovl;
     o.valid = false;
     if (n > 0 && (!it->offsets || !it->xy)) return fail(ctx, ROCKET_E_INVALID, "offsets or xy is NULL");
-    if (!(it->sigma > 0.0) || !std::isfinite(it->sigma)) return fail(ctx, ROCKET_E_INVALID, "sigma must be > 0");
+    if (mode == MODE_OVERLAP && (!(it->sigma > 0.0) || !std::isfinite(it->sigma)))
+        return fail(ctx, ROCKET_E_INVALID, "sigma must be > 0");
+    if (mode != MODE_OVERLAP && n > 0 && !it->point_sigma)
+        return fail(ctx, ROCKET_E_INVALID, "point_sigma is NULL");
+    o.mode = mode;
     if (n >= (1 << 30)) return fail(ctx, ROCKET_E_INVALID, "n too large");
     o.n = n;
     o.offsets = it->offsets;
@@ -343,17 +474,30 @@ rocket_status ovl_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, hi
     meta[n] = acc;
     const size_t poff = ((n + 1 + 63) / 64) * 64;
     for (int64_t s2 = 0; s2 < n; ++s2) meta[poff + s2] = o.perm[s2];
-    void *mp = nullptr, *pp = nullptr;
+    void *mp = nullptr, *pp = nullptr, *sp = nullptr, *fp = nullptr;
     RK_TRY(ws_get(ctx, WS_OVL_META, sizeof(int) * meta.size(), &mp));
     RK_TRY(ws_get(ctx, WS_OVL_PACK, sizeof(float2) * (size_t)std::max<int64_t>(o.total, 1), &pp));
+    const bool gmm = mode != MODE_OVERLAP;
+    if (gmm) {
+        RK_TRY(ws_get(ctx, WS_OVL_SIG, sizeof(float) * (size_t)std::max<int64_t>(o.total, 1), &sp));
+        RK_TRY(ws_get(ctx, WS_FLAGS, 256, &fp));
+        hipLaunchKernelGGL(k_ovl_zero, dim3(1), dim3(64), 0, s, (int *)fp);
+        RK_HIP(hipGetLastError());
+    }
     RK_HIP(hipMemcpyAsync(mp, meta.data(), sizeof(int) * meta.size(), hipMemcpyHostToDevice, s));
     if (n > 0) {
         const OvlDev d = dev_ptrs(ctx, n);
+        // s~^2 = 2 ln2 s^2 (L2) or 4 ln2 s^2 (Bhattacharya): see the kernel's header comment
+        const double sscale = std::sqrt((mode == MODE_GMM_L2 ? 2.0 : 4.0) * 0.69314718055994530942);
         hipLaunchKernelGGL(k_ovl_pack, dim3((unsigned)std::min<int64_t>(n, 65535)), dim3(256), 0, s,
-                           (const float2 *)it->xy, it->offsets, d.perm, d.coff, d.pts, (int)n);
+                           (const float2 *)it->xy, it->offsets, d.perm, d.coff, d.pts, (int)n,
+                           gmm ? it->point_sigma : nullptr, sscale, gmm ? d.sig : nullptr, (int *)fp);
         RK_HIP(hipGetLastError());
     }
+    int flag = 0;
+    if (gmm) RK_HIP(hipMemcpyAsync(&flag, fp, sizeof(int), hipMemcpyDeviceToHost, s));
     RK_HIP(hipStreamSynchronize(s));  // meta staging vector goes out of scope
+    if (flag) return fail(ctx, ROCKET_E_INVALID, "point_sigma outside [1e-18, 1e18]");
     RK_TRY(ovl_replan(ctx, s));
     if (ctx->opt[ROCKET_OPT_AUTOTUNE] && n >= 64) RK_TRY(ovl_autotune(ctx, s));
     ctx->stats.tiles = o.tiles;
@@ -369,24 +513,34 @@ static rocket_status ovl_launch(rocket_ctx *ctx, hipStream_t s, float *out, cons
 {
     OvlState &o = ctx->ovl;
     const OvlDev d = dev_ptrs(ctx, o.n);
-    const size_t lds = (size_t)2 * o.max_block_pts * sizeof(float2) + 16;
+    const size_t lds = ovl_lds_bytes(o.mode, o.max_block_pts);
     const bool g = params != nullptr;
-    const int grid = auto_grid(ctx, g ? ovl_kernel<true>(variant) : ovl_kernel<false>(variant), OVL_THREADS, lds,
-                               o.tiles);
+    const void *kern = ovl_kernel(o.mode, g, variant);
+    const int grid = auto_grid(ctx, kern, OVL_THREADS, lds, o.tiles);
     ctx->stats.grid = grid;
     ctx->stats.variant = variant;
-    RK_HIP(hipFuncSetAttribute(g ? ovl_kernel<true>(variant) : ovl_kernel<false>(variant),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    RK_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     RK_TRY(reset_queue(ctx, s, o.qa));
-    const float cexp = (float)(1.4426950408889634 / (4.0 * o.sigma * o.sigma));
-    const float gscale = (float)(-1.0 / (2.0 * o.sigma * o.sigma));
+    OvlLaunch a;
+    a.pts = d.pts;
+    a.coff = d.coff;
+    a.perm = d.perm;
+    a.n = (int)o.n;
+    a.T = o.block;
+    a.cexp = o.mode == MODE_OVERLAP ? (float)(1.4426950408889634 / (4.0 * o.sigma * o.sigma)) : 0.f;
+    a.qa = o.qa;
+    a.out = out;
+    a.cen = g ? cen : nullptr;
+    a.params = g ? params : nullptr;
+    a.grad = g ? grad : nullptr;
+    a.gscale = o.mode == MODE_OVERLAP ? (float)(-1.0 / (2.0 * o.sigma * o.sigma)) : 0.f;
+    a.psig = o.mode == MODE_OVERLAP ? nullptr : d.sig;
+    a.sig_at = (int)(2 * 2 * o.max_block_pts);  // floats: behind 2 blocks of float2 points
+    // per-pair factor: ln2 / pi (L2), 2 (Bhattacharya)
+    a.cpost = o.mode == MODE_GMM_L2 ? (float)(0.69314718055994530942 / 3.14159265358979323846)
+                                    : (o.mode == MODE_GMM_BH ? 2.f : 1.f);
     RK_TRY(timing_begin(ctx, s));
-    if (g)
-        launch_ovl<true>(variant, grid, lds, s, d.pts, d.coff, d.perm, (int)o.n, o.block, cexp, o.qa, out, cen, params,
-                         grad, gscale);
-    else
-        launch_ovl<false>(variant, grid, lds, s, d.pts, d.coff, d.perm, (int)o.n, o.block, cexp, o.qa, out, nullptr,
-                          nullptr, nullptr, gscale);
+    launch_ovl(o.mode, g, variant, grid, lds, s, a);
     RK_HIP(hipGetLastError());
     RK_TRY(timing_end(ctx, s));
     return ROCKET_OK;
@@ -425,7 +579,7 @@ rocket_status ovl_autotune(rocket_ctx *ctx, hipStream_t s)
         ctx->opt[ROCKET_OPT_OVL_BLOCK] = b;
         if ((st = ovl_replan(ctx, s)) != ROCKET_OK) break;
         if (o.block != b) continue;  // block did not fit in LDS
-        for (int v = 1; v <= 3; ++v) {
+        for (int v = 1; v <= 4; ++v) {
             if ((st = ovl_launch(ctx, s, scratch, nullptr, nullptr, nullptr, v)) != ROCKET_OK) break;  // warm-up
             (void)hipEventRecord(e0, s);
             if ((st = ovl_launch(ctx, s, scratch, nullptr, nullptr, nullptr, v)) != ROCKET_OK) break;

@@ -18,7 +18,7 @@ rocket_ctx *g_default[64] = {nullptr};
 std::mutex g_default_mu;
 std::string g_null_error;
 
-bool valid_fn(int fn) { return fn >= ROCKET_NCC_FP32 && fn <= ROCKET_SPARSE_COSINE; }
+bool valid_fn(int fn) { return fn >= ROCKET_NCC_FP32 && fn <= ROCKET_GMM_BHATTACHARYA; }
 
 }  // namespace
 
@@ -220,7 +220,9 @@ rocket_status rocket_prepare(rocket_ctx *ctx, const rocket_items *items, int64_t
     case ROCKET_NCC_FP32:
     case ROCKET_NCC_BF16X3:
     case ROCKET_NCC_BF16X6: st = rk::ncc_prepare(ctx, items, n, (int)fn, s); break;
-    case ROCKET_GAUSS_OVERLAP: st = rk::ovl_prepare(ctx, items, n, s); break;
+    case ROCKET_GAUSS_OVERLAP: st = rk::ovl_prepare(ctx, items, n, 0, s); break;
+    case ROCKET_GMM_L2: st = rk::ovl_prepare(ctx, items, n, 1, s); break;
+    case ROCKET_GMM_BHATTACHARYA: st = rk::ovl_prepare(ctx, items, n, 2, s); break;
     case ROCKET_SPARSE_COSINE: st = rk::sp_prepare(ctx, items, n, s); break;
     default: st = ROCKET_E_UNSUPPORTED;
     }
@@ -243,7 +245,9 @@ rocket_status rocket_compare(rocket_ctx *ctx, float *out, uint32_t *out_counts, 
     case ROCKET_NCC_FP32:
     case ROCKET_NCC_BF16X3:
     case ROCKET_NCC_BF16X6: st = rk::ncc_compare(ctx, out, s); break;
-    case ROCKET_GAUSS_OVERLAP: st = rk::ovl_compare(ctx, out, nullptr, nullptr, nullptr, s); break;
+    case ROCKET_GAUSS_OVERLAP:
+    case ROCKET_GMM_L2:
+    case ROCKET_GMM_BHATTACHARYA: st = rk::ovl_compare(ctx, out, nullptr, nullptr, nullptr, s); break;
     case ROCKET_SPARSE_COSINE: st = rk::sp_compare(ctx, out, out_counts, s); break;
     default: st = ROCKET_E_STATE;
     }
@@ -289,11 +293,11 @@ rocket_status rocket_overlap_cost_grad(rocket_ctx *ctx, const rocket_items *clou
         return rk::fail(ctx, ROCKET_E_INVALID, "centroids, params and out_cost are required");
     hipStream_t s = (hipStream_t)stream;
     const rk::OvlState &o = ctx->ovl;
-    const bool reuse = o.valid && o.n == n && o.offsets == clouds->offsets && o.xy == clouds->xy &&
+    const bool reuse = o.valid && o.mode == 0 && o.n == n && o.offsets == clouds->offsets && o.xy == clouds->xy &&
                        o.sigma == clouds->sigma;
     if (!reuse) {
         ctx->prepared_fn = 0;
-        RK_TRY(rk::ovl_prepare(ctx, clouds, n, s));
+        RK_TRY(rk::ovl_prepare(ctx, clouds, n, 0, s));
         ctx->prepared_fn = ROCKET_GAUSS_OVERLAP;
     }
     ctx->stats.n = n;
@@ -313,7 +317,7 @@ rocket_status rocket_set_option(rocket_ctx *ctx, rocket_option opt, int64_t valu
     if (opt == ROCKET_OPT_NCC_KCHUNK && value % 16 != 0)
         return rk::fail(ctx, ROCKET_E_INVALID, "NCC K chunk must be a multiple of 16");
     if (opt == ROCKET_OPT_QUEUE_ORDER && value > 2) return rk::fail(ctx, ROCKET_E_INVALID, "queue order 0..2");
-    if (opt == ROCKET_OPT_OVL_VARIANT && value > 3) return rk::fail(ctx, ROCKET_E_INVALID, "overlap variant 0..3");
+    if (opt == ROCKET_OPT_OVL_VARIANT && value > 4) return rk::fail(ctx, ROCKET_E_INVALID, "overlap variant 0..4");
     if (opt == ROCKET_OPT_OVL_BLOCK && value > 64) return rk::fail(ctx, ROCKET_E_INVALID, "overlap block <= 64");
     ctx->opt[opt] = value;
     return ROCKET_OK;
@@ -358,7 +362,9 @@ rocket_status rocket_get_ledger(rocket_ctx *ctx, int32_t *out, int64_t cap, int6
 rocket_status rocket_autotune(rocket_ctx *ctx, void *stream)
 {
     RK_TRY(enter(ctx));
-    if (ctx->prepared_fn == ROCKET_GAUSS_OVERLAP) return rk::ovl_autotune(ctx, (hipStream_t)stream);
+    if (ctx->prepared_fn == ROCKET_GAUSS_OVERLAP || ctx->prepared_fn == ROCKET_GMM_L2 ||
+        ctx->prepared_fn == ROCKET_GMM_BHATTACHARYA)
+        return rk::ovl_autotune(ctx, (hipStream_t)stream);
     if (!ctx->prepared_fn) return rk::fail(ctx, ROCKET_E_STATE, "autotune needs a prepared set");
     return ROCKET_OK;  // dense and sparse paths have fixed shapes
 }

@@ -139,6 +139,12 @@ def cloud_centroids(offsets: np.ndarray, xy: np.ndarray) -> np.ndarray:
     return out.astype(np.float32)
 
 
+def point_sigmas(offsets: np.ndarray, lo: float = 0.01, hi: float = 0.03, config: int = 2, salt: int = 0):
+    """Per-localisation uncertainty sigma_k ~ U[lo, hi] (f32), one per point."""
+    g = rng(config, 500 + salt)
+    return g.uniform(lo, hi, int(offsets[-1])).astype(np.float32)
+
+
 def rigid_starts(npairs: int, config: int = 3, salt: int = 0) -> np.ndarray:
     """Per-pair start transform (theta, tx, ty): theta ~ U[-pi, pi), t ~ U[-0.5, 0.5]^2."""
     g = rng(config, salt)

@@ -54,3 +54,15 @@ def test_bad_arguments_rejected_without_device(lib):
     assert lib.rocket_plan_tiles(5, 0, None, None, 0) < 0
     st = lib.rocket_prepare(None, None, 4, 3, None)
     assert st == _lib.E_INVALID
+
+
+def test_binding_matches_header_enums_and_items():
+    header = open(os.path.join(ROOT, "include", "rocket.h")).read()
+    fns = dict((k, int(v)) for k, v in re.findall(r"ROCKET_(NCC_\w+|GAUSS_OVERLAP|SPARSE_COSINE|GMM_\w+) = (\d+)", header))
+    assert {k.lower(): v for k, v in fns.items()} == _lib.FN_BY_NAME
+    opts = dict((k.lower(), int(v)) for k, v in re.findall(r"ROCKET_OPT_(\w+) = (\d+)", header))
+    assert opts == _lib.OPT
+    body = re.search(r"typedef struct \{(.*?)\} rocket_items;", header, re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"(\w+);", body)
+    assert fields == [f for f, _ in _lib.Items._fields_]
