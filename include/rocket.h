@@ -14,7 +14,9 @@
  *                    persistent launch that pulls tiles of the pair matrix from an
  *                    on-device queue (Section IV-B's divide-and-conquer split and
  *                    work stealing, mapped onto the chip);
- *   rocket_allpairs  both, back to back.
+ *   rocket_allpairs  both, back to back;
+ *   rocket_allpairs_host  the same for NCC items that stay in host memory and
+ *                    pass through a fixed-size device cache (Section IV-A).
  *
  * Three pair functions are provided, one per application of Section V:
  *   ROCKET_NCC_*          normalised cross-correlation of dense vectors (V-A);
@@ -161,6 +163,20 @@ rocket_status rocket_allpairs_ex(rocket_ctx *ctx, const rocket_items *items, int
  * before returning.  out: float32 [n(n-1)/2]. */
 rocket_status rocket_allpairs(const rocket_items *items, int64_t n, rocket_pair_fn fn, float *out_upper_triangle);
 
+/* Out-of-core all pairs for the NCC functions: items stay in HOST memory (float32
+ * [n][ld], row-major; page-locked memory lets copies run asynchronously) and pass
+ * through a device cache (Section IV-A, first level) of ROCKET_OPT_CACHE_SLOTS slots,
+ * each holding one block of `tile` items in split form.  Leaf tiles are visited in
+ * divide-and-conquer order; a missing block evicts the least recently used slot not
+ * needed by the same tile and is copied in on a separate stream, then centred and split
+ * on `stream`, while earlier tiles compute.  `out` (device, P floats) receives exactly
+ * what rocket_allpairs gives for the same items, options and pair function.
+ * rocket_get_stats reports cache_slots and cache_loads.  Any set prepared on this
+ * context is dropped (its workspace holds the cache).  The host array must stay alive
+ * and unchanged until the enqueued work completes. */
+rocket_status rocket_allpairs_host(rocket_ctx *ctx, const float *host_items /* host */, int64_t n, int64_t dim,
+                                   int64_t ld, rocket_pair_fn fn, float *out, void *stream);
+
 /* Registration gradient (Section V-C optimiser).  For every pair (i, j), i < j, and
  * its transform q = params[idx(i,j)] = (theta, tx, ty), the second cloud is moved as
  *     y'_l = R(theta) (y_l - c_j) + c_j + t,   c_j = centroids[j],
@@ -193,8 +209,11 @@ typedef enum {
     ROCKET_OPT_SP_CHUNK = 10,       /* sparse: key-range chunk width (power of two) */
     ROCKET_OPT_WORKSPACE_CAP = 11,  /* bytes; workspace growth beyond it fails with ROCKET_E_OOM */
     ROCKET_OPT_AUTOTUNE = 12,       /* 1: rocket_prepare of ragged sets runs the tile-shape autotuner */
-    ROCKET_OPT_TIMING = 13          /* 1: bracket each compare's main persistent kernel with HIP events on the
-                                       launch stream; rocket_get_stats reports its duration */
+    ROCKET_OPT_TIMING = 13,         /* 1: bracket each compare's main persistent kernel with HIP events on the
+                                       launch stream; rocket_get_stats reports its duration (for
+                                       rocket_allpairs_host: the whole call's device work) */
+    ROCKET_OPT_CACHE_SLOTS = 14     /* rocket_allpairs_host: device cache slots, one block of `tile` items each
+                                       (0: one per block, i.e. everything stays resident); at least 2 */
 } rocket_option;
 
 rocket_status rocket_set_option(rocket_ctx *ctx, rocket_option opt, int64_t value);
@@ -213,6 +232,9 @@ typedef struct {
     int64_t variant;         /* kernel variant in use */
     int64_t kernel_ns;       /* duration of the last main kernel (ROCKET_OPT_TIMING=1), else -1;
                                 reading it waits for that kernel to finish */
+    int64_t cache_slots;     /* rocket_allpairs_host: device cache slots used (0 otherwise) */
+    int64_t cache_loads;     /* rocket_allpairs_host: block loads from host memory; the reload factor is
+                                cache_loads / ceil(n / tile) (1 when every block is loaded once) */
 } rocket_stats;
 
 rocket_status rocket_get_stats(const rocket_ctx *ctx, rocket_stats *out /* host */);

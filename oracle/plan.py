@@ -60,3 +60,40 @@ def level1_pair_counts(n: int):
     quads = [(0, h, 0, h), (0, h, h, side), (h, side, 0, h), (h, side, h, side)]
     return [sum(1 for i in range(r0, min(r1, n)) for j in range(c0, min(c1, n)) if i < j)
             for (r0, r1, c0, c1) in quads]
+
+
+def lru_loads(n: int, T: int, slots: int):
+    """Block loads of a device cache of ``slots`` block slots visiting the leaves in order.
+
+    Section IV-A (first-level device cache): a job (i, j) needs both items in the
+    cache; on a miss the least-recently-used slot is evicted and refilled from the
+    next level.  Here the cached unit is a block of T items and a job is a leaf tile
+    (bi, bj).  The block a tile still needs is never the one evicted for its other
+    block.  Returns (number of loads, list of (block, slot) loads in order).
+    """
+    if slots < 1 or (slots < 2 and (n + T - 1) // T > 1):
+        raise ValueError("a tile of two blocks needs two slots")
+    holder = [None] * slots   # slot -> block
+    last = [-1] * slots       # slot -> time of last use
+    where = {}                # block -> slot
+    loads = []
+    clock = 0
+    for bi, bj in quadtree_leaves(n, T):
+        need = [bi] if bi == bj else [bi, bj]
+        for b in need:
+            clock += 1
+            if b in where:
+                last[where[b]] = clock
+                continue
+            keep = {where[o] for o in need if o != b and o in where}
+            free = [s for s in range(slots) if holder[s] is None]
+            if free:
+                s = free[0]
+            else:
+                s = min((s for s in range(slots) if s not in keep), key=lambda s: last[s])
+                del where[holder[s]]
+            holder[s] = b
+            where[b] = s
+            last[s] = clock
+            loads.append((b, s))
+    return len(loads), loads

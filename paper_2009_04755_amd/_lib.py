@@ -21,11 +21,12 @@ FN_BY_NAME = {"ncc_fp32": NCC_FP32, "ncc_bf16x3": NCC_BF16X3, "ncc_bf16x6": NCC_
               "gmm_bhattacharya": GMM_BHATTACHARYA}
 
 OPT = {"ncc_tile": 1, "ncc_kchunk": 2, "grid": 3, "queue_order": 4, "seed": 5, "ledger": 6, "ovl_block": 7,
-       "ovl_variant": 8, "sp_rows": 9, "sp_chunk": 10, "workspace_cap": 11, "autotune": 12, "timing": 13}
+       "ovl_variant": 8, "sp_rows": 9, "sp_chunk": 10, "workspace_cap": 11, "autotune": 12, "timing": 13,
+       "cache_slots": 14}
 
 # every symbol include/rocket.h declares
 SYMBOLS = ["rocket_create", "rocket_destroy", "rocket_status_str", "rocket_last_error", "rocket_prepare",
-           "rocket_compare", "rocket_allpairs_ex", "rocket_allpairs", "rocket_overlap_cost_grad",
+           "rocket_compare", "rocket_allpairs_ex", "rocket_allpairs", "rocket_allpairs_host", "rocket_overlap_cost_grad",
            "rocket_set_option", "rocket_get_option", "rocket_get_stats", "rocket_get_ledger", "rocket_autotune",
            "rocket_plan_tiles", "rocket_pair_index"]
 
@@ -39,7 +40,7 @@ class Items(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in
                 ("n", "pairs", "tiles", "work_items", "grid", "tile", "kchunk", "workspace_bytes", "variant",
-                 "kernel_ns")]
+                 "kernel_ns", "cache_slots", "cache_loads")]
 
 
 class RocketError(RuntimeError):
@@ -79,6 +80,8 @@ def load():
     L.rocket_allpairs_ex.restype = I32
     L.rocket_allpairs.argtypes = [IT, I64, I32, P]
     L.rocket_allpairs.restype = I32
+    L.rocket_allpairs_host.argtypes = [P, P, I64, I64, I64, I32, P, P]
+    L.rocket_allpairs_host.restype = I32
     L.rocket_overlap_cost_grad.argtypes = [P, IT, I64, P, P, P, P, P]
     L.rocket_overlap_cost_grad.restype = I32
     L.rocket_set_option.argtypes = [P, I32, I64]

@@ -158,6 +158,21 @@ class Context:
         self.prepare(x, fn)
         return self.compare(out=out, counts=counts)
 
+    def allpairs_host(self, x, fn: str = "ncc_bf16x6", out=None):
+        """All pairs of NCC items kept in host memory (float32 [n][d] CPU tensor, ideally
+        pinned) through the device cache; ``set(cache_slots=S)`` bounds the cache."""
+        code = _lib.FN_BY_NAME[fn]
+        assert not x.is_cuda and x.dtype == torch.float32 and x.dim() == 2 and x.stride(1) == 1
+        n, d = x.shape
+        ld = x.stride(0) if n > 1 else d
+        if out is None:
+            out = torch.empty(num_pairs(n), dtype=torch.float32, device=torch.device("cuda", self.device))
+        self._keep = (x,)
+        self._n = 0  # no prepared set remains
+        _lib.check(_lib.load().rocket_allpairs_host(self.handle, ctypes.c_void_p(x.data_ptr()), n, d, ld, code,
+                                                    _ptr(out), _stream()), self.handle)
+        return out
+
     def autotune(self):
         _lib.check(_lib.load().rocket_autotune(self.handle, _stream()), self.handle)
         return {k: self.get(k) for k in ("ovl_block", "ovl_variant")}

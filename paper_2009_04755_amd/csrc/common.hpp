@@ -22,6 +22,7 @@ enum Slot {
     WS_NCC_PLANES,       // split / centred operand planes
     WS_NCC_PARTIAL,      // split-K partial Gram tiles
     WS_NCC_TILES,        // tile list (bi, bj) for the epilogue
+    WS_OOC_STAGE,        // two raw staging buffers for host-resident items
     WS_OVL_PACK,         // size-sorted packed clouds
     WS_OVL_META,         // per sorted cloud: offset, count, original index
     WS_OVL_SIG,          // packed scaled per-point deviations (GMM scores)
@@ -95,6 +96,14 @@ struct SpState {
     bool valid = false;
 };
 
+// Out-of-core state: copy stream and the events that order it against the compute stream.
+struct OocState {
+    hipStream_t copy = nullptr;
+    hipEvent_t start = nullptr;
+    hipEvent_t copied[2] = {nullptr, nullptr};  // raw block k landed in staging buffer k
+    hipEvent_t freed[2] = {nullptr, nullptr};   // staging buffer k consumed by the split
+};
+
 }  // namespace rk
 
 struct rocket_ctx {
@@ -107,6 +116,7 @@ struct rocket_ctx {
     rk::NccState ncc;
     rk::OvlState ovl;
     rk::SpState sp;
+    rk::OocState ooc;
     rocket_stats stats = {};
     int64_t ledger_items = 0;
     hipEvent_t ev_begin = nullptr, ev_end = nullptr;  // main-kernel timing (ROCKET_OPT_TIMING)
@@ -144,6 +154,8 @@ void single_segment(std::vector<int> &seg, int64_t nitems);
 // Per pair-function modules.
 rocket_status ncc_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, int scheme, hipStream_t s);
 rocket_status ncc_compare(rocket_ctx *ctx, float *out, hipStream_t s);
+rocket_status ncc_allpairs_host(rocket_ctx *ctx, const float *host, int64_t n, int64_t dim, int64_t ld, int scheme,
+                                float *out, hipStream_t s);
 rocket_status ovl_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, int mode, hipStream_t s);
 rocket_status ovl_compare(rocket_ctx *ctx, float *out, const float *centroids, const float *params, float *grad,
                           hipStream_t s);

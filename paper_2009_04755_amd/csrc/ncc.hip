@@ -3,8 +3,12 @@
 // rho_ij = <a_i - mu_i, a_j - mu_j> / (s_i s_j), s = centred L2 norm.  Stages:
 //   k_ncc_stats   per item: mean and centred norm, FP64 (one pass with a shift)
 //   k_ncc_split   per item: centred values in FP32, split into bf16 planes (or kept FP32),
-//                 written K16-major: element (r, k) at ((k/16) * n_pad + r) * 16 + k%16, so the
-//                 16-deep K slice of any row block is one contiguous chunk
+//                 stored block-major, then by 16-deep K slice, then by component: rows are
+//                 grouped in blocks of T (the tile edge) and element (r, k) of component c
+//                 of block b sits at element ((b * nkt + k/16) * NC + c) * T * 16 + (r%T) * 16
+//                 + k%16, so one K slice of a block (all components) is one contiguous run
+//                 and a block is one contiguous region.  The out-of-core path's device
+//                 cache slots have exactly this block layout.
 //   k_ncc_gram    persistent: pops (tile, K chunk) items, stages both row blocks of every
 //                 16-deep K slice in LDS (double buffered) and accumulates the tile's Gram
 //                 block with MFMA, FP32 accumulation; writes one partial tile per item
@@ -116,18 +120,22 @@ __global__ __launch_bounds__(256) void k_ncc_stats(const float *__restrict__ X, 
 
 // ------------------------------------------------------------------------------------------
 // Centre and split.  Thread = (row r, four consecutive K slices): reads 64 contiguous values
-// of row r (256 bytes), writes for each slice kt 16 outputs per plane at ((kt * n_pad + r) *
-// 16), so consecutive threads write consecutive 32-byte (bf16) or 64-byte (fp32) runs.
-// grid.x = groups of four K slices, grid.y = groups of 256 rows.  Rows >= n and columns >= d
-// become zeros.
+// of row r (256 bytes), writes for each slice kt 16 outputs per plane at ((kt * T + r % T) *
+// 16) of block r / T, so consecutive threads write consecutive 32-byte (bf16) or 64-byte
+// (fp32) runs.  grid.x = groups of four K slices, grid.y = groups of 256 rows.  Rows >= n
+// (up to rows_pad) and columns >= d become zeros.
 // ------------------------------------------------------------------------------------------
 template <int SCH>
 __global__ __launch_bounds__(256) void k_ncc_split(const float *__restrict__ X, int64_t ld, int64_t d, int64_t n,
-                                                   const double *__restrict__ mu, int64_t n_pad, int64_t nkt,
-                                                   char *__restrict__ planes, int64_t plane_bytes)
+                                                   const double *__restrict__ mu, int64_t rows_pad, int64_t nkt,
+                                                   int64_t T, char *__restrict__ planes)
 {
     const int64_t r = (int64_t)blockIdx.y * 256 + threadIdx.x;
-    if (r >= n_pad) return;
+    if (r >= rows_pad) return;
+    const int64_t blk = r / T, rr = r - blk * T;
+    constexpr int NC = Scheme<SCH>::NC;
+    const int64_t plane_bytes = T * 16 * Scheme<SCH>::ES;  // one component of one K slice of a block
+    planes += blk * nkt * NC * plane_bytes;
     const bool vec = ((ld & 3) == 0) && ((((uintptr_t)X) & 15) == 0);
     const double m = r < n ? mu[r] : 0.0;
 #pragma unroll
@@ -155,7 +163,7 @@ __global__ __launch_bounds__(256) void k_ncc_split(const float *__restrict__ X, 
                     if (k0 + e < d) x[e] = (float)((double)a[e] - m);
             }
         }
-        const int64_t dst = (kt * n_pad + r) * 16;
+        const int64_t dst = (kt * NC * T + rr) * 16;
         if constexpr (SCH == SCH_FP32) {
             float4 *p = (float4 *)((float *)planes + dst);
 #pragma unroll
@@ -228,10 +236,8 @@ typedef __attribute__((address_space(1))) void *gbl_ptr_t;
 // Output block layout (both): acc[r] of lane l is row 8*(r/4) + 4*(l/32) + r%4, col l%32.
 // ------------------------------------------------------------------------------------------
 template <int BM, int BN, int SCH>
-__global__ __launch_bounds__(256, 1) void k_ncc_gram(const char *__restrict__ planes,
-                                                                     int64_t plane_bytes, int64_t n_pad,
-                                                                     int kt_per_chunk, int nkt, int nchunks,
-                                                                     QueueArgs q, float *__restrict__ partial)
+__global__ __launch_bounds__(256, 1) void k_ncc_gram(const char *__restrict__ planes, int kt_per_chunk, int nkt,
+                                                     int nchunks, QueueArgs q, float *__restrict__ partial)
 {
     constexpr int NC = Scheme<SCH>::NC, ES = Scheme<SCH>::ES;
     constexpr int ROWB = 16 * ES;
@@ -284,7 +290,10 @@ __global__ __launch_bounds__(256, 1) void k_ncc_gram(const char *__restrict__ pl
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[m][n][r] = 0.f;
 
-        const int64_t rowA = (int64_t)bi * BM, rowB = (int64_t)bj * BM + (int64_t)(slot % HALVES) * BN;
+        // block-major operands: slice kt, component c, row r of block b at
+        // planes + ((b*nkt + kt)*NC + c)*BM*ROWB + r*ROWB
+        const char *baseA = planes + (int64_t)bi * nkt * (NC * BM * ROWB);
+        const char *baseB = planes + (int64_t)bj * nkt * (NC * BM * ROWB) + (int64_t)(slot % HALVES) * BN * ROWB;
 
         // Copy of K slice kt into dstbuf: this wave moves 1 KiB blocks wv, wv+4, ...; the
         // block's source base is wave-uniform (scalar registers), the lane adds its own
@@ -299,7 +308,7 @@ __global__ __launch_bounds__(256, 1) void k_ncc_gram(const char *__restrict__ pl
                 const int rb = (side ? inb - TA : inb) / ROWB;
                 const int row = rb + lrow;
                 const int loff = lrow * ROWB + ((pseg ^ swz<SEGS>(row)) * 16);
-                const char *sbase = planes + comp * plane_bytes + (((int64_t)kt * n_pad + (side ? rowB : rowA) + rb) * ROWB);
+                const char *sbase = (side ? baseB : baseA) + (int64_t)kt * (NC * BM * ROWB) + (comp * BM + rb) * ROWB;
                 __builtin_amdgcn_global_load_lds((gbl_ptr_t)(sbase + loff), (lds_ptr_t)(dstbuf + b * 1024), 16, 0, 0);
             }
         };
@@ -562,6 +571,26 @@ int es_of(int sch) { return sch == SCH_FP32 ? 4 : 2; }
 
 }  // namespace
 
+static int ncc_tile(rocket_ctx *ctx, int64_t n)
+{
+    const int bm = (int)ctx->opt[ROCKET_OPT_NCC_TILE];
+    return bm ? bm : n >= 1536 ? 256 : n >= 384 ? 128 : 64;
+}
+
+// Split-K chunk length: enough chunks for ~2048 work items, within [256, 2048] elements.
+static int64_t ncc_kchunk(rocket_ctx *ctx, int64_t d_pad, int64_t tiles)
+{
+    int64_t kc = ctx->opt[ROCKET_OPT_NCC_KCHUNK];
+    if (!kc) {
+        const int64_t want_chunks = std::max<int64_t>(1, (2048 + tiles - 1) / std::max<int64_t>(tiles, 1));
+        kc = round_up((d_pad + want_chunks - 1) / want_chunks, 16);
+        // FP32 accumulation error of a chunk grows like sqrt(chunk length): 2048-element
+        // chunks keep it well inside 1e-5 of the dot product's error scale at 2^20 elements
+        kc = std::max<int64_t>(256, std::min<int64_t>(kc, 2048));
+    }
+    return std::min<int64_t>(kc, d_pad);
+}
+
 rocket_status ncc_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, int scheme, hipStream_t s)
 {
     if (n > 0 && !it->dense) return fail(ctx, ROCKET_E_INVALID, "dense is NULL");
@@ -574,8 +603,7 @@ rocket_status ncc_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, in
     st.ld = it->ld;
     st.src = it->dense;
     st.scheme = scheme;
-    int bm = (int)ctx->opt[ROCKET_OPT_NCC_TILE];
-    if (!bm) bm = n >= 1536 ? 256 : n >= 384 ? 128 : 64;
+    const int bm = ncc_tile(ctx, n);
     st.tile = bm;
     st.n_pad = round_up(std::max<int64_t>(n, 1), bm);
     st.d_pad = round_up(it->dim, 16);
@@ -590,15 +618,7 @@ rocket_status ncc_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, in
         pc.pc_nchunks = -1;
     }
     st.tiles = (int64_t)pc.h_tiles.size();
-    int64_t kc = ctx->opt[ROCKET_OPT_NCC_KCHUNK];
-    if (!kc) {
-        const int64_t want_chunks = std::max<int64_t>(1, (2048 + st.tiles - 1) / std::max<int64_t>(st.tiles, 1));
-        kc = round_up((st.d_pad + want_chunks - 1) / want_chunks, 16);
-        // FP32 accumulation error of a chunk grows like sqrt(chunk length): 2048-element
-        // chunks keep it well inside 1e-5 of the dot product's error scale at 2^20 elements
-        kc = std::max<int64_t>(256, std::min<int64_t>(kc, 2048));
-    }
-    kc = std::min<int64_t>(kc, st.d_pad);
+    const int64_t kc = ncc_kchunk(ctx, st.d_pad, st.tiles);
     st.kt_per_chunk = (int)(kc / 16);
     st.nchunks = (int)((st.nkt + st.kt_per_chunk - 1) / st.kt_per_chunk);
     const int halves = 1;  // column slices per tile (the kernels use square blocks)
@@ -641,35 +661,62 @@ rocket_status ncc_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, in
     const dim3 g((unsigned)((st.nkt + 3) / 4), (unsigned)((st.n_pad + 255) / 256));
     if (scheme == SCH_FP32)
         hipLaunchKernelGGL(k_ncc_split<SCH_FP32>, g, dim3(256), 0, s, it->dense, it->ld, it->dim, n, mu, st.n_pad,
-                           (int64_t)st.nkt, (char *)planes, plane_bytes);
+                           (int64_t)st.nkt, (int64_t)bm, (char *)planes);
     else if (scheme == SCH_X3)
         hipLaunchKernelGGL(k_ncc_split<SCH_X3>, g, dim3(256), 0, s, it->dense, it->ld, it->dim, n, mu, st.n_pad,
-                           (int64_t)st.nkt, (char *)planes, plane_bytes);
+                           (int64_t)st.nkt, (int64_t)bm, (char *)planes);
     else
         hipLaunchKernelGGL(k_ncc_split<SCH_X6>, g, dim3(256), 0, s, it->dense, it->ld, it->dim, n, mu, st.n_pad,
-                           (int64_t)st.nkt, (char *)planes, plane_bytes);
+                           (int64_t)st.nkt, (int64_t)bm, (char *)planes);
     RK_HIP(hipGetLastError());
     return ROCKET_OK;
 }
 
 template <int BM, int SCH>
-static void launch_gram(int grid, hipStream_t s, const char *planes, int64_t pb, const NccState &st,
-                        const QueueArgs &qa, float *partial)
+static void launch_gram(int grid, hipStream_t s, const char *planes, const NccState &st, const QueueArgs &qa,
+                        float *partial)
 {
-    hipLaunchKernelGGL((k_ncc_gram<BM, bn_of<BM>(), SCH>), dim3(grid), dim3(256), 0, s, planes, pb, st.n_pad, st.kt_per_chunk,
+    hipLaunchKernelGGL((k_ncc_gram<BM, bn_of<BM>(), SCH>), dim3(grid), dim3(256), 0, s, planes, st.kt_per_chunk,
                        st.nkt, st.nchunks, qa, partial);
 }
 
 template <int SCH>
-static void launch_gram_bm(int grid, hipStream_t s, const char *planes, int64_t pb, const NccState &st,
-                           const QueueArgs &qa, float *partial)
+static void launch_gram_bm(int grid, hipStream_t s, const char *planes, const NccState &st, const QueueArgs &qa,
+                           float *partial)
 {
     if (st.tile == 64)
-        launch_gram<64, SCH>(grid, s, planes, pb, st, qa, partial);
+        launch_gram<64, SCH>(grid, s, planes, st, qa, partial);
     else if (st.tile == 128)
-        launch_gram<128, SCH>(grid, s, planes, pb, st, qa, partial);
+        launch_gram<128, SCH>(grid, s, planes, st, qa, partial);
     else
-        launch_gram<256, SCH>(grid, s, planes, pb, st, qa, partial);
+        launch_gram<256, SCH>(grid, s, planes, st, qa, partial);
+}
+
+static void launch_gram_any(int grid, hipStream_t s, const char *planes, const NccState &st, const QueueArgs &qa,
+                            float *partial)
+{
+    if (st.scheme == SCH_FP32)
+        launch_gram_bm<SCH_FP32>(grid, s, planes, st, qa, partial);
+    else if (st.scheme == SCH_X3)
+        launch_gram_bm<SCH_X3>(grid, s, planes, st, qa, partial);
+    else
+        launch_gram_bm<SCH_X6>(grid, s, planes, st, qa, partial);
+}
+
+static void launch_finish(hipStream_t s, const NccState &st, int64_t ntiles, const float *partial, const int2 *tiles,
+                          const float *inv_s, float *out)
+{
+    const int bm = st.tile;
+    const int64_t blocks = ntiles * (int64_t)bm * bm / 1024;  // every slice of every tile
+    if (bm == 64)
+        hipLaunchKernelGGL((k_ncc_finish<64, 64>), dim3((unsigned)blocks), dim3(256), 0, s, partial, tiles,
+                           st.nchunks, st.n, inv_s, out);
+    else if (bm == 128)
+        hipLaunchKernelGGL((k_ncc_finish<128, 128>), dim3((unsigned)blocks), dim3(256), 0, s, partial, tiles,
+                           st.nchunks, st.n, inv_s, out);
+    else
+        hipLaunchKernelGGL((k_ncc_finish<256, 256>), dim3((unsigned)blocks), dim3(256), 0, s, partial, tiles,
+                           st.nchunks, st.n, inv_s, out);
 }
 
 rocket_status ncc_compare(rocket_ctx *ctx, float *out, hipStream_t s)
@@ -686,29 +733,232 @@ rocket_status ncc_compare(rocket_ctx *ctx, float *out, hipStream_t s)
     const int grid = auto_grid(ctx, gram_kernel(bm, st.scheme), 256, 0, st.items);
     ctx->stats.grid = grid;
     const char *planes = (const char *)ctx->ws[WS_NCC_PLANES].ptr;
-    const int64_t pb = st.n_pad * st.d_pad * es_of(st.scheme);
     RK_TRY(timing_begin(ctx, s));
-    if (st.scheme == SCH_FP32)
-        launch_gram_bm<SCH_FP32>(grid, s, planes, pb, st, pc.qa, (float *)partial);
-    else if (st.scheme == SCH_X3)
-        launch_gram_bm<SCH_X3>(grid, s, planes, pb, st, pc.qa, (float *)partial);
-    else
-        launch_gram_bm<SCH_X6>(grid, s, planes, pb, st, pc.qa, (float *)partial);
+    launch_gram_any(grid, s, planes, st, pc.qa, (float *)partial);
     RK_HIP(hipGetLastError());
     RK_TRY(timing_end(ctx, s));
     const float *inv_s = (const float *)((char *)ctx->ws[WS_NCC_STATS].ptr + (((size_t)st.n * 8 + 255) & ~(size_t)255));
-    const int2 *tiles = (const int2 *)ctx->ws[WS_NCC_TILES].ptr;
-    const int64_t blocks = st.tiles * (int64_t)bm * bm / 1024;  // every slice of every tile
-    if (bm == 64)
-        hipLaunchKernelGGL((k_ncc_finish<64, 64>), dim3((unsigned)blocks), dim3(256), 0, s, (const float *)partial, tiles,
-                           st.nchunks, st.n, inv_s, out);
-    else if (bm == 128)
-        hipLaunchKernelGGL((k_ncc_finish<128, 128>), dim3((unsigned)blocks), dim3(256), 0, s, (const float *)partial, tiles,
-                           st.nchunks, st.n, inv_s, out);
-    else
-        hipLaunchKernelGGL((k_ncc_finish<256, 256>), dim3((unsigned)blocks), dim3(256), 0, s, (const float *)partial, tiles,
-                           st.nchunks, st.n, inv_s, out);
+    launch_finish(s, st, st.tiles, (const float *)partial, (const int2 *)ctx->ws[WS_NCC_TILES].ptr, inv_s, out);
     RK_HIP(hipGetLastError());
+    return ROCKET_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// Out-of-core all pairs (Section IV-A: a device cache of fixed-size slots, least recently
+// used slot evicted on a miss, refilled from the next level, here the caller's host array).
+// The cached unit is a block of `tile` items in split form (the GPU pre-process stage of the
+// items); jobs are the divide-and-conquer leaf tiles in visiting order, which is what gives
+// the cache its hits.  The host plans the whole schedule first: the LRU decisions fix a
+// sequence of block loads and tile batches; a batch is cut where a load must evict a slot
+// that the batch still reads.  On the device, loads run as host-to-device copies on a copy
+// stream into two raw staging buffers, and stats + split on the caller's stream write the
+// slot; each batch is one persistent Gram launch over its tiles' K chunks (items name slots,
+// not blocks) plus the epilogue.  Copies run ahead of compute by up to two blocks.  Kernels,
+// chunking and summation order are those of the in-core path, so results are identical.
+// ------------------------------------------------------------------------------------------
+namespace {
+
+struct OocBatch {
+    int64_t item0, nitems, tile0, ntiles;
+};
+
+struct OocOp {
+    int batch;  // >= 0: run that batch; -1: load `block` into `slot`
+    int block, slot;
+};
+
+}  // namespace
+
+rocket_status ncc_allpairs_host(rocket_ctx *ctx, const float *host, int64_t n, int64_t dim, int64_t ld, int scheme,
+                                float *out, hipStream_t s)
+{
+    if (n < 0) return fail(ctx, ROCKET_E_INVALID, "n < 0");
+    if (n > 0 && !host) return fail(ctx, ROCKET_E_INVALID, "host items pointer is NULL");
+    if (dim < 1) return fail(ctx, ROCKET_E_INVALID, "dim < 1");
+    if (ld < dim) return fail(ctx, ROCKET_E_INVALID, "ld < dim");
+    if (n > (int64_t)1 << 24) return fail(ctx, ROCKET_E_INVALID, "n too large");
+    if (n >= 2 && !out) return fail(ctx, ROCKET_E_INVALID, "out is NULL");
+    NccState &st = ctx->ncc;
+    // the plane workspace now holds cache slots and the queue holds this schedule
+    st.pc_n = -1;
+    ctx->queue_owner = QOWN_NONE;
+    st.n = n;
+    st.dim = dim;
+    st.ld = ld;
+    st.src = nullptr;
+    st.scheme = scheme;
+    const int T = ncc_tile(ctx, n);
+    st.tile = T;
+    st.n_pad = round_up(std::max<int64_t>(n, 1), T);
+    st.d_pad = round_up(dim, 16);
+    st.nkt = (int)(st.d_pad / 16);
+    std::vector<int2> leaves;
+    plan_leaves(n, T, leaves);
+    st.tiles = (int64_t)leaves.size();
+    const int64_t kc = ncc_kchunk(ctx, st.d_pad, st.tiles);
+    st.kt_per_chunk = (int)(kc / 16);
+    st.nchunks = (int)((st.nkt + st.kt_per_chunk - 1) / st.kt_per_chunk);
+    st.items = st.tiles * st.nchunks;
+    ctx->stats.tiles = st.tiles;
+    ctx->stats.work_items = st.items;
+    ctx->stats.tile = T;
+    ctx->stats.kchunk = kc;
+    ctx->stats.variant = scheme;
+    ctx->stats.cache_slots = 0;
+    ctx->stats.cache_loads = 0;
+    if (st.items > INT32_MAX / 2) return fail(ctx, ROCKET_E_INVALID, "too many work items");
+    if (n < 2) return ROCKET_OK;
+
+    const int64_t nb = (n + T - 1) / T;
+    int64_t S = ctx->opt[ROCKET_OPT_CACHE_SLOTS] ? ctx->opt[ROCKET_OPT_CACHE_SLOTS] : nb;
+    S = std::min<int64_t>(S, nb);
+    if (nb >= 2 && S < 2) return fail(ctx, ROCKET_E_INVALID, "the device cache needs at least 2 slots");
+    const int64_t rowb = 16 * es_of(scheme);
+    const int64_t comp_bytes = (int64_t)st.nkt * T * rowb;
+    const int64_t slot_bytes = nc_of(scheme) * comp_bytes;
+    const int64_t tile_partial = (int64_t)st.nchunks * T * T * 4;
+    const int64_t max_batch = std::max<int64_t>(1, std::min<int64_t>(64, ((int64_t)2 << 30) / tile_partial));
+
+    // --- schedule: LRU over the slots, visiting the leaves in order --------------------------
+    std::vector<int64_t> holder(S, -1), last(S, -1), where(nb, -1);
+    std::vector<char> in_batch(S, 0);
+    std::vector<OocOp> ops;
+    std::vector<OocBatch> batches;
+    std::vector<int2> bt_slots, bt_tiles;  // open batch: slot pairs, block pairs
+    std::vector<int2> all_tiles;           // every batch's block pairs, batch after batch
+    std::vector<int4> all_items;
+    std::vector<int> all_segs;
+    std::vector<int4> bi_items;
+    std::vector<int> bi_seg;
+    int64_t clock = 0, loads = 0;
+    auto close_batch = [&]() {
+        if (bt_slots.empty()) return;
+        plan_chunked(bt_slots, st.nchunks, MAX_SEG, bi_items, bi_seg, 1);
+        OocBatch b;
+        b.item0 = (int64_t)all_items.size();
+        b.nitems = (int64_t)bi_items.size();
+        b.tile0 = (int64_t)all_tiles.size();
+        b.ntiles = (int64_t)bt_tiles.size();
+        all_items.insert(all_items.end(), bi_items.begin(), bi_items.end());
+        all_segs.insert(all_segs.end(), bi_seg.begin(), bi_seg.end());
+        all_tiles.insert(all_tiles.end(), bt_tiles.begin(), bt_tiles.end());
+        ops.push_back({(int)batches.size(), -1, -1});
+        batches.push_back(b);
+        bt_slots.clear();
+        bt_tiles.clear();
+        std::fill(in_batch.begin(), in_batch.end(), 0);
+    };
+    for (const int2 &lf : leaves) {
+        const int need[2] = {lf.x, lf.y};
+        const int nneed = lf.x == lf.y ? 1 : 2;
+        for (int q = 0; q < nneed; ++q) {
+            const int b = need[q];
+            ++clock;
+            if (where[b] >= 0) {
+                last[where[b]] = clock;
+                continue;
+            }
+            const int64_t keep = nneed == 2 ? where[need[1 - q]] : -1;
+            int64_t v = -1;
+            for (int64_t k = 0; k < S && v < 0; ++k)
+                if (holder[k] < 0) v = k;
+            if (v < 0)
+                for (int64_t k = 0; k < S; ++k)
+                    if (k != keep && (v < 0 || last[k] < last[v])) v = k;
+            if (in_batch[v]) close_batch();  // the open batch still reads the victim
+            if (holder[v] >= 0) where[holder[v]] = -1;
+            holder[v] = b;
+            where[b] = v;
+            last[v] = clock;
+            ops.push_back({-1, b, (int)v});
+            ++loads;
+        }
+        bt_slots.push_back(make_int2((int)where[lf.x], (int)where[lf.y]));
+        bt_tiles.push_back(lf);
+        in_batch[where[lf.x]] = in_batch[where[lf.y]] = 1;
+        if ((int64_t)bt_slots.size() >= max_batch) close_batch();
+    }
+    close_batch();
+    ctx->stats.cache_slots = S;
+    ctx->stats.cache_loads = loads;
+
+    // --- device buffers ------------------------------------------------------------------
+    void *slots = nullptr, *stage = nullptr, *stats = nullptr, *partial = nullptr, *tiles = nullptr, *items = nullptr,
+         *segs = nullptr, *heads = nullptr;
+    const int64_t stage_bytes = (int64_t)T * ld * 4;
+    RK_TRY(ws_get(ctx, WS_NCC_PLANES, (size_t)(S * slot_bytes), &slots));
+    RK_TRY(ws_get(ctx, WS_OOC_STAGE, (size_t)(2 * stage_bytes), &stage));
+    RK_TRY(ws_get(ctx, WS_NCC_STATS, (size_t)n * 12 + 64, &stats));
+    int64_t maxb = 0;
+    for (const OocBatch &b : batches) maxb = std::max(maxb, b.ntiles);
+    RK_TRY(ws_get(ctx, WS_NCC_PARTIAL, (size_t)(maxb * tile_partial), &partial));
+    RK_TRY(ws_get(ctx, WS_NCC_TILES, sizeof(int2) * all_tiles.size(), &tiles));
+    RK_TRY(ws_get(ctx, WS_QUEUE_ITEMS, sizeof(int4) * all_items.size(), &items));
+    RK_TRY(ws_get(ctx, WS_QUEUE_SEGS, sizeof(int) * all_segs.size(), &segs));
+    RK_TRY(ws_get(ctx, WS_QUEUE_HEADS, sizeof(int) * HEAD_STRIDE * MAX_SEG, &heads));
+    RK_HIP(hipMemcpyAsync(tiles, all_tiles.data(), sizeof(int2) * all_tiles.size(), hipMemcpyHostToDevice, s));
+    RK_HIP(hipMemcpyAsync(items, all_items.data(), sizeof(int4) * all_items.size(), hipMemcpyHostToDevice, s));
+    RK_HIP(hipMemcpyAsync(segs, all_segs.data(), sizeof(int) * all_segs.size(), hipMemcpyHostToDevice, s));
+    RK_HIP(hipStreamSynchronize(s));  // the schedule vectors are local
+    OocState &oc = ctx->ooc;
+    if (!oc.copy) {
+        RK_HIP(hipStreamCreateWithFlags(&oc.copy, hipStreamNonBlocking));
+        RK_HIP(hipEventCreateWithFlags(&oc.start, hipEventDisableTiming));
+        for (int k = 0; k < 2; ++k) {
+            RK_HIP(hipEventCreateWithFlags(&oc.copied[k], hipEventDisableTiming));
+            RK_HIP(hipEventCreateWithFlags(&oc.freed[k], hipEventDisableTiming));
+        }
+    }
+    double *mu = (double *)stats;
+    float *inv_s = (float *)((char *)stats + (((size_t)n * 8 + 255) & ~(size_t)255));
+    const dim3 sg((unsigned)((st.nkt + 3) / 4), (unsigned)((T + 255) / 256));
+
+    // --- enqueue -------------------------------------------------------------------------
+    RK_HIP(hipEventRecord(oc.start, s));  // staging buffers are free once earlier work on s is done
+    RK_HIP(hipStreamWaitEvent(oc.copy, oc.start, 0));
+    RK_TRY(timing_begin(ctx, s));
+    int64_t m = 0;
+    for (const OocOp &op : ops) {
+        if (op.batch < 0) {
+            const int k = (int)(m & 1);
+            const int64_t r0 = (int64_t)op.block * T, rows = std::min<int64_t>(T, n - r0);
+            float *buf = (float *)((char *)stage + k * stage_bytes);
+            if (m >= 2) RK_HIP(hipStreamWaitEvent(oc.copy, oc.freed[k], 0));
+            RK_HIP(hipMemcpyAsync(buf, host + r0 * ld, (size_t)(rows * ld * 4), hipMemcpyHostToDevice, oc.copy));
+            RK_HIP(hipEventRecord(oc.copied[k], oc.copy));
+            RK_HIP(hipStreamWaitEvent(s, oc.copied[k], 0));
+            hipLaunchKernelGGL(k_ncc_stats, dim3((unsigned)rows), dim3(256), 0, s, buf, ld, dim, mu + r0, inv_s + r0);
+            char *dst = (char *)slots + op.slot * slot_bytes;
+            if (scheme == SCH_FP32)
+                hipLaunchKernelGGL(k_ncc_split<SCH_FP32>, sg, dim3(256), 0, s, buf, ld, dim, rows, mu + r0, (int64_t)T,
+                                   (int64_t)st.nkt, (int64_t)T, dst);
+            else if (scheme == SCH_X3)
+                hipLaunchKernelGGL(k_ncc_split<SCH_X3>, sg, dim3(256), 0, s, buf, ld, dim, rows, mu + r0, (int64_t)T,
+                                   (int64_t)st.nkt, (int64_t)T, dst);
+            else
+                hipLaunchKernelGGL(k_ncc_split<SCH_X6>, sg, dim3(256), 0, s, buf, ld, dim, rows, mu + r0, (int64_t)T,
+                                   (int64_t)st.nkt, (int64_t)T, dst);
+            RK_HIP(hipGetLastError());
+            RK_HIP(hipEventRecord(oc.freed[k], s));
+            ++m;
+        } else {
+            const OocBatch &b = batches[op.batch];
+            QueueArgs qa;
+            qa.items = (const int4 *)items + b.item0;
+            qa.heads = (int *)heads;
+            qa.seg = (const int *)segs + (int64_t)op.batch * (MAX_SEG + 1);
+            qa.ledger = nullptr;
+            qa.nseg = MAX_SEG;
+            RK_TRY(reset_queue(ctx, s, qa));
+            const int grid = auto_grid(ctx, gram_kernel(T, scheme), 256, 0, b.nitems);
+            ctx->stats.grid = grid;
+            launch_gram_any(grid, s, (const char *)slots, st, qa, (float *)partial);
+            RK_HIP(hipGetLastError());
+            launch_finish(s, st, b.ntiles, (const float *)partial, (const int2 *)tiles + b.tile0, inv_s, out);
+            RK_HIP(hipGetLastError());
+        }
+    }
+    RK_TRY(timing_end(ctx, s));
     return ROCKET_OK;
 }
 

@@ -194,6 +194,13 @@ void rocket_destroy(rocket_ctx *ctx)
         if (b.ptr) (void)hipFree(b.ptr);
     if (ctx->ev_begin) (void)hipEventDestroy(ctx->ev_begin);
     if (ctx->ev_end) (void)hipEventDestroy(ctx->ev_end);
+    rk::OocState &oc = ctx->ooc;
+    if (oc.copy) (void)hipStreamDestroy(oc.copy);
+    if (oc.start) (void)hipEventDestroy(oc.start);
+    for (int k = 0; k < 2; ++k) {
+        if (oc.copied[k]) (void)hipEventDestroy(oc.copied[k]);
+        if (oc.freed[k]) (void)hipEventDestroy(oc.freed[k]);
+    }
     (void)hipSetDevice(prev);
     delete ctx;
 }
@@ -215,6 +222,8 @@ rocket_status rocket_prepare(rocket_ctx *ctx, const rocket_items *items, int64_t
     if (!valid_fn(fn)) return rk::fail(ctx, ROCKET_E_UNSUPPORTED, "unknown pair function");
     hipStream_t s = (hipStream_t)stream;
     ctx->prepared_fn = 0;
+    ctx->stats.cache_slots = 0;
+    ctx->stats.cache_loads = 0;
     rocket_status st;
     switch (fn) {
     case ROCKET_NCC_FP32:
@@ -282,6 +291,20 @@ rocket_status rocket_allpairs(const rocket_items *items, int64_t n, rocket_pair_
     return ROCKET_OK;
 }
 
+rocket_status rocket_allpairs_host(rocket_ctx *ctx, const float *host_items, int64_t n, int64_t dim, int64_t ld,
+                                   rocket_pair_fn fn, float *out, void *stream)
+{
+    RK_TRY(enter(ctx));
+    if (fn != ROCKET_NCC_FP32 && fn != ROCKET_NCC_BF16X3 && fn != ROCKET_NCC_BF16X6)
+        return rk::fail(ctx, ROCKET_E_UNSUPPORTED, "host-resident items: NCC pair functions only");
+    ctx->prepared_fn = 0;  // the plane workspace is reused as the device cache
+    rocket_status st = rk::ncc_allpairs_host(ctx, host_items, n, dim, ld, (int)fn, out, (hipStream_t)stream);
+    ctx->stats.n = n;
+    ctx->stats.pairs = n > 1 ? n * (n - 1) / 2 : 0;
+    ctx->stats.workspace_bytes = rk::ws_total(ctx);
+    return st;
+}
+
 rocket_status rocket_overlap_cost_grad(rocket_ctx *ctx, const rocket_items *clouds, int64_t n, const float *centroids,
                                        const float *params, float *out_cost, float *out_grad, void *stream)
 {
@@ -310,7 +333,7 @@ rocket_status rocket_overlap_cost_grad(rocket_ctx *ctx, const rocket_items *clou
 rocket_status rocket_set_option(rocket_ctx *ctx, rocket_option opt, int64_t value)
 {
     if (!ctx) return rk::fail(nullptr, ROCKET_E_INVALID, "ctx is NULL");
-    if (opt < ROCKET_OPT_NCC_TILE || opt > ROCKET_OPT_TIMING) return rk::fail(ctx, ROCKET_E_UNSUPPORTED, "option");
+    if (opt < ROCKET_OPT_NCC_TILE || opt > ROCKET_OPT_CACHE_SLOTS) return rk::fail(ctx, ROCKET_E_UNSUPPORTED, "option");
     if (value < 0) return rk::fail(ctx, ROCKET_E_INVALID, "negative option value");
     if (opt == ROCKET_OPT_NCC_TILE && value != 0 && value != 64 && value != 128 && value != 256)
         return rk::fail(ctx, ROCKET_E_INVALID, "NCC tile must be 0, 64, 128 or 256");
@@ -326,7 +349,7 @@ rocket_status rocket_set_option(rocket_ctx *ctx, rocket_option opt, int64_t valu
 rocket_status rocket_get_option(const rocket_ctx *ctx, rocket_option opt, int64_t *value)
 {
     if (!ctx || !value) return rk::fail(nullptr, ROCKET_E_INVALID, "NULL argument");
-    if (opt < ROCKET_OPT_NCC_TILE || opt > ROCKET_OPT_TIMING) return ROCKET_E_UNSUPPORTED;
+    if (opt < ROCKET_OPT_NCC_TILE || opt > ROCKET_OPT_CACHE_SLOTS) return ROCKET_E_UNSUPPORTED;
     *value = ctx->opt[opt];
     return ROCKET_OK;
 }

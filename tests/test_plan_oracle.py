@@ -55,3 +55,26 @@ def test_packed_index_is_dense_row_major():
     n = 13
     pi, pj = oracle.all_pairs(n)
     assert [oracle.packed_index(i, j, n) for i, j in zip(pi, pj)] == list(range(pi.size))
+
+
+def _golden_loads(name):
+    rows = [l.split() for l in open(os.path.join(GOLDEN, name)) if l.strip() and not l.startswith("#")]
+    return [(int(a), int(b)) for a, b in rows]
+
+
+def test_lru_hand_worked_example():
+    count, loads = plan.lru_loads(4, 1, 2)
+    assert loads == _golden_loads("lru_n4_T1_S2.txt") and count == 8
+
+
+@pytest.mark.parametrize("n,T", [(4096, 256), (700, 128), (300, 64), (1000, 7), (2, 64)])
+def test_lru_bounds(n, T):
+    nb = (n + T - 1) // T
+    leaves = plan.quadtree_leaves(n, T)
+    for S in range(1 if nb == 1 else 2, nb + 3):
+        count, loads = plan.lru_loads(n, T, S)
+        assert nb <= count <= 2 * len(leaves)
+        if S >= nb:
+            assert count == nb  # everything fits: each block loaded exactly once
+        assert sorted({b for b, _ in loads}) == list(range(nb))  # every block is loaded
+        assert all(0 <= s < S for _, s in loads)
