@@ -16,7 +16,9 @@
  *                    work stealing, mapped onto the chip);
  *   rocket_allpairs  both, back to back;
  *   rocket_allpairs_host  the same for NCC items that stay in host memory and
- *                    pass through a fixed-size device cache (Section IV-A).
+ *                    pass through a fixed-size device cache (Section IV-A);
+ *   rocket_cv_build  the GPU pre-process of the sparse application: protein
+ *                    sequences to composition vectors (Section V-B).
  *
  * Three pair functions are provided, one per application of Section V:
  *   ROCKET_NCC_*          normalised cross-correlation of dense vectors (V-A);
@@ -162,6 +164,22 @@ rocket_status rocket_allpairs_ex(rocket_ctx *ctx, const rocket_items *items, int
  * library-owned default context per device and the null stream; synchronises
  * before returning.  out: float32 [n(n-1)/2]. */
 rocket_status rocket_allpairs(const rocket_items *items, int64_t n, rocket_pair_fn fn, float *out_upper_triangle);
+
+/* Composition vectors (the GPU pre-process stage of Section V-B's application): for each
+ * species, the K-string composition vector of Qi, Wang and Hao over its proteins,
+ *     f(s) = n(s) / N_K,  f0(s) = f(s_1..s_{K-1}) f(s_2..s_K) / f(s_2..s_{K-1}),
+ *     a(s) = (f(s) - f0(s)) / f0(s),
+ * n(s) the occurrences of K-string s in windows of K residues inside one protein, N_k the
+ * number of such windows of length k (FP64, rounded once to float32).  One entry per
+ * K-string that occurs, keyed by its base-20 code (s_1 most significant), keys ascending.
+ * residues: uint8 codes, 0..19 amino acids; any code >= 20 ends a protein (no window
+ * spans it).  offsets: int64 [n+1], species s owns residues offsets[s]..offsets[s+1]-1.
+ * K: 3..6.  Outputs form a ROCKET_SPARSE_COSINE item set: cv_offsets int64 [n+1], keys
+ * int64 and vals float32 of `capacity` entries; capacity >= offsets[n] always suffices
+ * (ROCKET_E_INVALID if the entries do not fit).  Reads offsets to the host and
+ * synchronises once at the start and once at the end. */
+rocket_status rocket_cv_build(rocket_ctx *ctx, const uint8_t *residues, const int64_t *offsets, int64_t n, int K,
+                              int64_t *cv_offsets, int64_t *keys, float *vals, int64_t capacity, void *stream);
 
 /* Out-of-core all pairs for the NCC functions: items stay in HOST memory (float32
  * [n][ld], row-major; page-locked memory lets copies run asynchronously) and pass

@@ -26,7 +26,8 @@ OPT = {"ncc_tile": 1, "ncc_kchunk": 2, "grid": 3, "queue_order": 4, "seed": 5, "
 
 # every symbol include/rocket.h declares
 SYMBOLS = ["rocket_create", "rocket_destroy", "rocket_status_str", "rocket_last_error", "rocket_prepare",
-           "rocket_compare", "rocket_allpairs_ex", "rocket_allpairs", "rocket_allpairs_host", "rocket_overlap_cost_grad",
+           "rocket_compare", "rocket_allpairs_ex", "rocket_allpairs", "rocket_allpairs_host", "rocket_cv_build",
+           "rocket_overlap_cost_grad",
            "rocket_set_option", "rocket_get_option", "rocket_get_stats", "rocket_get_ledger", "rocket_autotune",
            "rocket_plan_tiles", "rocket_pair_index"]
 
@@ -82,6 +83,8 @@ def load():
     L.rocket_allpairs.restype = I32
     L.rocket_allpairs_host.argtypes = [P, P, I64, I64, I64, I32, P, P]
     L.rocket_allpairs_host.restype = I32
+    L.rocket_cv_build.argtypes = [P, P, P, I64, I32, P, P, P, I64, P]
+    L.rocket_cv_build.restype = I32
     L.rocket_overlap_cost_grad.argtypes = [P, IT, I64, P, P, P, P, P]
     L.rocket_overlap_cost_grad.restype = I32
     L.rocket_set_option.argtypes = [P, I32, I64]

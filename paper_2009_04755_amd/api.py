@@ -173,6 +173,21 @@ class Context:
                                                     _ptr(out), _stream()), self.handle)
         return out
 
+    def cv_build(self, residues, offsets, K: int = 6):
+        """Composition vectors of n species (uint8 residue codes on the device, int64
+        offsets [n+1]) as a :class:`SparseSet` ready for ``sparse_cosine``."""
+        assert residues.dtype == torch.uint8 and residues.is_cuda and offsets.dtype == torch.int64
+        n = offsets.numel() - 1
+        cap = max(int(residues.numel()), 1)
+        dev = residues.device
+        cv_off = torch.empty(n + 1, dtype=torch.int64, device=dev)
+        keys = torch.empty(cap, dtype=torch.int64, device=dev)
+        vals = torch.empty(cap, dtype=torch.float32, device=dev)
+        _lib.check(_lib.load().rocket_cv_build(self.handle, _ptr(residues), _ptr(offsets), n, K, _ptr(cv_off),
+                                               _ptr(keys), _ptr(vals), cap, _stream()), self.handle)
+        total = int(cv_off[-1].item()) if n > 0 else 0
+        return SparseSet(cv_off, keys[:total], vals[:total])
+
     def autotune(self):
         _lib.check(_lib.load().rocket_autotune(self.handle, _stream()), self.handle)
         return {k: self.get(k) for k in ("ovl_block", "ovl_variant")}

@@ -31,6 +31,8 @@ enum Slot {
     WS_SP_CHUNKS,        // band histogram over key micro-chunks + chunk counts
     WS_SP_CSHIFT,        // per band start of its chunk boundaries
     WS_SP_BOUNDS,        // chunk boundaries (micro-chunk indices)
+    WS_CV_K,             // dense K-string counts of a group of species (kept zeroed between calls)
+    WS_CV_AUX,           // (K-1)- and (K-2)-string counts, chunk occupancy, totals
     WS_COUNT
 };
 
@@ -96,6 +98,13 @@ struct SpState {
     bool valid = false;
 };
 
+// Composition-vector builder: whether the dense K-string count array is all zeros.
+struct CvState {
+    bool clean = false;
+    int K = 0;
+    int64_t G = 0;
+};
+
 // Out-of-core state: copy stream and the events that order it against the compute stream.
 struct OocState {
     hipStream_t copy = nullptr;
@@ -117,6 +126,7 @@ struct rocket_ctx {
     rk::OvlState ovl;
     rk::SpState sp;
     rk::OocState ooc;
+    rk::CvState cv;
     rocket_stats stats = {};
     int64_t ledger_items = 0;
     hipEvent_t ev_begin = nullptr, ev_end = nullptr;  // main-kernel timing (ROCKET_OPT_TIMING)
@@ -162,6 +172,8 @@ rocket_status ovl_compare(rocket_ctx *ctx, float *out, const float *centroids, c
 rocket_status ovl_autotune(rocket_ctx *ctx, hipStream_t s);
 rocket_status sp_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, hipStream_t s);
 rocket_status sp_compare(rocket_ctx *ctx, float *out, uint32_t *counts, hipStream_t s);
+rocket_status cv_build(rocket_ctx *ctx, const uint8_t *res, const int64_t *offsets, int64_t n, int K,
+                       int64_t *cv_off, int64_t *keys, float *vals, int64_t capacity, hipStream_t s);
 
 }  // namespace rk
 

@@ -1,0 +1,280 @@
+// Composition vectors of protein K-strings on the GPU (Section V-B pre-process), the
+// K-string composition approach of Qi, Wang and Hao:
+//   f(s) = n(s) / N_K over all windows of K residues inside one protein,
+//   f0(s) = f(s_1..s_{K-1}) f(s_2..s_K) / f(s_2..s_{K-1}),   a(s) = (f(s) - f0(s)) / f0(s),
+// one entry per K-string that occurs, keyed by its base-20 code, keys ascending.
+//
+// Species are processed in groups.  Per species the counts of K-, (K-1)- and (K-2)-strings
+// are dense arrays over the code space (20^K u32; 256 MB at K = 6) filled with atomics,
+// one thread per window start; a K-string's first occurrence also bumps the occupancy
+// count of its 1024-code chunk.  A scan of the chunk counts gives every chunk its output
+// base; an emit pass streams the dense K array chunk by chunk, ranks the non-zero codes
+// with a workgroup prefix sum (so keys come out ascending), writes key and a(s) (FP64,
+// rounded once to f32) and writes zeros back, so the K array is clean for the next group.
+#include <algorithm>
+#include <vector>
+
+#include "common.hpp"
+
+namespace rk {
+namespace {
+
+constexpr int CV_ALPHA = 20;
+constexpr int CV_CHLOG = 10;  // 1024 codes per chunk
+constexpr int CV_CH = 1 << CV_CHLOG;
+constexpr int64_t CV_GROUP_BYTES = (int64_t)4 << 30;  // count arrays in flight
+
+__host__ __device__ inline int64_t ipow20(int k)
+{
+    int64_t v = 1;
+    for (int i = 0; i < k; ++i) v *= CV_ALPHA;
+    return v;
+}
+
+__global__ void k_cv_zero(uint32_t *__restrict__ p, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+// Base-20 code of the window of k residues starting at p (all < 20), else -1.
+__device__ inline int64_t window_code(const uint8_t *__restrict__ res, int64_t p, int64_t end, int k)
+{
+    if (p + k > end) return -1;
+    int64_t c = 0;
+    for (int t = 0; t < k; ++t) {
+        const int r = res[p + t];
+        if (r >= CV_ALPHA) return -1;
+        c = c * CV_ALPHA + r;
+    }
+    return c;
+}
+
+// grid (x, group size): blockIdx.y = species s0 + y, threads stride over its window starts.
+// tot[3*y + {0,1,2}] accumulate N_K, N_{K-1}, N_{K-2}.
+__global__ __launch_bounds__(256) void k_cv_count(const uint8_t *__restrict__ res, const int64_t *__restrict__ off,
+                                                  int64_t s0, int K, uint32_t *__restrict__ cK,
+                                                  uint32_t *__restrict__ c1, uint32_t *__restrict__ c2,
+                                                  uint32_t *__restrict__ chunk_cnt, int64_t nchunks,
+                                                  unsigned long long *__restrict__ tot)
+{
+    const int y = blockIdx.y;
+    const int64_t b = off[s0 + y], e = off[s0 + y + 1];
+    const int64_t szK = ipow20(K), sz1 = szK / CV_ALPHA, sz2 = sz1 / CV_ALPHA;
+    uint32_t *cKy = cK + y * szK, *c1y = c1 + y * sz1, *c2y = c2 + y * sz2;
+    uint32_t *chy = chunk_cnt + y * nchunks;
+    unsigned nk = 0, n1 = 0, n2 = 0;
+    for (int64_t p = b + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < e; p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t w2 = window_code(res, p, e, K - 2);
+        if (w2 < 0) continue;  // a shorter window is a prefix of the longer ones
+        atomicAdd(c2y + w2, 1u);
+        ++n2;
+        if (p + K - 1 > e) continue;
+        const int r1 = res[p + K - 2];
+        if (r1 >= CV_ALPHA) continue;
+        const int64_t w1 = w2 * CV_ALPHA + r1;
+        atomicAdd(c1y + w1, 1u);
+        ++n1;
+        if (p + K > e) continue;
+        const int rK = res[p + K - 1];
+        if (rK >= CV_ALPHA) continue;
+        const int64_t wK = w1 * CV_ALPHA + rK;
+        if (atomicAdd(cKy + wK, 1u) == 0u) atomicAdd(chy + (wK >> CV_CHLOG), 1u);
+        ++nk;
+    }
+    // wave sums, one atomic per wave and total
+    for (int o = 32; o > 0; o >>= 1) {
+        nk += __shfl_xor(nk, o);
+        n1 += __shfl_xor(n1, o);
+        n2 += __shfl_xor(n2, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(tot + 3 * y, (unsigned long long)nk);
+        atomicAdd(tot + 3 * y + 1, (unsigned long long)n1);
+        atomicAdd(tot + 3 * y + 2, (unsigned long long)n2);
+    }
+}
+
+// One workgroup per species of the group: exclusive scan of its chunk counts in place,
+// total into nnz[y].
+__global__ __launch_bounds__(1024) void k_cv_scan(uint32_t *__restrict__ chunk_cnt, int64_t nchunks,
+                                                  int64_t *__restrict__ nnz)
+{
+    __shared__ int64_t part[1024];
+    uint32_t *c = chunk_cnt + blockIdx.x * nchunks;
+    const int64_t per = (nchunks + 1023) / 1024;
+    const int64_t a = threadIdx.x * per, z = std::min<int64_t>(nchunks, a + per);
+    int64_t s = 0;
+    for (int64_t i = a; i < z; ++i) s += c[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {  // inclusive Hillis-Steele scan of the thread sums
+        const int64_t v = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int64_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
+    for (int64_t i = a; i < z; ++i) {
+        const uint32_t v = c[i];
+        c[i] = (uint32_t)run;
+        run += v;
+    }
+    if (threadIdx.x == 1023) nnz[blockIdx.x] = part[1023];
+}
+
+// Output offsets of the group's species, in order (one thread; the group is small).
+__global__ void k_cv_base(const int64_t *__restrict__ nnz, int G, int64_t s0, int64_t *__restrict__ cv_off)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (s0 == 0) cv_off[0] = 0;
+    int64_t run = cv_off[s0];
+    for (int y = 0; y < G; ++y) {
+        run += nnz[y];
+        cv_off[s0 + y + 1] = run;
+    }
+}
+
+// grid (chunks, group size), 256 threads x 4 codes = one 1024-code chunk per workgroup.
+__global__ __launch_bounds__(256) void k_cv_emit(uint32_t *__restrict__ cK, const uint32_t *__restrict__ c1,
+                                                 const uint32_t *__restrict__ c2,
+                                                 const uint32_t *__restrict__ chunk_base, int64_t nchunks,
+                                                 const unsigned long long *__restrict__ tot,
+                                                 const int64_t *__restrict__ cv_off, int64_t s0, int K,
+                                                 int64_t *__restrict__ keys, float *__restrict__ vals,
+                                                 int64_t capacity, int *__restrict__ overflow)
+{
+    __shared__ int wsum[4];
+    const int y = blockIdx.y;
+    const int64_t szK = ipow20(K), sz1 = szK / CV_ALPHA, sz2 = sz1 / CV_ALPHA;
+    uint32_t *cKy = cK + y * szK;
+    const uint32_t *c1y = c1 + y * sz1, *c2y = c2 + y * sz2;
+    const int64_t code0 = ((int64_t)blockIdx.x << CV_CHLOG) + 4 * threadIdx.x;
+    uint32_t v[4] = {0u, 0u, 0u, 0u};
+    if (code0 + 3 < szK) {
+        const uint4 q = *(const uint4 *)(cKy + code0);
+        v[0] = q.x;
+        v[1] = q.y;
+        v[2] = q.z;
+        v[3] = q.w;
+    } else {
+        for (int t = 0; t < 4; ++t)
+            if (code0 + t < szK) v[t] = cKy[code0 + t];
+    }
+    const int mine = (v[0] != 0) + (v[1] != 0) + (v[2] != 0) + (v[3] != 0);
+    // exclusive prefix of `mine` over the workgroup: wave scan, then wave totals
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int incl = mine;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(incl, o);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    int before = incl - mine;
+    for (int w = 0; w < wave; ++w) before += wsum[w];
+    if (mine == 0) return;
+    const double NK = (double)tot[3 * y], N1 = (double)tot[3 * y + 1], N2 = (double)tot[3 * y + 2];
+    int64_t pos = cv_off[s0 + y] + chunk_base[y * nchunks + blockIdx.x] + before;
+    const int64_t m1 = sz1, m2 = sz2;
+    for (int t = 0; t < 4; ++t) {
+        if (v[t] == 0u) continue;
+        const int64_t code = code0 + t;
+        if (pos >= capacity) {
+            *overflow = 1;
+        } else {
+            const int64_t pre = code / CV_ALPHA, suf = code % m1, mid = pre % m2;
+            const double f = (double)v[t] / NK;
+            const double f0 = ((double)c1y[pre] / N1) * ((double)c1y[suf] / N1) / ((double)c2y[mid] / N2);
+            keys[pos] = code;
+            vals[pos] = (float)((f - f0) / f0);
+        }
+        cKy[code] = 0u;  // leave the K array clean for the next group
+        ++pos;
+    }
+}
+
+}  // namespace
+
+rocket_status cv_build(rocket_ctx *ctx, const uint8_t *res, const int64_t *offsets, int64_t n, int K,
+                       int64_t *cv_off, int64_t *keys, float *vals, int64_t capacity, hipStream_t s)
+{
+    if (n < 0) return fail(ctx, ROCKET_E_INVALID, "n < 0");
+    if (K < 3 || K > 6) return fail(ctx, ROCKET_E_UNSUPPORTED, "K must be 3..6");
+    if (!cv_off || (n > 0 && (!offsets || !res))) return fail(ctx, ROCKET_E_INVALID, "NULL pointer");
+    if (capacity < 0) return fail(ctx, ROCKET_E_INVALID, "capacity < 0");
+    std::vector<int64_t> h_off((size_t)n + 1, 0);
+    if (n > 0) {
+        RK_HIP(hipMemcpyAsync(h_off.data(), offsets, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, s));
+        RK_HIP(hipStreamSynchronize(s));
+    }
+    if (h_off[0] != 0) return fail(ctx, ROCKET_E_INVALID, "offsets[0] != 0");
+    for (int64_t i = 0; i < n; ++i)
+        if (h_off[i + 1] < h_off[i]) return fail(ctx, ROCKET_E_INVALID, "offsets decrease");
+    if (capacity > 0 && (!keys || !vals)) return fail(ctx, ROCKET_E_INVALID, "keys or vals is NULL");
+    ctx->stats.cache_loads = 0;
+    if (n == 0) {
+        const int64_t zero = 0;
+        RK_HIP(hipMemcpyAsync(cv_off, &zero, sizeof(int64_t), hipMemcpyHostToDevice, s));
+        RK_HIP(hipStreamSynchronize(s));
+        return ROCKET_OK;
+    }
+    const int64_t szK = ipow20(K), sz1 = szK / CV_ALPHA, sz2 = sz1 / CV_ALPHA;
+    const int64_t nchunks = (szK + CV_CH - 1) / CV_CH;
+    const int64_t per_species = 4 * (szK + sz1 + sz2 + nchunks) + 8 * 4;
+    const int64_t G = std::max<int64_t>(1, std::min<int64_t>({n, 64, CV_GROUP_BYTES / per_species}));
+    CvState &cs = ctx->cv;
+    void *pK = nullptr, *p1 = nullptr, *p2 = nullptr, *pch = nullptr, *ptot = nullptr, *pnnz = nullptr,
+         *pflag = nullptr;
+    const bool fresh = !cs.clean || cs.K != K || cs.G < G || ctx->ws[WS_CV_K].ptr == nullptr;
+    RK_TRY(ws_get(ctx, WS_CV_K, (size_t)(4 * G * szK), &pK));
+    RK_TRY(ws_get(ctx, WS_CV_AUX, (size_t)(4 * G * (sz1 + sz2 + nchunks) + 8 * 4 * G + 64), &p1));
+    p2 = (char *)p1 + 4 * G * sz1;
+    pch = (char *)p2 + 4 * G * sz2;
+    ptot = (char *)pch + 4 * G * nchunks;  // 3 x u64 per species, then nnz, then the flag
+    ptot = (void *)(((uintptr_t)ptot + 7) & ~(uintptr_t)7);
+    pnnz = (char *)ptot + 8 * 3 * G;
+    pflag = (char *)pnnz + 8 * G;
+    cs.clean = false;
+    if (fresh) {
+        hipLaunchKernelGGL(k_cv_zero, dim3(4096), dim3(256), 0, s, (uint32_t *)pK, G * szK);
+        RK_HIP(hipGetLastError());
+    }
+    cs.K = K;
+    cs.G = G;
+    hipLaunchKernelGGL(k_cv_zero, dim3(1), dim3(64), 0, s, (uint32_t *)pflag, (int64_t)1);
+    RK_TRY(timing_begin(ctx, s));
+    for (int64_t s0 = 0; s0 < n; s0 += G) {
+        const int g = (int)std::min<int64_t>(G, n - s0);
+        int64_t longest = 0;
+        for (int y = 0; y < g; ++y) longest = std::max(longest, h_off[s0 + y + 1] - h_off[s0 + y]);
+        // clear the small count arrays, chunk counts and totals (the K array is kept clean)
+        const int64_t aux_words = (int64_t)g * (sz1 + sz2 + nchunks);
+        hipLaunchKernelGGL(k_cv_zero, dim3((unsigned)std::min<int64_t>(4096, (aux_words + 255) / 256)), dim3(256), 0,
+                           s, (uint32_t *)p1, (int64_t)G * (sz1 + sz2 + nchunks));
+        hipLaunchKernelGGL(k_cv_zero, dim3(1), dim3(256), 0, s, (uint32_t *)ptot, (int64_t)(2 * 3 * G));
+        if (longest > 0) {
+            const unsigned bx = (unsigned)std::min<int64_t>(2048, (longest + 255) / 256);
+            hipLaunchKernelGGL(k_cv_count, dim3(bx, g), dim3(256), 0, s, res, offsets, s0, K, (uint32_t *)pK,
+                               (uint32_t *)p1, (uint32_t *)p2, (uint32_t *)pch, nchunks, (unsigned long long *)ptot);
+        }
+        hipLaunchKernelGGL(k_cv_scan, dim3(g), dim3(1024), 0, s, (uint32_t *)pch, nchunks, (int64_t *)pnnz);
+        hipLaunchKernelGGL(k_cv_base, dim3(1), dim3(64), 0, s, (const int64_t *)pnnz, g, s0, cv_off);
+        hipLaunchKernelGGL(k_cv_emit, dim3((unsigned)nchunks, g), dim3(256), 0, s, (uint32_t *)pK,
+                           (const uint32_t *)p1, (const uint32_t *)p2, (const uint32_t *)pch, nchunks,
+                           (const unsigned long long *)ptot, (const int64_t *)cv_off, s0, K, keys, vals, capacity,
+                           (int *)pflag);
+        RK_HIP(hipGetLastError());
+    }
+    RK_TRY(timing_end(ctx, s));
+    int flag = 0;
+    RK_HIP(hipMemcpyAsync(&flag, pflag, sizeof(int), hipMemcpyDeviceToHost, s));
+    RK_HIP(hipStreamSynchronize(s));
+    cs.clean = true;  // every emitted code was written back to zero
+    ctx->stats.n = n;
+    ctx->stats.pairs = 0;
+    if (flag) return fail(ctx, ROCKET_E_INVALID, "capacity smaller than the total number of CV entries");
+    return ROCKET_OK;
+}
+
+}  // namespace rk

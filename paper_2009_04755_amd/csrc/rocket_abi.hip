@@ -305,6 +305,15 @@ rocket_status rocket_allpairs_host(rocket_ctx *ctx, const float *host_items, int
     return st;
 }
 
+rocket_status rocket_cv_build(rocket_ctx *ctx, const uint8_t *residues, const int64_t *offsets, int64_t n, int K,
+                              int64_t *cv_offsets, int64_t *keys, float *vals, int64_t capacity, void *stream)
+{
+    RK_TRY(enter(ctx));
+    rocket_status st = rk::cv_build(ctx, residues, offsets, n, K, cv_offsets, keys, vals, capacity, (hipStream_t)stream);
+    ctx->stats.workspace_bytes = rk::ws_total(ctx);
+    return st;
+}
+
 rocket_status rocket_overlap_cost_grad(rocket_ctx *ctx, const rocket_items *clouds, int64_t n, const float *centroids,
                                        const float *params, float *out_cost, float *out_grad, void *stream)
 {

@@ -270,3 +270,36 @@ def sparse_vectors_device(n: int, key_space: int = 20 ** 6, zipf_a: float = 1.1,
         keys[a:b] = k[order]
         vals[a:b] = (cnt[order].to(torch.float64) / float(draws.numel())).to(torch.float32)
     return torch.from_numpy(offsets).to(device), keys, vals
+
+
+def proteomes(n: int, n_families: int = 4000, len_min: int = 100, len_max: int = 500, p_keep: float = 0.7,
+              rate_min: float = 0.05, rate_max: float = 0.6, config: int = 5, salt: int = 0):
+    """Synthetic proteomes standing in for bacterial reference proteomes.
+
+    A pool of ``n_families`` ancestral proteins (lengths U{len_min..len_max}, residues
+    drawn from a seeded background distribution over the 20 amino-acid codes 0..19) is
+    shared by all species; species s keeps each family with probability ``p_keep`` and
+    substitutes each residue with probability rate_s ~ U[rate_min, rate_max] by a fresh
+    background draw.  Proteins are concatenated with the code 255 after each one.
+    Returns (residues uint8, offsets int64 [n+1]) with species s at offsets[s]..offsets[s+1]-1.
+    """
+    g = rng(config, salt)
+    bg = g.dirichlet(np.full(20, 8.0))
+    lens = g.integers(len_min, len_max + 1, n_families)
+    pool = g.choice(20, size=int(lens.sum()), p=bg).astype(np.uint8)
+    starts = np.concatenate([[0], np.cumsum(lens)])
+    parts, off = [], [0]
+    for s in range(n):
+        keep = np.nonzero(g.random(n_families) < p_keep)[0]
+        rate = g.uniform(rate_min, rate_max)
+        seq = []
+        for f in keep:
+            seq.append(pool[starts[f]:starts[f + 1]])
+            seq.append(np.array([255], dtype=np.uint8))
+        sp = np.concatenate(seq) if seq else np.zeros(0, np.uint8)
+        mut = (g.random(sp.size) < rate) & (sp != 255)
+        sp = sp.copy()
+        sp[mut] = g.choice(20, size=int(mut.sum()), p=bg).astype(np.uint8)
+        parts.append(sp)
+        off.append(off[-1] + sp.size)
+    return np.concatenate(parts) if parts else np.zeros(0, np.uint8), np.array(off, dtype=np.int64)

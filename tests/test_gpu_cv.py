@@ -1,0 +1,123 @@
+"""GPU composition vectors (Section V-B pre-process) against the FP64 oracle.
+
+Offsets and keys must be bit-exact; values are FP64 on both sides rounded once to f32, so
+they must agree to within one f32 rounding of the oracle's value (plus 1e-14 absolute for
+the FP64 cancellation in f/f0 - 1).  End to end, the sparse cosine of the GPU vectors
+must match the oracle cosine of the oracle vectors to 1e-5.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import cv
+from paper_2009_04755_amd import synth
+
+from gpu_util import announce, device_or_skip
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    device_or_skip()
+    from paper_2009_04755_amd import Context
+    return Context(0)
+
+
+def _gpu_cv(ctx, res, off, K):
+    import torch
+    S = ctx.cv_build(torch.from_numpy(res).cuda(), torch.from_numpy(off).cuda(), K)
+    torch.cuda.synchronize()
+    return S, S.offsets.cpu().numpy(), S.keys.cpu().numpy(), S.vals.cpu().numpy()
+
+
+def _check(off_g, keys_g, vals_g, res, off, K):
+    co, ck, cvv = cv.composition_vectors(res, off, K)
+    assert np.array_equal(off_g, co)
+    assert np.array_equal(keys_g, ck)
+    r32 = cvv.astype(np.float32).astype(np.float64)
+    err = np.abs(vals_g.astype(np.float64) - cvv)
+    lim = np.abs(r32 - cvv) + 2.0 ** -24 * np.abs(cvv) + 1e-14 * (np.abs(cvv) + 1)
+    assert np.all(err <= lim), err[err > lim][:5]
+    return co, ck, cvv
+
+
+@pytest.mark.parametrize("K", [3, 4, 5, 6])
+def test_small_species_all_k(ctx, K):
+    announce("cv small species K=%d" % K)
+    res, off = synth.proteomes(9, n_families=60, config=5, salt=K)
+    _, og, kg, vg = _gpu_cv(ctx, res, off, K)
+    _check(og, kg, vg, res, off, K)
+
+
+def test_edge_species(ctx):
+    announce("cv edge species")
+    g = np.random.default_rng(3)
+    sp = [
+        np.zeros(0, np.uint8),                          # empty species
+        np.array([0, 1, 2], np.uint8),                  # shorter than K: no entry
+        np.array([0, 1, 255, 2, 3, 200, 4], np.uint8),  # only breaks between residues
+        np.tile(np.array([0, 1], np.uint8), 500),       # periodic: two entries
+        g.integers(0, 20, 5000).astype(np.uint8),
+        np.where(g.random(3000) < 0.1, 255, g.integers(0, 20, 3000)).astype(np.uint8),
+    ]
+    off = np.zeros(len(sp) + 1, dtype=np.int64)
+    off[1:] = np.cumsum([s.size for s in sp])
+    res = np.concatenate(sp)
+    _, og, kg, vg = _gpu_cv(ctx, res, off, 4)
+    _check(og, kg, vg, res, off, 4)
+    assert og[1] == og[0] and og[2] == og[1] and og[3] == og[2]
+
+
+def test_groups_and_reuse_across_calls(ctx):
+    # more species than one group (K = 6 groups hold ~15 species), then a call with another
+    # K, then K = 6 again: the count arrays must come back clean every time
+    announce("cv groups n=40 K=6, then K=5, then K=6")
+    res, off = synth.proteomes(40, n_families=200, config=5, salt=11)
+    for K in (6, 5, 6):
+        _, og, kg, vg = _gpu_cv(ctx, res, off, K)
+        _check(og, kg, vg, res, off, K)
+
+
+def test_end_to_end_cosine(ctx):
+    import torch
+    announce("cv -> sparse cosine n=24 K=6")
+    res, off = synth.proteomes(24, n_families=400, config=5, salt=2)
+    S, og, kg, vg = _gpu_cv(ctx, res, off, 6)
+    co, ck, cvv = _check(og, kg, vg, res, off, 6)
+    got, cnt = ctx.allpairs(S, "sparse_cosine", counts=True)
+    got, cnt = got.cpu().numpy(), cnt.cpu().numpy()
+    pi, pj = oracle.all_pairs(24)
+    ref, rcnt, _ = oracle.sparse_cosine(co, ck, cvv.astype(np.float32), pi, pj)
+    assert np.array_equal(cnt.astype(np.int64), rcnt)
+    assert np.max(np.abs(got - ref) / np.abs(ref)) <= 1e-5
+
+
+def test_errors(ctx):
+    import torch
+    from paper_2009_04755_amd import _lib
+    from paper_2009_04755_amd._lib import RocketError, E_INVALID, E_UNSUPPORTED
+    announce("cv errors")
+    res = torch.zeros(100, dtype=torch.uint8, device="cuda")
+    off = torch.tensor([0, 60, 100], dtype=torch.int64, device="cuda")
+    with pytest.raises(RocketError) as e:
+        ctx.cv_build(res, off, 7)
+    assert e.value.status == E_UNSUPPORTED
+    with pytest.raises(RocketError) as e:
+        ctx.cv_build(res, torch.tensor([0, 60, 50], dtype=torch.int64, device="cuda"), 4)
+    assert e.value.status == E_INVALID
+    # capacity too small for the entries: reported, nothing written out of bounds
+    g = np.random.default_rng(1)
+    r = torch.from_numpy(g.integers(0, 20, 100).astype(np.uint8)).cuda()
+    o = torch.tensor([0, 100], dtype=torch.int64, device="cuda")
+    cvo = torch.empty(2, dtype=torch.int64, device="cuda")
+    keys = torch.empty(10, dtype=torch.int64, device="cuda")
+    vals = torch.empty(10, device="cuda")
+    L = _lib.load()
+    st = L.rocket_cv_build(ctx.handle, r.data_ptr(), o.data_ptr(), 1, 4, cvo.data_ptr(), keys.data_ptr(),
+                           vals.data_ptr(), 10, None)
+    assert st == E_INVALID
+    # and the next call is still right
+    S = ctx.cv_build(r, o, 4)
+    k0, v0 = cv.composition_vector(r.cpu().numpy(), 4)
+    assert np.array_equal(S.keys.cpu().numpy(), k0)
