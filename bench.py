@@ -189,6 +189,44 @@ def cv_pipeline(ctx, with_cpu=True):
     return res_
 
 
+PEAK_LDS = 256 * 128 * 2.4e9 / 1e9  # GB/s: 128 bytes per clock per CU
+
+
+def pce_pair_fn(ctx, with_cpu=True):
+    """PCE over all shifts for 1024 noise images of 128 x 128 (523,776 pairs)."""
+    import numpy as np
+    import torch
+    from paper_2009_04755_amd import synth
+
+    n, L = 1024, 128
+    X, _, _ = synth.noise_images(n, L, nsrc=16, amp=0.3, config=6, salt=0)
+    Xd = torch.from_numpy(X).cuda()
+    P = n * (n - 1) // 2
+    out = torch.empty(P, device="cuda")
+    dt, kern = _time_fn(ctx, Xd, "pce", out, 3, 1)
+    # LDS bytes per pair of the in-LDS design: product tile written, four FFT steps read and
+    # write the L x L complex tile, two statistics passes read it
+    lds_bytes = (1 + 8 + 2) * L * L * 8
+    res = {"workload": "1024 noise images 128 x 128 (16 sources, amp 0.3, 25 % shifted crops), h = 5",
+           "pairs_per_s": 3 * P / dt, "kernel_ms": kern * 1e3,
+           "roofline": {"bound": "lds", "achieved": P * lds_bytes / kern / 1e9, "peak": PEAK_LDS, "unit": "GB/s",
+                        "frac": P * lds_bytes / kern / 1e9 / PEAK_LDS,
+                        "model": "11 L^2 complex f32 LDS passes per pair"}}
+    if with_cpu:
+        import oracle.pce as opce
+        g = np.random.default_rng(8)
+        t0 = time.perf_counter()
+        m = 0
+        while time.perf_counter() - t0 < 5.0:
+            i, j = sorted(g.choice(n, 2, replace=False))
+            opce.pce(X[i].reshape(L, L), X[j].reshape(L, L))
+            m += 1
+        dto = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": m / dto, "unit": "pairs/s", "cores": 1, "kind": "oracle",
+                               "sample": "%d random pairs (numpy FFT, FP64)" % m}
+    return res
+
+
 def other_pair_fns(ctx, with_cpu=True):
     """Gaussian overlap (2048 uneven clouds), the two per-point-sigma scores and the
     20-step registration, one entry each."""
@@ -382,6 +420,7 @@ def main():
         rec["pair_fns"] = other_pair_fns(ctx, not args.no_cpu_baseline)
         rec["pair_fns"]["sparse_cosine"] = sparse_pair_fn(ctx, not args.no_cpu_baseline)
         rec["cv_build"] = cv_pipeline(ctx, not args.no_cpu_baseline)
+        rec["pair_fns"]["pce"] = pce_pair_fn(ctx, not args.no_cpu_baseline)
     print(json.dumps(rec))
     sys.stdout.flush()
 

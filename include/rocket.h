@@ -27,6 +27,7 @@
  *                         of the key intersection (V-B);
  *   ROCKET_GMM_L2, ROCKET_GMM_BHATTACHARYA  the two particle scores of V-C for
  *                         clouds whose points carry their own uncertainty;
+ *   ROCKET_PCE            peak-to-correlation energy over all shifts (V-A variant);
  * and rocket_overlap_cost_grad gives the overlap cost's gradient with respect to a
  * rigid transform per pair (the registration optimiser of V-C).
  *
@@ -109,7 +110,17 @@ typedef enum {
      * point_sigma and must lie in [1e-18, 1e18] (checked in rocket_prepare, else
      * ROCKET_E_INVALID); the scalar sigma is ignored.  An empty cloud gives 0. */
     ROCKET_GMM_L2 = 6,
-    ROCKET_GMM_BHATTACHARYA = 7
+    ROCKET_GMM_BHATTACHARYA = 7,
+    /* Peak-to-correlation energy over all cyclic shifts (the PCE variant of the forensics
+     * comparison, Section V-A).  Items are L x L images, L = 32, 64 or 128, flattened
+     * row-major (dense, dim = L*L, ld >= dim).  With a, b the two items minus their means,
+     *   C(s) = sum_x a(x + s) b(x)  (indices mod L),  s* = argmax C (smallest shift index
+     *   r*L + c on ties),  PCE = C(s*)^2 (L^2 - |N|) / sum_{s outside N} C(s)^2,
+     * N the (2h+1) x (2h+1) cyclic neighbourhood of s*, h = ROCKET_OPT_PCE_RADIUS (5 if 0).
+     * rocket_prepare transforms every item once (FP64 mean, f32 2-D FFT in LDS);
+     * rocket_compare runs one f32 2-D FFT per pair.  out_counts, when given, receives the
+     * peak shift index r*L + c of s* (a(x) ~ b(x - s*)).  A constant item gives NaN. */
+    ROCKET_PCE = 8
 } rocket_pair_fn;
 
 /* The item set.  Which fields are read depends on the pair function; unused
@@ -153,7 +164,8 @@ rocket_status rocket_prepare(rocket_ctx *ctx, const rocket_items *items, int64_t
 
 /* Compare stage (the GPU part of f) for every pair of the last prepared set.
  * out: float32 [P] packed upper triangle (required when P > 0).
- * out_counts: uint32 [P] intersection sizes, sparse cosine only; may be NULL. */
+ * out_counts: uint32 [P] secondary result, may be NULL: intersection sizes (sparse cosine)
+ * or peak shift indices (PCE); ignored by the other functions. */
 rocket_status rocket_compare(rocket_ctx *ctx, float *out, uint32_t *out_counts, void *stream);
 
 /* rocket_prepare followed by rocket_compare on `stream`. */
@@ -230,8 +242,9 @@ typedef enum {
     ROCKET_OPT_TIMING = 13,         /* 1: bracket each compare's main persistent kernel with HIP events on the
                                        launch stream; rocket_get_stats reports its duration (for
                                        rocket_allpairs_host: the whole call's device work) */
-    ROCKET_OPT_CACHE_SLOTS = 14     /* rocket_allpairs_host: device cache slots, one block of `tile` items each
+    ROCKET_OPT_CACHE_SLOTS = 14,    /* rocket_allpairs_host: device cache slots, one block of `tile` items each
                                        (0: one per block, i.e. everything stays resident); at least 2 */
+    ROCKET_OPT_PCE_RADIUS = 15      /* ROCKET_PCE: half-width h of the excluded peak neighbourhood (0: 5); h < L/2 */
 } rocket_option;
 
 rocket_status rocket_set_option(rocket_ctx *ctx, rocket_option opt, int64_t value);

@@ -15,14 +15,14 @@ LIB_PATH = os.path.join(HERE, "librocket.so")
 OK = 0
 E_INVALID, E_UNSUPPORTED, E_OOM, E_HIP, E_KEYRANGE, E_UNSORTED, E_STATE = -1, -2, -3, -4, -5, -6, -7
 
-NCC_FP32, NCC_BF16X3, NCC_BF16X6, GAUSS_OVERLAP, SPARSE_COSINE, GMM_L2, GMM_BHATTACHARYA = 1, 2, 3, 4, 5, 6, 7
+NCC_FP32, NCC_BF16X3, NCC_BF16X6, GAUSS_OVERLAP, SPARSE_COSINE, GMM_L2, GMM_BHATTACHARYA, PCE = 1, 2, 3, 4, 5, 6, 7, 8
 FN_BY_NAME = {"ncc_fp32": NCC_FP32, "ncc_bf16x3": NCC_BF16X3, "ncc_bf16x6": NCC_BF16X6,
               "gauss_overlap": GAUSS_OVERLAP, "sparse_cosine": SPARSE_COSINE, "gmm_l2": GMM_L2,
-              "gmm_bhattacharya": GMM_BHATTACHARYA}
+              "gmm_bhattacharya": GMM_BHATTACHARYA, "pce": PCE}
 
 OPT = {"ncc_tile": 1, "ncc_kchunk": 2, "grid": 3, "queue_order": 4, "seed": 5, "ledger": 6, "ovl_block": 7,
        "ovl_variant": 8, "sp_rows": 9, "sp_chunk": 10, "workspace_cap": 11, "autotune": 12, "timing": 13,
-       "cache_slots": 14}
+       "cache_slots": 14, "pce_radius": 15}
 
 # every symbol include/rocket.h declares
 SYMBOLS = ["rocket_create", "rocket_destroy", "rocket_status_str", "rocket_last_error", "rocket_prepare",

@@ -109,7 +109,7 @@ class Context:
     @staticmethod
     def _items(x, fn: int):
         it = _lib.Items()
-        if fn in (_lib.NCC_FP32, _lib.NCC_BF16X3, _lib.NCC_BF16X6):
+        if fn in (_lib.NCC_FP32, _lib.NCC_BF16X3, _lib.NCC_BF16X6, _lib.PCE):
             assert x.dtype == torch.float32 and x.dim() == 2 and x.stride(1) == 1 and x.is_cuda
             it.dense = x.data_ptr()
             it.dim = x.shape[1]

@@ -31,6 +31,7 @@ enum Slot {
     WS_SP_CHUNKS,        // band histogram over key micro-chunks + chunk counts
     WS_SP_CSHIFT,        // per band start of its chunk boundaries
     WS_SP_BOUNDS,        // chunk boundaries (micro-chunk indices)
+    WS_PCE_SPEC,         // PCE item spectra (complex f32, natural order)
     WS_CV_K,             // dense K-string counts of a group of species (kept zeroed between calls)
     WS_CV_AUX,           // (K-1)- and (K-2)-string counts, chunk occupancy, totals
     WS_COUNT
@@ -51,7 +52,7 @@ struct QueueArgs {
 };
 constexpr int HEAD_STRIDE = 32;  // 128 bytes between segment counters
 constexpr int MAX_SEG = 8;       // one segment per XCD
-enum { QOWN_NONE = 0, QOWN_NCC, QOWN_OVL, QOWN_SP };
+enum { QOWN_NONE = 0, QOWN_NCC, QOWN_OVL, QOWN_SP, QOWN_PCE };
 
 struct NccState {
     int64_t n = 0, dim = 0, ld = 0, n_pad = 0, d_pad = 0;
@@ -98,6 +99,13 @@ struct SpState {
     bool valid = false;
 };
 
+struct PceState {
+    int64_t n = 0, tiles = 0;
+    int L = 0;
+    QueueArgs qa{};
+    bool valid = false;
+};
+
 // Composition-vector builder: whether the dense K-string count array is all zeros.
 struct CvState {
     bool clean = false;
@@ -127,6 +135,7 @@ struct rocket_ctx {
     rk::SpState sp;
     rk::OocState ooc;
     rk::CvState cv;
+    rk::PceState pce;
     rocket_stats stats = {};
     int64_t ledger_items = 0;
     hipEvent_t ev_begin = nullptr, ev_end = nullptr;  // main-kernel timing (ROCKET_OPT_TIMING)
@@ -172,6 +181,8 @@ rocket_status ovl_compare(rocket_ctx *ctx, float *out, const float *centroids, c
 rocket_status ovl_autotune(rocket_ctx *ctx, hipStream_t s);
 rocket_status sp_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, hipStream_t s);
 rocket_status sp_compare(rocket_ctx *ctx, float *out, uint32_t *counts, hipStream_t s);
+rocket_status pce_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, hipStream_t s);
+rocket_status pce_compare(rocket_ctx *ctx, float *out, uint32_t *peak, hipStream_t s);
 rocket_status cv_build(rocket_ctx *ctx, const uint8_t *res, const int64_t *offsets, int64_t n, int K,
                        int64_t *cv_off, int64_t *keys, float *vals, int64_t capacity, hipStream_t s);
 

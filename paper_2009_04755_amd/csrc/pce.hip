@@ -1,0 +1,376 @@
+// Peak-to-correlation energy (PCE) over all cyclic shifts: the forensics application's PCE
+// variant of the pattern comparison (Section V-A; the application's stage table names PCE).
+//
+//   C(s) = sum_x a(x + s) b(x)   (mean-removed L x L items, indices mod L)
+//   s*   = argmax_s C(s),  PCE = C(s*)^2 (L^2 - |N|) / sum_{s not in N} C(s)^2,
+//   N    = the (2h+1) x (2h+1) cyclic neighbourhood of s*.
+//
+// Prepare (l's GPU stage): one workgroup per item removes the mean (FP64) and transforms
+// the item with a 2-D FFT in LDS; spectra F are stored in natural order, complex f32.
+// Compare: a persistent kernel pulls tiles of T x T item pairs from the work queue (the
+// spectra of a tile's 2T items stay in L2); per pair one workgroup forms conj(F_a) F_b in
+// LDS, transforms it forward (the real part is L^2 C(s); the scale cancels in PCE), finds
+// the peak and the energy outside its neighbourhood, and writes PCE and the peak shift.
+//
+// The L-point FFTs are four-step L = N1 x N2 transforms: N1-point DFTs in registers
+// (radix-2, decimation in frequency), twiddles W_L^(n2 k1) from an LDS table, N2-point
+// DFTs in registers.  Each task writes back to the positions it read, so a step needs no
+// barrier between its reads and writes; the price is that position p of a transformed
+// vector holds frequency k(p) = p / N2 + N1 (p % N2), which prepare undoes when it stores
+// the spectra and the statistics undo when they name the peak.
+#include <cmath>
+
+#include "common.hpp"
+#include "queue.hpp"
+
+namespace rk {
+namespace {
+
+constexpr int PCE_THREADS = 256;
+constexpr int PCE_T = 8;  // items per block of the tile grid
+
+// cos(pi m / 8) and sin(pi m / 8), m = 0..15
+constexpr float kCos16[16] = {1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f, 0.0f,
+                              -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f, -1.0f,
+                              -0.92387953251128674f, -0.70710678118654752f, -0.38268343236508977f, 0.0f,
+                              0.38268343236508977f, 0.70710678118654752f, 0.92387953251128674f};
+constexpr float kSin16[16] = {0.0f, 0.38268343236508977f, 0.70710678118654752f, 0.92387953251128674f, 1.0f,
+                              0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f, 0.0f,
+                              -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f, -1.0f,
+                              -0.92387953251128674f, -0.70710678118654752f, -0.38268343236508977f};
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b)
+{
+    return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
+}
+
+// d * W_16^m, W_16 = exp(-2 pi i / 16); m is a constant once the DFT loops are unrolled
+__device__ __forceinline__ float2 tw16(float2 d, int m)
+{
+    if (m == 0) return d;
+    if (m == 4) return make_float2(d.y, -d.x);
+    if (m == 8) return make_float2(-d.x, -d.y);
+    if (m == 12) return make_float2(-d.y, d.x);
+    const float c = kCos16[m], s = kSin16[m];
+    return make_float2(fmaf(d.x, c, d.y * s), fmaf(d.y, c, -(d.x * s)));
+}
+
+// In-register N-point forward DFT (N = 2, 4, 8, 16), radix-2 decimation in frequency;
+// the output is bit-reversed: X[k] ends in x[rev(k)].
+template <int N>
+__device__ __forceinline__ void dft_dif(float2 (&x)[N])
+{
+#pragma unroll
+    for (int span = N / 2; span >= 1; span >>= 1)
+#pragma unroll
+        for (int st = 0; st < N; st += 2 * span)
+#pragma unroll
+            for (int j = 0; j < span; ++j) {
+                const float2 a = x[st + j], b = x[st + j + span];
+                x[st + j] = cadd(a, b);
+                x[st + j + span] = tw16(csub(a, b), (16 / (2 * span)) * j);
+            }
+}
+
+template <int N>
+__device__ __forceinline__ constexpr int bitrev(int k)
+{
+    int r = 0;
+    for (int b = 1; b < N; b <<= 1) {
+        r = (r << 1) | (k & 1);
+        k >>= 1;
+    }
+    return r;
+}
+
+// One 2-D forward FFT of the L x L complex array at `a` (row stride RS = L + 1) in place.
+// `tw` holds W_L^m, m = 0..L-1.  Position (pr, pc) ends holding frequency (k(pr), k(pc)).
+template <int L, int N1, int N2>
+__device__ void fft2d(float2 *a, const float2 *tw)
+{
+    constexpr int RS = L + 1;
+#pragma unroll 1
+    for (int dim = 0; dim < 2; ++dim) {
+        // rows: vector v at v*RS, element stride 1; columns: vector v at v, stride RS
+        const int vstride = dim == 0 ? RS : 1, estride = dim == 0 ? 1 : RS;
+        // step A: for every (v, n2): N1-point DFT over n1 of x[N2 n1 + n2], twiddle W_L^(n2 k1)
+        for (int id = threadIdx.x; id < L * N2; id += PCE_THREADS) {
+            const int v = id % L, n2 = id / L;
+            float2 *p = a + v * vstride + n2 * estride;
+            float2 x[N1];
+#pragma unroll
+            for (int n1 = 0; n1 < N1; ++n1) x[n1] = p[n1 * N2 * estride];
+            dft_dif<N1>(x);
+#pragma unroll
+            for (int k1 = 0; k1 < N1; ++k1) p[k1 * N2 * estride] = cmul(x[bitrev<N1>(k1)], tw[n2 * k1]);
+        }
+        __syncthreads();
+        // step B: for every (v, k1): N2-point DFT over n2 of y[N2 k1 + n2], written back in place
+        for (int id = threadIdx.x; id < L * N1; id += PCE_THREADS) {
+            const int v = id % L, k1 = id / L;
+            float2 *p = a + v * vstride + k1 * N2 * estride;
+            float2 x[N2];
+#pragma unroll
+            for (int n2 = 0; n2 < N2; ++n2) x[n2] = p[n2 * estride];
+            dft_dif<N2>(x);
+#pragma unroll
+            for (int k2 = 0; k2 < N2; ++k2) p[k2 * estride] = x[bitrev<N2>(k2)];
+        }
+        __syncthreads();
+    }
+}
+
+template <int L>
+__device__ void fill_twiddles(float2 *tw)
+{
+    for (int m = threadIdx.x; m < L; m += PCE_THREADS) {
+        double s, c;
+        sincospi(-2.0 * m / L, &s, &c);
+        tw[m] = make_float2((float)c, (float)s);
+    }
+}
+
+// frequency held at position p of a transformed vector, and the position of frequency k
+template <int N1, int N2>
+__device__ __forceinline__ int freq_of(int p)
+{
+    return p / N2 + N1 * (p % N2);
+}
+template <int N1, int N2>
+__device__ __forceinline__ int pos_of(int k)
+{
+    return N2 * (k % N1) + k / N1;
+}
+
+// Prepare: grid = n items.  X: f32 [n][ld], item = L*L values row-major.  F: [n][L*L] float2.
+template <int L, int N1, int N2>
+__global__ __launch_bounds__(PCE_THREADS) void k_pce_prepare(const float *__restrict__ X, int64_t ld,
+                                                             float2 *__restrict__ F)
+{
+    constexpr int RS = L + 1;
+    extern __shared__ float2 sm[];
+    float2 *a = sm, *tw = sm + L * RS;
+    __shared__ double red[PCE_THREADS / 64];
+    const float *x = X + (int64_t)blockIdx.x * ld;
+    fill_twiddles<L>(tw);
+    double s = 0.0;
+    for (int i = threadIdx.x; i < L * L; i += PCE_THREADS) s += (double)x[i];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    const double mean = ((red[0] + red[1]) + (red[2] + red[3])) / (double)(L * L);
+    for (int i = threadIdx.x; i < L * L; i += PCE_THREADS)
+        a[(i / L) * RS + i % L] = make_float2((float)((double)x[i] - mean), 0.f);
+    __syncthreads();
+    fft2d<L, N1, N2>(a, tw);
+    float2 *f = F + (int64_t)blockIdx.x * L * L;
+    for (int i = threadIdx.x; i < L * L; i += PCE_THREADS)
+        f[i] = a[pos_of<N1, N2>(i / L) * RS + pos_of<N1, N2>(i % L)];
+}
+
+// Compare: persistent; work item = tile (bi, bj) of PCE_T-item blocks, bi <= bj.
+template <int L, int N1, int N2>
+__global__ __launch_bounds__(PCE_THREADS, 1) void k_pce(const float2 *__restrict__ F, int n, int h, QueueArgs q,
+                                                        float *__restrict__ out, uint32_t *__restrict__ peak_out)
+{
+    constexpr int RS = L + 1;
+    constexpr int NV = L * L;
+    extern __shared__ float2 sm[];
+    float2 *a = sm, *tw = sm + L * RS;
+    __shared__ float s_val[PCE_THREADS / 64];
+    __shared__ int s_idx[PCE_THREADS / 64];
+    __shared__ double s_sum[PCE_THREADS / 64];
+    __shared__ int s_item;
+    fill_twiddles<L>(tw);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nb_side = 2 * h + 1 < L ? 2 * h + 1 : L;
+    for (;;) {
+        const int it = queue_pop_wg(q, &s_item);
+        if (it < 0) break;
+        const int4 w = q.items[it];
+        const int i0 = w.x * PCE_T, i1 = min(n, i0 + PCE_T), j0 = w.y * PCE_T, j1 = min(n, j0 + PCE_T);
+        for (int i = i0; i < i1; ++i) {
+            for (int j = max(j0, i + 1); j < j1; ++j) {
+                const float2 *fa = F + (int64_t)i * NV, *fb = F + (int64_t)j * NV;
+                // conj(F_a) F_b = conj(F_a conj(F_b)): its forward FFT is L^2 conj(C)
+                for (int e = threadIdx.x; e < NV; e += PCE_THREADS) {
+                    const float2 u = fa[e], v = fb[e];
+                    a[(e / L) * RS + e % L] = make_float2(fmaf(u.x, v.x, u.y * v.y), fmaf(u.x, v.y, -(u.y * v.x)));
+                }
+                __syncthreads();
+                fft2d<L, N1, N2>(a, tw);
+                // peak: largest real part, smallest shift index on ties
+                float best = -INFINITY;
+                int bidx = 0x7fffffff;
+                for (int e = threadIdx.x; e < NV; e += PCE_THREADS) {
+                    const int pr = e / L, pc = e % L;
+                    const float v = a[pr * RS + pc].x;
+                    const int k = freq_of<N1, N2>(pr) * L + freq_of<N1, N2>(pc);
+                    if (v > best || (v == best && k < bidx)) {
+                        best = v;
+                        bidx = k;
+                    }
+                }
+                for (int o = 32; o > 0; o >>= 1) {
+                    const float ov = __shfl_xor(best, o);
+                    const int oi = __shfl_xor(bidx, o);
+                    if (ov > best || (ov == best && oi < bidx)) {
+                        best = ov;
+                        bidx = oi;
+                    }
+                }
+                if (lane == 0) {
+                    s_val[wave] = best;
+                    s_idx[wave] = bidx;
+                }
+                __syncthreads();
+                float pv = s_val[0];
+                int pk = s_idx[0];
+                for (int ww = 1; ww < PCE_THREADS / 64; ++ww)
+                    if (s_val[ww] > pv || (s_val[ww] == pv && s_idx[ww] < pk)) {
+                        pv = s_val[ww];
+                        pk = s_idx[ww];
+                    }
+                const int r0 = pk / L, c0 = pk % L;
+                // energy outside the cyclic neighbourhood of the peak, FP64, fixed order
+                double en = 0.0;
+                for (int e = threadIdx.x; e < NV; e += PCE_THREADS) {
+                    const int pr = e / L, pc = e % L;
+                    const int kr = freq_of<N1, N2>(pr), kc = freq_of<N1, N2>(pc);
+                    int dr = kr - r0, dc = kc - c0;
+                    dr = dr < 0 ? -dr : dr;
+                    dc = dc < 0 ? -dc : dc;
+                    dr = min(dr, L - dr);
+                    dc = min(dc, L - dc);
+                    if (dr <= h && dc <= h) continue;
+                    const double v = (double)a[pr * RS + pc].x;
+                    en = fma(v, v, en);
+                }
+                for (int o = 32; o > 0; o >>= 1) en += __shfl_xor(en, o);
+                if (lane == 0) s_sum[wave] = en;
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    const double rest = (s_sum[0] + s_sum[1]) + (s_sum[2] + s_sum[3]);
+                    const double num = (double)pv * (double)pv * (double)(NV - nb_side * nb_side);
+                    const int64_t pidx = (int64_t)i * n - (int64_t)i * (i + 1) / 2 + (j - i - 1);
+                    out[pidx] = rest > 0.0 ? (float)(num / rest) : __builtin_nanf("");
+                    if (peak_out) peak_out[pidx] = (uint32_t)pk;
+                }
+                __syncthreads();  // LDS is refilled by the next pair
+            }
+        }
+    }
+}
+
+template <int L>
+struct PceShape;
+template <>
+struct PceShape<32> {
+    static constexpr int N1 = 8, N2 = 4;
+};
+template <>
+struct PceShape<64> {
+    static constexpr int N1 = 8, N2 = 8;
+};
+template <>
+struct PceShape<128> {
+    static constexpr int N1 = 16, N2 = 8;
+};
+
+template <int L>
+size_t pce_lds() { return (size_t)(L * (L + 1) + L) * sizeof(float2); }
+
+template <int L>
+const void *pce_kernel() { return (const void *)&k_pce<L, PceShape<L>::N1, PceShape<L>::N2>; }
+
+int side_of(int64_t dim)
+{
+    for (int L : {32, 64, 128})
+        if ((int64_t)L * L == dim) return L;
+    return 0;
+}
+
+}  // namespace
+
+rocket_status pce_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, hipStream_t s)
+{
+    PceState &p = ctx->pce;
+    p.valid = false;
+    if (n > 0 && !it->dense) return fail(ctx, ROCKET_E_INVALID, "dense is NULL");
+    const int L = side_of(it->dim);
+    if (!L) return fail(ctx, ROCKET_E_UNSUPPORTED, "PCE items must be L x L with L = 32, 64 or 128");
+    if (it->ld < it->dim) return fail(ctx, ROCKET_E_INVALID, "ld < dim");
+    if (n >= (1 << 30)) return fail(ctx, ROCKET_E_INVALID, "n too large");
+    p.n = n;
+    p.L = L;
+    void *spec = nullptr;
+    RK_TRY(ws_get(ctx, WS_PCE_SPEC, (size_t)std::max<int64_t>(n, 1) * L * L * sizeof(float2), &spec));
+    if (n > 0) {
+        const size_t lds = L == 32 ? pce_lds<32>() : L == 64 ? pce_lds<64>() : pce_lds<128>();
+        const void *kp = L == 32   ? (const void *)&k_pce_prepare<32, 8, 4>
+                         : L == 64 ? (const void *)&k_pce_prepare<64, 8, 8>
+                                   : (const void *)&k_pce_prepare<128, 16, 8>;
+        RK_HIP(hipFuncSetAttribute(kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        if (L == 32)
+            hipLaunchKernelGGL((k_pce_prepare<32, 8, 4>), dim3((unsigned)n), dim3(PCE_THREADS), lds, s, it->dense,
+                               it->ld, (float2 *)spec);
+        else if (L == 64)
+            hipLaunchKernelGGL((k_pce_prepare<64, 8, 8>), dim3((unsigned)n), dim3(PCE_THREADS), lds, s, it->dense,
+                               it->ld, (float2 *)spec);
+        else
+            hipLaunchKernelGGL((k_pce_prepare<128, 16, 8>), dim3((unsigned)n), dim3(PCE_THREADS), lds, s, it->dense,
+                               it->ld, (float2 *)spec);
+        RK_HIP(hipGetLastError());
+    }
+    std::vector<int2> tiles;
+    plan_leaves(n, PCE_T, tiles);
+    p.tiles = (int64_t)tiles.size();
+    if (p.tiles > 0) {
+        plan_chunked(tiles, 1, MAX_SEG, ctx->h_items, ctx->h_seg, 1);
+        const int64_t order = ctx->opt[ROCKET_OPT_QUEUE_ORDER];
+        if (order == 1) shuffle_items(ctx->h_items, ctx->h_seg, (uint64_t)ctx->opt[ROCKET_OPT_SEED]);
+        if (order == 2) single_segment(ctx->h_seg, (int64_t)ctx->h_items.size());
+        RK_TRY(upload_queue(ctx, s, &p.qa));
+        ctx->queue_owner = QOWN_PCE;
+    }
+    ctx->stats.tiles = p.tiles;
+    ctx->stats.work_items = p.tiles;
+    ctx->stats.tile = PCE_T;
+    ctx->stats.kchunk = 0;
+    ctx->stats.variant = L;
+    p.valid = true;
+    return ROCKET_OK;
+}
+
+rocket_status pce_compare(rocket_ctx *ctx, float *out, uint32_t *peak, hipStream_t s)
+{
+    PceState &p = ctx->pce;
+    if (!p.valid) return fail(ctx, ROCKET_E_STATE, "PCE set not prepared");
+    if (p.n < 2 || p.tiles == 0) return ROCKET_OK;
+    if (ctx->queue_owner != QOWN_PCE) return fail(ctx, ROCKET_E_STATE, "queue was replanned by another prepare");
+    const int L = p.L;
+    const int h = ctx->opt[ROCKET_OPT_PCE_RADIUS] ? (int)ctx->opt[ROCKET_OPT_PCE_RADIUS] : 5;
+    if (h >= L / 2) return fail(ctx, ROCKET_E_INVALID, "PCE neighbourhood radius must be < L/2");
+    const size_t lds = L == 32 ? pce_lds<32>() : L == 64 ? pce_lds<64>() : pce_lds<128>();
+    const void *kp = L == 32 ? pce_kernel<32>() : L == 64 ? pce_kernel<64>() : pce_kernel<128>();
+    RK_HIP(hipFuncSetAttribute(kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const int grid = auto_grid(ctx, kp, PCE_THREADS, lds, p.tiles);
+    ctx->stats.grid = grid;
+    RK_TRY(reset_queue(ctx, s, p.qa));
+    const float2 *F = (const float2 *)ctx->ws[WS_PCE_SPEC].ptr;
+    RK_TRY(timing_begin(ctx, s));
+    if (L == 32)
+        hipLaunchKernelGGL((k_pce<32, 8, 4>), dim3(grid), dim3(PCE_THREADS), lds, s, F, (int)p.n, h, p.qa, out, peak);
+    else if (L == 64)
+        hipLaunchKernelGGL((k_pce<64, 8, 8>), dim3(grid), dim3(PCE_THREADS), lds, s, F, (int)p.n, h, p.qa, out, peak);
+    else
+        hipLaunchKernelGGL((k_pce<128, 16, 8>), dim3(grid), dim3(PCE_THREADS), lds, s, F, (int)p.n, h, p.qa, out,
+                           peak);
+    RK_HIP(hipGetLastError());
+    RK_TRY(timing_end(ctx, s));
+    return ROCKET_OK;
+}
+
+}  // namespace rk

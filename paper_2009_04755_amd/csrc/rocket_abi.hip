@@ -18,7 +18,7 @@ rocket_ctx *g_default[64] = {nullptr};
 std::mutex g_default_mu;
 std::string g_null_error;
 
-bool valid_fn(int fn) { return fn >= ROCKET_NCC_FP32 && fn <= ROCKET_GMM_BHATTACHARYA; }
+bool valid_fn(int fn) { return fn >= ROCKET_NCC_FP32 && fn <= ROCKET_PCE; }
 
 }  // namespace
 
@@ -233,6 +233,7 @@ rocket_status rocket_prepare(rocket_ctx *ctx, const rocket_items *items, int64_t
     case ROCKET_GMM_L2: st = rk::ovl_prepare(ctx, items, n, 1, s); break;
     case ROCKET_GMM_BHATTACHARYA: st = rk::ovl_prepare(ctx, items, n, 2, s); break;
     case ROCKET_SPARSE_COSINE: st = rk::sp_prepare(ctx, items, n, s); break;
+    case ROCKET_PCE: st = rk::pce_prepare(ctx, items, n, s); break;
     default: st = ROCKET_E_UNSUPPORTED;
     }
     if (st == ROCKET_OK) ctx->prepared_fn = (int)fn;
@@ -258,6 +259,7 @@ rocket_status rocket_compare(rocket_ctx *ctx, float *out, uint32_t *out_counts, 
     case ROCKET_GMM_L2:
     case ROCKET_GMM_BHATTACHARYA: st = rk::ovl_compare(ctx, out, nullptr, nullptr, nullptr, s); break;
     case ROCKET_SPARSE_COSINE: st = rk::sp_compare(ctx, out, out_counts, s); break;
+    case ROCKET_PCE: st = rk::pce_compare(ctx, out, out_counts, s); break;
     default: st = ROCKET_E_STATE;
     }
     ctx->stats.workspace_bytes = rk::ws_total(ctx);
@@ -342,7 +344,7 @@ rocket_status rocket_overlap_cost_grad(rocket_ctx *ctx, const rocket_items *clou
 rocket_status rocket_set_option(rocket_ctx *ctx, rocket_option opt, int64_t value)
 {
     if (!ctx) return rk::fail(nullptr, ROCKET_E_INVALID, "ctx is NULL");
-    if (opt < ROCKET_OPT_NCC_TILE || opt > ROCKET_OPT_CACHE_SLOTS) return rk::fail(ctx, ROCKET_E_UNSUPPORTED, "option");
+    if (opt < ROCKET_OPT_NCC_TILE || opt > ROCKET_OPT_PCE_RADIUS) return rk::fail(ctx, ROCKET_E_UNSUPPORTED, "option");
     if (value < 0) return rk::fail(ctx, ROCKET_E_INVALID, "negative option value");
     if (opt == ROCKET_OPT_NCC_TILE && value != 0 && value != 64 && value != 128 && value != 256)
         return rk::fail(ctx, ROCKET_E_INVALID, "NCC tile must be 0, 64, 128 or 256");
@@ -358,7 +360,7 @@ rocket_status rocket_set_option(rocket_ctx *ctx, rocket_option opt, int64_t valu
 rocket_status rocket_get_option(const rocket_ctx *ctx, rocket_option opt, int64_t *value)
 {
     if (!ctx || !value) return rk::fail(nullptr, ROCKET_E_INVALID, "NULL argument");
-    if (opt < ROCKET_OPT_NCC_TILE || opt > ROCKET_OPT_CACHE_SLOTS) return ROCKET_E_UNSUPPORTED;
+    if (opt < ROCKET_OPT_NCC_TILE || opt > ROCKET_OPT_PCE_RADIUS) return ROCKET_E_UNSUPPORTED;
     *value = ctx->opt[opt];
     return ROCKET_OK;
 }

@@ -303,3 +303,21 @@ def proteomes(n: int, n_families: int = 4000, len_min: int = 100, len_max: int =
         parts.append(sp)
         off.append(off[-1] + sp.size)
     return np.concatenate(parts) if parts else np.zeros(0, np.uint8), np.array(off, dtype=np.int64)
+
+
+def noise_images(n: int, L: int, nsrc: int = 8, amp: float = 0.05, p_shift: float = 0.25, config: int = 6,
+                 salt: int = 0):
+    """Camera-noise-like L x L images (flattened, f32 [n][L*L]): item = amp * source[c] + N(0, 1)
+    with c uniform over ``nsrc`` N(0, 1) sources; with probability ``p_shift`` the source is
+    cyclically shifted by a uniform (dy, dx) (a crop taken at another offset).
+    Returns (images, source index, shift (dy, dx) per item)."""
+    g = rng(config, salt)
+    src = g.standard_normal((nsrc, L, L))
+    c = g.integers(0, nsrc, n)
+    shifted = g.random(n) < p_shift
+    sh = np.where(shifted[:, None], g.integers(0, L, (n, 2)), 0)
+    X = np.empty((n, L * L), dtype=np.float32)
+    for i in range(n):
+        s = np.roll(src[c[i]], (int(sh[i, 0]), int(sh[i, 1])), axis=(0, 1))
+        X[i] = (amp * s + g.standard_normal((L, L))).reshape(-1)
+    return X, c, sh
