@@ -5,12 +5,14 @@
 //   s*   = argmax_s C(s),  PCE = C(s*)^2 (L^2 - |N|) / sum_{s not in N} C(s)^2,
 //   N    = the (2h+1) x (2h+1) cyclic neighbourhood of s*.
 //
-// Prepare (l's GPU stage): one workgroup per item removes the mean (FP64) and transforms
-// the item with a 2-D FFT in LDS; spectra F are stored in natural order, complex f32.
+// Prepare (l's GPU stage): one workgroup per item removes the mean and scales to unit norm
+// (FP64; PCE does not depend on either) and transforms the item with a 2-D FFT in LDS;
+// spectra F are stored in natural order, complex f32.
 // Compare: a persistent kernel pulls tiles of T x T item pairs from the work queue (the
-// spectra of a tile's 2T items stay in L2); per pair one workgroup forms conj(F_a) F_b in
-// LDS, transforms it forward (the real part is L^2 C(s); the scale cancels in PCE), finds
-// the peak and the energy outside its neighbourhood, and writes PCE and the peak shift.
+// spectra of a tile's 2T items stay in L2); per two pairs one workgroup forms
+// conj(F_a) F_b + i conj(F_c) F_d in LDS and transforms it forward: the real part is L^2 times
+// the first pair's C(s), the imaginary part the second's (both are real).  Per pair it finds
+// the peak and the energy outside its neighbourhood and writes PCE and the peak shift.
 //
 // The L-point FFTs are four-step L = N1 x N2 transforms: N1-point DFTs in registers
 // (radix-2, decimation in frequency), twiddles W_L^(n2 k1) from an LDS table, N2-point
@@ -26,7 +28,8 @@
 namespace rk {
 namespace {
 
-constexpr int PCE_THREADS = 256;
+constexpr int PCE_THREADS = 256;  // prepare
+constexpr int PCE_CMP_THREADS = 512;  // compare: two waves per SIMD hide LDS and L2 latency
 constexpr int PCE_T = 8;  // items per block of the tile grid
 
 // cos(pi m / 8) and sin(pi m / 8), m = 0..15
@@ -87,7 +90,7 @@ __device__ __forceinline__ constexpr int bitrev(int k)
 
 // One 2-D forward FFT of the L x L complex array at `a` (row stride RS = L + 1) in place.
 // `tw` holds W_L^m, m = 0..L-1.  Position (pr, pc) ends holding frequency (k(pr), k(pc)).
-template <int L, int N1, int N2>
+template <int L, int N1, int N2, int NT>
 __device__ void fft2d(float2 *a, const float2 *tw)
 {
     constexpr int RS = L + 1;
@@ -96,7 +99,7 @@ __device__ void fft2d(float2 *a, const float2 *tw)
         // rows: vector v at v*RS, element stride 1; columns: vector v at v, stride RS
         const int vstride = dim == 0 ? RS : 1, estride = dim == 0 ? 1 : RS;
         // step A: for every (v, n2): N1-point DFT over n1 of x[N2 n1 + n2], twiddle W_L^(n2 k1)
-        for (int id = threadIdx.x; id < L * N2; id += PCE_THREADS) {
+        for (int id = threadIdx.x; id < L * N2; id += NT) {
             const int v = id % L, n2 = id / L;
             float2 *p = a + v * vstride + n2 * estride;
             float2 x[N1];
@@ -108,7 +111,7 @@ __device__ void fft2d(float2 *a, const float2 *tw)
         }
         __syncthreads();
         // step B: for every (v, k1): N2-point DFT over n2 of y[N2 k1 + n2], written back in place
-        for (int id = threadIdx.x; id < L * N1; id += PCE_THREADS) {
+        for (int id = threadIdx.x; id < L * N1; id += NT) {
             const int v = id % L, k1 = id / L;
             float2 *p = a + v * vstride + k1 * N2 * estride;
             float2 x[N2];
@@ -125,7 +128,7 @@ __device__ void fft2d(float2 *a, const float2 *tw)
 template <int L>
 __device__ void fill_twiddles(float2 *tw)
 {
-    for (int m = threadIdx.x; m < L; m += PCE_THREADS) {
+    for (int m = threadIdx.x; m < L; m += blockDim.x) {
         double s, c;
         sincospi(-2.0 * m / L, &s, &c);
         tw[m] = make_float2((float)c, (float)s);
@@ -147,7 +150,7 @@ __device__ __forceinline__ int pos_of(int k)
 // Prepare: grid = n items.  X: f32 [n][ld], item = L*L values row-major.  F: [n][L*L] float2.
 template <int L, int N1, int N2>
 __global__ __launch_bounds__(PCE_THREADS) void k_pce_prepare(const float *__restrict__ X, int64_t ld,
-                                                             float2 *__restrict__ F)
+                                                             float2 *__restrict__ F, int *__restrict__ live)
 {
     constexpr int RS = L + 1;
     extern __shared__ float2 sm[];
@@ -161,27 +164,44 @@ __global__ __launch_bounds__(PCE_THREADS) void k_pce_prepare(const float *__rest
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
     const double mean = ((red[0] + red[1]) + (red[2] + red[3])) / (double)(L * L);
-    for (int i = threadIdx.x; i < L * L; i += PCE_THREADS)
-        a[(i / L) * RS + i % L] = make_float2((float)((double)x[i] - mean), 0.f);
     __syncthreads();
-    fft2d<L, N1, N2>(a, tw);
+    // unit norm: correlation scale is the same for every pair (two pairs share one FFT)
+    double q = 0.0;
+    for (int i = threadIdx.x; i < L * L; i += PCE_THREADS) {
+        const double c = (double)x[i] - mean;
+        q = fma(c, c, q);
+    }
+    for (int o = 32; o > 0; o >>= 1) q += __shfl_xor(q, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = q;
+    __syncthreads();
+    const double ss = (red[0] + red[1]) + (red[2] + red[3]);
+    const double inv = ss > 0.0 ? 1.0 / sqrt(ss) : 0.0;  // a constant item gets a zero spectrum
+    if (threadIdx.x == 0) live[blockIdx.x] = ss > 0.0;
+    for (int i = threadIdx.x; i < L * L; i += PCE_THREADS)
+        a[(i / L) * RS + i % L] = make_float2((float)(((double)x[i] - mean) * inv), 0.f);
+    __syncthreads();
+    fft2d<L, N1, N2, PCE_THREADS>(a, tw);
     float2 *f = F + (int64_t)blockIdx.x * L * L;
     for (int i = threadIdx.x; i < L * L; i += PCE_THREADS)
         f[i] = a[pos_of<N1, N2>(i / L) * RS + pos_of<N1, N2>(i % L)];
 }
 
-// Compare: persistent; work item = tile (bi, bj) of PCE_T-item blocks, bi <= bj.
+// Compare: persistent; work item = tile (bi, bj) of PCE_T-item blocks, bi <= bj.  The
+// tile's pairs are taken two at a time: C1 and C2 are real, so one forward FFT of
+// conj(Z1) + i conj(Z2) gives L^2 C1 in the real and L^2 C2 in the imaginary part.
 template <int L, int N1, int N2>
-__global__ __launch_bounds__(PCE_THREADS, 1) void k_pce(const float2 *__restrict__ F, int n, int h, QueueArgs q,
-                                                        float *__restrict__ out, uint32_t *__restrict__ peak_out)
+__global__ __launch_bounds__(PCE_CMP_THREADS, 1) void k_pce(const float2 *__restrict__ F, const int *__restrict__ live,
+                                                            int n, int h, QueueArgs q, float *__restrict__ out,
+                                                            uint32_t *__restrict__ peak_out)
 {
     constexpr int RS = L + 1;
     constexpr int NV = L * L;
+    constexpr int NT = PCE_CMP_THREADS, NW = NT / 64;
     extern __shared__ float2 sm[];
     float2 *a = sm, *tw = sm + L * RS;
-    __shared__ float s_val[PCE_THREADS / 64];
-    __shared__ int s_idx[PCE_THREADS / 64];
-    __shared__ double s_sum[PCE_THREADS / 64];
+    __shared__ float s_val[2][NW];
+    __shared__ int s_idx[2][NW];
+    __shared__ double s_sum[2][NW];
     __shared__ int s_item;
     fill_twiddles<L>(tw);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -191,75 +211,124 @@ __global__ __launch_bounds__(PCE_THREADS, 1) void k_pce(const float2 *__restrict
         if (it < 0) break;
         const int4 w = q.items[it];
         const int i0 = w.x * PCE_T, i1 = min(n, i0 + PCE_T), j0 = w.y * PCE_T, j1 = min(n, j0 + PCE_T);
-        for (int i = i0; i < i1; ++i) {
-            for (int j = max(j0, i + 1); j < j1; ++j) {
-                const float2 *fa = F + (int64_t)i * NV, *fb = F + (int64_t)j * NV;
-                // conj(F_a) F_b = conj(F_a conj(F_b)): its forward FFT is L^2 conj(C)
-                for (int e = threadIdx.x; e < NV; e += PCE_THREADS) {
-                    const float2 u = fa[e], v = fb[e];
-                    a[(e / L) * RS + e % L] = make_float2(fmaf(u.x, v.x, u.y * v.y), fmaf(u.x, v.y, -(u.y * v.x)));
+        // pairs of the tile in row-major order, i < j
+        int pi[2], pj[2], np = 0;
+        int ci = i0, cj = max(j0, i0 + 1);
+        auto next_pair = [&](int &oi, int &oj) -> bool {
+            while (ci < i1 && cj >= j1) {
+                ++ci;
+                cj = max(j0, ci + 1);
+            }
+            if (ci >= i1) return false;
+            oi = ci;
+            oj = cj++;
+            return true;
+        };
+        for (;;) {
+            np = 0;
+            if (next_pair(pi[0], pj[0])) ++np;
+            if (np == 1 && next_pair(pi[1], pj[1])) ++np;
+            if (np == 0) break;
+            const float2 *fa0 = F + (int64_t)pi[0] * NV, *fb0 = F + (int64_t)pj[0] * NV;
+            const float2 *fa1 = F + (int64_t)pi[np - 1] * NV, *fb1 = F + (int64_t)pj[np - 1] * NV;
+            const bool two = np == 2;
+#pragma unroll 4
+            for (int e = threadIdx.x; e < NV; e += NT) {
+                // conj(Z) = conj(F_a) F_b for each pair; pack the second as the imaginary part
+                const float2 u = fa0[e], v = fb0[e];
+                float2 z = make_float2(fmaf(u.x, v.x, u.y * v.y), fmaf(u.x, v.y, -(u.y * v.x)));
+                if (two) {
+                    const float2 u2 = fa1[e], v2 = fb1[e];
+                    const float2 z2 = make_float2(fmaf(u2.x, v2.x, u2.y * v2.y), fmaf(u2.x, v2.y, -(u2.y * v2.x)));
+                    z = make_float2(z.x - z2.y, z.y + z2.x);  // z + i z2
                 }
-                __syncthreads();
-                fft2d<L, N1, N2>(a, tw);
-                // peak: largest real part, smallest shift index on ties
-                float best = -INFINITY;
-                int bidx = 0x7fffffff;
-                for (int e = threadIdx.x; e < NV; e += PCE_THREADS) {
-                    const int pr = e / L, pc = e % L;
-                    const float v = a[pr * RS + pc].x;
-                    const int k = freq_of<N1, N2>(pr) * L + freq_of<N1, N2>(pc);
-                    if (v > best || (v == best && k < bidx)) {
-                        best = v;
-                        bidx = k;
-                    }
+                a[(e / L) * RS + e % L] = z;
+            }
+            __syncthreads();
+            fft2d<L, N1, N2, NT>(a, tw);
+            // peaks: largest value per channel, smallest shift index on ties
+            float best[2] = {-INFINITY, -INFINITY};
+            int bidx[2] = {0x7fffffff, 0x7fffffff};
+            for (int e = threadIdx.x; e < NV; e += NT) {
+                const int pr = e / L, pc = e % L;
+                const float2 v = a[pr * RS + pc];
+                const int k = freq_of<N1, N2>(pr) * L + freq_of<N1, N2>(pc);
+                if (v.x > best[0] || (v.x == best[0] && k < bidx[0])) {
+                    best[0] = v.x;
+                    bidx[0] = k;
                 }
+                if (v.y > best[1] || (v.y == best[1] && k < bidx[1])) {
+                    best[1] = v.y;
+                    bidx[1] = k;
+                }
+            }
+#pragma unroll
+            for (int ch = 0; ch < 2; ++ch) {
                 for (int o = 32; o > 0; o >>= 1) {
-                    const float ov = __shfl_xor(best, o);
-                    const int oi = __shfl_xor(bidx, o);
-                    if (ov > best || (ov == best && oi < bidx)) {
-                        best = ov;
-                        bidx = oi;
+                    const float ov = __shfl_xor(best[ch], o);
+                    const int oi = __shfl_xor(bidx[ch], o);
+                    if (ov > best[ch] || (ov == best[ch] && oi < bidx[ch])) {
+                        best[ch] = ov;
+                        bidx[ch] = oi;
                     }
                 }
                 if (lane == 0) {
-                    s_val[wave] = best;
-                    s_idx[wave] = bidx;
+                    s_val[ch][wave] = best[ch];
+                    s_idx[ch][wave] = bidx[ch];
                 }
-                __syncthreads();
-                float pv = s_val[0];
-                int pk = s_idx[0];
-                for (int ww = 1; ww < PCE_THREADS / 64; ++ww)
-                    if (s_val[ww] > pv || (s_val[ww] == pv && s_idx[ww] < pk)) {
-                        pv = s_val[ww];
-                        pk = s_idx[ww];
+            }
+            __syncthreads();
+            float pv[2];
+            int pk[2];
+#pragma unroll
+            for (int ch = 0; ch < 2; ++ch) {
+                pv[ch] = s_val[ch][0];
+                pk[ch] = s_idx[ch][0];
+                for (int ww = 1; ww < NW; ++ww)
+                    if (s_val[ch][ww] > pv[ch] || (s_val[ch][ww] == pv[ch] && s_idx[ch][ww] < pk[ch])) {
+                        pv[ch] = s_val[ch][ww];
+                        pk[ch] = s_idx[ch][ww];
                     }
-                const int r0 = pk / L, c0 = pk % L;
-                // energy outside the cyclic neighbourhood of the peak, FP64, fixed order
-                double en = 0.0;
-                for (int e = threadIdx.x; e < NV; e += PCE_THREADS) {
-                    const int pr = e / L, pc = e % L;
-                    const int kr = freq_of<N1, N2>(pr), kc = freq_of<N1, N2>(pc);
-                    int dr = kr - r0, dc = kc - c0;
+            }
+            // energy outside the cyclic neighbourhood of each peak, FP64, fixed order
+            double en[2] = {0.0, 0.0};
+            const int r0[2] = {pk[0] / L, pk[1] / L}, c0[2] = {pk[0] % L, pk[1] % L};
+            for (int e = threadIdx.x; e < NV; e += NT) {
+                const int pr = e / L, pc = e % L;
+                const int kr = freq_of<N1, N2>(pr), kc = freq_of<N1, N2>(pc);
+                const float2 v = a[pr * RS + pc];
+#pragma unroll
+                for (int ch = 0; ch < 2; ++ch) {
+                    int dr = kr - r0[ch], dc = kc - c0[ch];
                     dr = dr < 0 ? -dr : dr;
                     dc = dc < 0 ? -dc : dc;
                     dr = min(dr, L - dr);
                     dc = min(dc, L - dc);
                     if (dr <= h && dc <= h) continue;
-                    const double v = (double)a[pr * RS + pc].x;
-                    en = fma(v, v, en);
+                    const double x = (double)(ch ? v.y : v.x);
+                    en[ch] = fma(x, x, en[ch]);
                 }
-                for (int o = 32; o > 0; o >>= 1) en += __shfl_xor(en, o);
-                if (lane == 0) s_sum[wave] = en;
-                __syncthreads();
-                if (threadIdx.x == 0) {
-                    const double rest = (s_sum[0] + s_sum[1]) + (s_sum[2] + s_sum[3]);
-                    const double num = (double)pv * (double)pv * (double)(NV - nb_side * nb_side);
-                    const int64_t pidx = (int64_t)i * n - (int64_t)i * (i + 1) / 2 + (j - i - 1);
-                    out[pidx] = rest > 0.0 ? (float)(num / rest) : __builtin_nanf("");
-                    if (peak_out) peak_out[pidx] = (uint32_t)pk;
-                }
-                __syncthreads();  // LDS is refilled by the next pair
             }
+#pragma unroll
+            for (int ch = 0; ch < 2; ++ch) {
+                for (int o = 32; o > 0; o >>= 1) en[ch] += __shfl_xor(en[ch], o);
+                if (lane == 0) s_sum[ch][wave] = en[ch];
+            }
+            __syncthreads();
+            if (threadIdx.x < np) {
+                const int ch = threadIdx.x;
+                double rest = 0.0;
+                for (int ww = 0; ww < NW; ++ww) rest += s_sum[ch][ww];
+                const double num = (double)pv[ch] * (double)pv[ch] * (double)(NV - nb_side * nb_side);
+                const int i = pi[ch], j = pj[ch];
+                const int64_t pidx = (int64_t)i * n - (int64_t)i * (i + 1) / 2 + (j - i - 1);
+                // a zero-variance item has no correlation: its channel holds only the other
+                // channel's rounding, so it is reported as NaN with peak 0
+                const bool ok = live[i] && live[j] && rest > 0.0;
+                out[pidx] = ok ? (float)(num / rest) : __builtin_nanf("");
+                if (peak_out) peak_out[pidx] = ok ? (uint32_t)pk[ch] : 0u;
+            }
+            __syncthreads();  // LDS is refilled by the next pairs
         }
     }
 }
@@ -306,7 +375,9 @@ rocket_status pce_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, hi
     p.n = n;
     p.L = L;
     void *spec = nullptr;
-    RK_TRY(ws_get(ctx, WS_PCE_SPEC, (size_t)std::max<int64_t>(n, 1) * L * L * sizeof(float2), &spec));
+    const size_t spec_bytes = (size_t)std::max<int64_t>(n, 1) * L * L * sizeof(float2);
+    RK_TRY(ws_get(ctx, WS_PCE_SPEC, spec_bytes + sizeof(int) * (size_t)std::max<int64_t>(n, 1), &spec));
+    int *live = (int *)((char *)spec + spec_bytes);  // per item: non-zero variance
     if (n > 0) {
         const size_t lds = L == 32 ? pce_lds<32>() : L == 64 ? pce_lds<64>() : pce_lds<128>();
         const void *kp = L == 32   ? (const void *)&k_pce_prepare<32, 8, 4>
@@ -315,13 +386,13 @@ rocket_status pce_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, hi
         RK_HIP(hipFuncSetAttribute(kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         if (L == 32)
             hipLaunchKernelGGL((k_pce_prepare<32, 8, 4>), dim3((unsigned)n), dim3(PCE_THREADS), lds, s, it->dense,
-                               it->ld, (float2 *)spec);
+                               it->ld, (float2 *)spec, live);
         else if (L == 64)
             hipLaunchKernelGGL((k_pce_prepare<64, 8, 8>), dim3((unsigned)n), dim3(PCE_THREADS), lds, s, it->dense,
-                               it->ld, (float2 *)spec);
+                               it->ld, (float2 *)spec, live);
         else
             hipLaunchKernelGGL((k_pce_prepare<128, 16, 8>), dim3((unsigned)n), dim3(PCE_THREADS), lds, s, it->dense,
-                               it->ld, (float2 *)spec);
+                               it->ld, (float2 *)spec, live);
         RK_HIP(hipGetLastError());
     }
     std::vector<int2> tiles;
@@ -356,17 +427,20 @@ rocket_status pce_compare(rocket_ctx *ctx, float *out, uint32_t *peak, hipStream
     const size_t lds = L == 32 ? pce_lds<32>() : L == 64 ? pce_lds<64>() : pce_lds<128>();
     const void *kp = L == 32 ? pce_kernel<32>() : L == 64 ? pce_kernel<64>() : pce_kernel<128>();
     RK_HIP(hipFuncSetAttribute(kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    const int grid = auto_grid(ctx, kp, PCE_THREADS, lds, p.tiles);
+    const int grid = auto_grid(ctx, kp, PCE_CMP_THREADS, lds, p.tiles);
     ctx->stats.grid = grid;
     RK_TRY(reset_queue(ctx, s, p.qa));
     const float2 *F = (const float2 *)ctx->ws[WS_PCE_SPEC].ptr;
+    const int *live = (const int *)((const char *)F + (size_t)p.n * L * L * sizeof(float2));
     RK_TRY(timing_begin(ctx, s));
     if (L == 32)
-        hipLaunchKernelGGL((k_pce<32, 8, 4>), dim3(grid), dim3(PCE_THREADS), lds, s, F, (int)p.n, h, p.qa, out, peak);
+        hipLaunchKernelGGL((k_pce<32, 8, 4>), dim3(grid), dim3(PCE_CMP_THREADS), lds, s, F, live, (int)p.n, h, p.qa, out,
+                           peak);
     else if (L == 64)
-        hipLaunchKernelGGL((k_pce<64, 8, 8>), dim3(grid), dim3(PCE_THREADS), lds, s, F, (int)p.n, h, p.qa, out, peak);
+        hipLaunchKernelGGL((k_pce<64, 8, 8>), dim3(grid), dim3(PCE_CMP_THREADS), lds, s, F, live, (int)p.n, h, p.qa, out,
+                           peak);
     else
-        hipLaunchKernelGGL((k_pce<128, 16, 8>), dim3(grid), dim3(PCE_THREADS), lds, s, F, (int)p.n, h, p.qa, out,
+        hipLaunchKernelGGL((k_pce<128, 16, 8>), dim3(grid), dim3(PCE_CMP_THREADS), lds, s, F, live, (int)p.n, h, p.qa, out,
                            peak);
     RK_HIP(hipGetLastError());
     RK_TRY(timing_end(ctx, s));

@@ -130,3 +130,16 @@ def test_errors(ctx):
         ctx.allpairs(torch.zeros((4, 1024), device="cuda"), "pce")
     assert e.value.status == E_INVALID
     ctx.set(pce_radius=0)
+
+
+def test_items_of_very_different_scale(ctx):
+    # PCE does not depend on an item's scale; two pairs share one FFT, so the library must
+    # not let a large pair drown a small one
+    announce("pce mixed scales")
+    L = 64
+    X, _, _ = synth.noise_images(16, L, nsrc=2, amp=0.3, config=6, salt=9)
+    g = np.random.default_rng(2)
+    X = (X * (10.0 ** g.uniform(-4, 4, (16, 1)))).astype(np.float32)
+    got, gpk = _run(ctx, X)
+    pairs = [(i, j) for i in range(16) for j in range(i + 1, 16)]
+    _check(got, gpk, X, L, pairs)
