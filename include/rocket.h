@@ -244,7 +244,9 @@ typedef enum {
                                        rocket_allpairs_host: the whole call's device work) */
     ROCKET_OPT_CACHE_SLOTS = 14,    /* rocket_allpairs_host: device cache slots, one block of `tile` items each
                                        (0: one per block, i.e. everything stays resident); at least 2 */
-    ROCKET_OPT_PCE_RADIUS = 15      /* ROCKET_PCE: half-width h of the excluded peak neighbourhood (0: 5); h < L/2 */
+    ROCKET_OPT_PCE_RADIUS = 15,     /* ROCKET_PCE: half-width h of the excluded peak neighbourhood (0: 5); h < L/2 */
+    ROCKET_OPT_NCC_WAVES = 16       /* NCC Gram workgroup: 4 or 8 waves (0: 8 for tiles of 128 and 256; tiles of
+                                       64 always use 4) */
 } rocket_option;
 
 rocket_status rocket_set_option(rocket_ctx *ctx, rocket_option opt, int64_t value);

@@ -56,7 +56,7 @@ enum { QOWN_NONE = 0, QOWN_NCC, QOWN_OVL, QOWN_SP, QOWN_PCE };
 
 struct NccState {
     int64_t n = 0, dim = 0, ld = 0, n_pad = 0, d_pad = 0;
-    int tile = 0, nkt = 0, kt_per_chunk = 0, nchunks = 0;
+    int tile = 0, nkt = 0, kt_per_chunk = 0, nchunks = 0, waves = 4;
     int64_t tiles = 0, items = 0;
     const float *src = nullptr;
     int scheme = 0;
@@ -126,7 +126,7 @@ struct OocState {
 struct rocket_ctx {
     int device = 0;
     int num_cu = 256;
-    int64_t opt[16] = {0};
+    int64_t opt[32] = {0};  // indexed by rocket_option
     rk::Buffer ws[rk::WS_COUNT];
     int prepared_fn = 0;
     int queue_owner = 0;  // which pair function's plan the device queue holds

@@ -235,8 +235,8 @@ typedef __attribute__((address_space(1))) void *gbl_ptr_t;
 //          k = 8 + s (lanes 32-63), the same permutation for both operands
 // Output block layout (both): acc[r] of lane l is row 8*(r/4) + 4*(l/32) + r%4, col l%32.
 // ------------------------------------------------------------------------------------------
-template <int BM, int BN, int SCH>
-__global__ __launch_bounds__(256, 1) void k_ncc_gram(const char *__restrict__ planes, int kt_per_chunk, int nkt,
+template <int BM, int BN, int SCH, int NWV>
+__global__ __launch_bounds__(64 * NWV, 1) void k_ncc_gram(const char *__restrict__ planes, int kt_per_chunk, int nkt,
                                                      int nchunks, QueueArgs q, float *__restrict__ partial)
 {
     constexpr int NC = Scheme<SCH>::NC, ES = Scheme<SCH>::ES;
@@ -246,17 +246,21 @@ __global__ __launch_bounds__(256, 1) void k_ncc_gram(const char *__restrict__ pl
     constexpr int CSB = TA + TB;                     // bytes of one component, both sides
     constexpr int STAGEB = NC * CSB;
     constexpr int BLOCKS = STAGEB / 1024;            // 1 KiB wave-copies per stage
-    constexpr int BPW = BLOCKS / 4;                  // per wave
+    constexpr int BPW = BLOCKS / NWV;                // per wave
     constexpr int ROWS_PER_BLOCK = 1024 / ROWB;
     constexpr int HALVES = BM / BN;
-    constexpr int WM = BM / 2, WN = BN / 2;
+    // NWV = 4: 2 x 2 waves, one per SIMD; NWV = 8: 2 x 4 waves, two per SIMD, so one wave's
+    // waits (LDS reads, barrier, copy completion) are covered by the other's MFMAs
+    constexpr int WAVES_N = NWV / 2;
+    constexpr int WM = BM / 2, WN = BN / WAVES_N;
     constexpr int MA = WM / 32, MBN = WN / 32;
     // products (A component, B component): h*h, h*m, m*h [, h*l, l*h, m*m]
     constexpr int NP = SCH == SCH_X6 ? 6 : SCH == SCH_X3 ? 3 : 0;
     constexpr int PA[6] = {0, 0, 1, 0, 2, 1};
     constexpr int PB[6] = {0, 1, 0, 2, 0, 1};
     static_assert(TA % 1024 == 0 && TB % 1024 == 0, "tile sides must be whole 1 KiB blocks");
-    static_assert(BLOCKS % 4 == 0, "every wave issues the same number of copies");
+    static_assert(BLOCKS % NWV == 0, "every wave issues the same number of copies");
+    static_assert(NWV == 4 || NWV == 8, "4 or 8 waves");
 
     // three separately declared stage buffers: slice s is read from one while the copies of
     // slices s+1 and s+2 land in the others (the compiler can tell them apart and does not
@@ -268,7 +272,7 @@ __global__ __launch_bounds__(256, 1) void k_ncc_gram(const char *__restrict__ pl
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wv = __builtin_amdgcn_readfirstlane(wave);
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave / WAVES_N, wn = wave % WAVES_N;
     const int h = lane >> 5;
     const int lrow = lane / SEGS, pseg = lane % SEGS;
 
@@ -301,7 +305,7 @@ __global__ __launch_bounds__(256, 1) void k_ncc_gram(const char *__restrict__ pl
         auto issue = [&](int kt, char *dstbuf) {
 #pragma unroll
             for (int c = 0; c < BPW; ++c) {
-                const int b = wv + 4 * c;
+                const int b = wv + NWV * c;
                 const int comp = (b * 1024) / CSB;
                 const int inb = b * 1024 - comp * CSB;  // byte offset inside the component
                 const int side = inb >= TA;
@@ -383,7 +387,7 @@ __global__ __launch_bounds__(256, 1) void k_ncc_gram(const char *__restrict__ pl
             __syncthreads();
         };
 
-        if constexpr (SCH == SCH_FP32) {
+        if constexpr (SCH == SCH_FP32 || NWV == 8) {
             issue(kt0, lds0);
             if (kt0 + 1 < kt1) {
                 issue(kt0 + 1, lds1);
@@ -475,24 +479,32 @@ __global__ __launch_bounds__(256, 1) void k_ncc_gram(const char *__restrict__ pl
             }
         }
 
-        // partial block in MFMA-native order: float4 chunk ((m*MBN + n)*4 + q)*256 + tid holds
-        // acc[m][n][4q .. 4q+3] of this thread (four consecutive rows, one column)
-        float4 *P = (float4 *)(partial + ((int64_t)slot * nchunks + kc) * (int64_t)BM * BN) + tid;
+        // partial block as float4 [BM/4][BN]: element (r4, c) holds rows 4 r4 .. 4 r4 + 3 of
+        // column c, which is what acc[m][n][4q .. 4q+3] of a lane is (two 512-byte runs per
+        // store instruction)
+        // the block and wave part of the address is wave-uniform (scalar registers), the lane
+        // adds a 32-bit offset, so no per-store address is kept in vector registers
+        const int wmu = __builtin_amdgcn_readfirstlane(wm), wnu = __builtin_amdgcn_readfirstlane(wn);
+        char *ubase = (char *)partial + (((int64_t)slot * nchunks + kc) * (int64_t)BM * BN) * 4 +
+                      ((int64_t)(wmu * WM / 4) * BN + wnu * WN) * 16;
+        const int loff = (h * BN + (lane & 31)) * 16;
 #pragma unroll
         for (int m = 0; m < MA; ++m)
 #pragma unroll
-            for (int n = 0; n < MBN; ++n)
+            for (int qq = 0; qq < 4; ++qq)
 #pragma unroll
-                for (int qq = 0; qq < 4; ++qq)
-                    P[((m * MBN + n) * 4 + qq) * 256] =
+                for (int n = 0; n < MBN; ++n) {
+                    char *ub = ubase + ((m * 8 + 2 * qq) * BN + n * 32) * 16;
+                    *(float4 *)(ub + loff) =
                         make_float4(acc[m][n][4 * qq], acc[m][n][4 * qq + 1], acc[m][n][4 * qq + 2], acc[m][n][4 * qq + 3]);
+                }
     }
 }
 
 // ------------------------------------------------------------------------------------------
 // Epilogue: out[idx(i,j)] = (sum_c partial_c[i][j]) * inv_s[i] * inv_s[j], chunks summed in
-// ascending order.  One thread per float4 of the MFMA-native partial layout (four rows of
-// one column), so partial reads are 16-byte coalesced and output writes are 128-byte runs.
+// ascending order.  One thread per float4 of the partial layout (four rows of one column),
+// so partial reads are 16-byte coalesced and output writes are runs along j.
 // ------------------------------------------------------------------------------------------
 template <int BM, int BN>
 __global__ __launch_bounds__(256) void k_ncc_finish(const float *__restrict__ partial, const int2 *__restrict__ tiles,
@@ -501,14 +513,9 @@ __global__ __launch_bounds__(256) void k_ncc_finish(const float *__restrict__ pa
 {
     constexpr int BPB = BM * BN / 4 / 256;  // workgroups per output block
     constexpr int HALVES = BM / BN;
-    constexpr int WM = BM / 2, WN = BN / 2, MBN = WN / 32;
     const int64_t slot = blockIdx.x / BPB;
     const int t = (int)(blockIdx.x % BPB) * 256 + threadIdx.x;  // float4 index in the block
-    const int tid = t & 255, lane = tid & 63, wave = tid >> 6;
-    const int qq = (t >> 8) & 3, mn = t >> 10;
-    const int m = mn / MBN, nn = mn % MBN;
-    const int row0 = (wave >> 1) * WM + m * 32 + 8 * qq + 4 * (lane >> 5);
-    const int col = (wave & 1) * WN + nn * 32 + (lane & 31);
+    const int row0 = (t / BN) * 4, col = t % BN;
     const int2 tl = tiles[slot / HALVES];
     const int64_t j = (int64_t)tl.y * BM + (slot % HALVES) * BN + col;
     const int64_t i0 = (int64_t)tl.x * BM + row0;
@@ -547,21 +554,23 @@ constexpr int bn_of()
 }
 
 template <int BM, int SCH>
-const void *gram_ptr()
+const void *gram_ptr(int nwv)
 {
-    return (const void *)&k_ncc_gram<BM, bn_of<BM>(), SCH>;
+    if constexpr (BM >= 128)
+        if (nwv == 8) return (const void *)&k_ncc_gram<BM, bn_of<BM>(), SCH, 8>;
+    return (const void *)&k_ncc_gram<BM, bn_of<BM>(), SCH, 4>;
 }
 
 template <int SCH>
-const void *gram_ptr_bm(int bm)
+const void *gram_ptr_bm(int bm, int nwv)
 {
-    return bm == 64 ? gram_ptr<64, SCH>() : bm == 128 ? gram_ptr<128, SCH>() : gram_ptr<256, SCH>();
+    return bm == 64 ? gram_ptr<64, SCH>(nwv) : bm == 128 ? gram_ptr<128, SCH>(nwv) : gram_ptr<256, SCH>(nwv);
 }
 
-const void *gram_kernel(int bm, int sch)
+const void *gram_kernel(int bm, int sch, int nwv)
 {
-    return sch == SCH_FP32 ? gram_ptr_bm<SCH_FP32>(bm) : sch == SCH_X3 ? gram_ptr_bm<SCH_X3>(bm)
-                                                                      : gram_ptr_bm<SCH_X6>(bm);
+    return sch == SCH_FP32 ? gram_ptr_bm<SCH_FP32>(bm, nwv) : sch == SCH_X3 ? gram_ptr_bm<SCH_X3>(bm, nwv)
+                                                                            : gram_ptr_bm<SCH_X6>(bm, nwv);
 }
 
 int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
@@ -575,6 +584,14 @@ static int ncc_tile(rocket_ctx *ctx, int64_t n)
 {
     const int bm = (int)ctx->opt[ROCKET_OPT_NCC_TILE];
     return bm ? bm : n >= 1536 ? 256 : n >= 384 ? 128 : 64;
+}
+
+// Waves per Gram workgroup: 8 (two per SIMD) for tiles of 128 and 256, else 4.
+static int ncc_waves(rocket_ctx *ctx, int bm)
+{
+    const int w = (int)ctx->opt[ROCKET_OPT_NCC_WAVES];
+    if (bm < 128) return 4;
+    return w ? w : 8;
 }
 
 // Split-K chunk length: enough chunks for ~2048 work items, within [256, 2048] elements.
@@ -605,6 +622,7 @@ rocket_status ncc_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, in
     st.scheme = scheme;
     const int bm = ncc_tile(ctx, n);
     st.tile = bm;
+    st.waves = ncc_waves(ctx, bm);
     st.n_pad = round_up(std::max<int64_t>(n, 1), bm);
     st.d_pad = round_up(it->dim, 16);
     st.nkt = (int)(st.d_pad / 16);
@@ -676,7 +694,13 @@ template <int BM, int SCH>
 static void launch_gram(int grid, hipStream_t s, const char *planes, const NccState &st, const QueueArgs &qa,
                         float *partial)
 {
-    hipLaunchKernelGGL((k_ncc_gram<BM, bn_of<BM>(), SCH>), dim3(grid), dim3(256), 0, s, planes, st.kt_per_chunk,
+    if constexpr (BM >= 128)
+        if (st.waves == 8) {
+            hipLaunchKernelGGL((k_ncc_gram<BM, bn_of<BM>(), SCH, 8>), dim3(grid), dim3(512), 0, s, planes,
+                               st.kt_per_chunk, st.nkt, st.nchunks, qa, partial);
+            return;
+        }
+    hipLaunchKernelGGL((k_ncc_gram<BM, bn_of<BM>(), SCH, 4>), dim3(grid), dim3(256), 0, s, planes, st.kt_per_chunk,
                        st.nkt, st.nchunks, qa, partial);
 }
 
@@ -730,7 +754,7 @@ rocket_status ncc_compare(rocket_ctx *ctx, float *out, hipStream_t s)
     const int bn = bm;
     RK_TRY(ws_get(ctx, WS_NCC_PARTIAL, (size_t)(st.items * bm * bn * 4), &partial));
     RK_TRY(reset_queue(ctx, s, pc.qa));
-    const int grid = auto_grid(ctx, gram_kernel(bm, st.scheme), 256, 0, st.items);
+    const int grid = auto_grid(ctx, gram_kernel(bm, st.scheme, st.waves), 64 * st.waves, 0, st.items);
     ctx->stats.grid = grid;
     const char *planes = (const char *)ctx->ws[WS_NCC_PLANES].ptr;
     RK_TRY(timing_begin(ctx, s));
@@ -789,6 +813,7 @@ rocket_status ncc_allpairs_host(rocket_ctx *ctx, const float *host, int64_t n, i
     st.scheme = scheme;
     const int T = ncc_tile(ctx, n);
     st.tile = T;
+    st.waves = ncc_waves(ctx, T);
     st.n_pad = round_up(std::max<int64_t>(n, 1), T);
     st.d_pad = round_up(dim, 16);
     st.nkt = (int)(st.d_pad / 16);
@@ -950,7 +975,7 @@ rocket_status ncc_allpairs_host(rocket_ctx *ctx, const float *host, int64_t n, i
             qa.ledger = nullptr;
             qa.nseg = MAX_SEG;
             RK_TRY(reset_queue(ctx, s, qa));
-            const int grid = auto_grid(ctx, gram_kernel(T, scheme), 256, 0, b.nitems);
+            const int grid = auto_grid(ctx, gram_kernel(T, scheme, st.waves), 64 * st.waves, 0, b.nitems);
             ctx->stats.grid = grid;
             launch_gram_any(grid, s, (const char *)slots, st, qa, (float *)partial);
             RK_HIP(hipGetLastError());

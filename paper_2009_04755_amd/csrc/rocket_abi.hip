@@ -344,13 +344,15 @@ rocket_status rocket_overlap_cost_grad(rocket_ctx *ctx, const rocket_items *clou
 rocket_status rocket_set_option(rocket_ctx *ctx, rocket_option opt, int64_t value)
 {
     if (!ctx) return rk::fail(nullptr, ROCKET_E_INVALID, "ctx is NULL");
-    if (opt < ROCKET_OPT_NCC_TILE || opt > ROCKET_OPT_PCE_RADIUS) return rk::fail(ctx, ROCKET_E_UNSUPPORTED, "option");
+    if (opt < ROCKET_OPT_NCC_TILE || opt > ROCKET_OPT_NCC_WAVES) return rk::fail(ctx, ROCKET_E_UNSUPPORTED, "option");
     if (value < 0) return rk::fail(ctx, ROCKET_E_INVALID, "negative option value");
     if (opt == ROCKET_OPT_NCC_TILE && value != 0 && value != 64 && value != 128 && value != 256)
         return rk::fail(ctx, ROCKET_E_INVALID, "NCC tile must be 0, 64, 128 or 256");
     if (opt == ROCKET_OPT_NCC_KCHUNK && value % 16 != 0)
         return rk::fail(ctx, ROCKET_E_INVALID, "NCC K chunk must be a multiple of 16");
     if (opt == ROCKET_OPT_QUEUE_ORDER && value > 2) return rk::fail(ctx, ROCKET_E_INVALID, "queue order 0..2");
+    if (opt == ROCKET_OPT_NCC_WAVES && value != 0 && value != 4 && value != 8)
+        return rk::fail(ctx, ROCKET_E_INVALID, "NCC waves must be 0, 4 or 8");
     if (opt == ROCKET_OPT_OVL_VARIANT && value > 4) return rk::fail(ctx, ROCKET_E_INVALID, "overlap variant 0..4");
     if (opt == ROCKET_OPT_OVL_BLOCK && value > 64) return rk::fail(ctx, ROCKET_E_INVALID, "overlap block <= 64");
     ctx->opt[opt] = value;
@@ -360,7 +362,7 @@ rocket_status rocket_set_option(rocket_ctx *ctx, rocket_option opt, int64_t valu
 rocket_status rocket_get_option(const rocket_ctx *ctx, rocket_option opt, int64_t *value)
 {
     if (!ctx || !value) return rk::fail(nullptr, ROCKET_E_INVALID, "NULL argument");
-    if (opt < ROCKET_OPT_NCC_TILE || opt > ROCKET_OPT_PCE_RADIUS) return ROCKET_E_UNSUPPORTED;
+    if (opt < ROCKET_OPT_NCC_TILE || opt > ROCKET_OPT_NCC_WAVES) return ROCKET_E_UNSUPPORTED;
     *value = ctx->opt[opt];
     return ROCKET_OK;
 }

@@ -164,3 +164,24 @@ def test_full_scale_sampled():
     ctx.close()
     del X
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("fn", ["ncc_fp32", "ncc_bf16x3", "ncc_bf16x6"])
+@pytest.mark.parametrize("tile", [128, 256])
+def test_four_and_eight_wave_gram_agree(ctx, fn, tile):
+    # both workgroup shapes issue the same MFMA sequence per output: results are identical
+    import torch
+    announce("ncc waves 4 vs 8 tile=%d %s" % (tile, fn))
+    g = np.random.default_rng(tile)
+    X = torch.from_numpy(g.standard_normal((tile * 3 + 5, 3000)).astype(np.float32)).cuda()
+    ctx.set(ncc_tile=tile, ncc_waves=4)
+    a = ctx.allpairs(X, fn)
+    ctx.set(ncc_waves=8)
+    b = ctx.allpairs(X, fn)
+    ctx.set(ncc_tile=0, ncc_waves=0)
+    assert torch.equal(a, b)
+    n = X.shape[0]
+    pi, pj = oracle.all_pairs(n)
+    sel = np.arange(0, pi.size, 53)
+    rho, tau = oracle.ncc(X.cpu().numpy(), pi[sel], pj[sel])
+    assert floored_rel(b.cpu().numpy()[sel], rho, tau).max() <= TOL[fn]
