@@ -29,6 +29,7 @@ constexpr int LPC = 8;          // lanes per column
 constexpr int SP_THREADS = 1024;
 constexpr int CB = SP_THREADS / LPC;  // columns per block
 constexpr int UMAX = 1536;      // union capacity of one chunk (row entries)
+constexpr int SR = 4;           // column entries per lane per streaming pass
 constexpr int HBITS = 12;
 constexpr int HSIZE = 1 << HBITS;
 constexpr uint32_t EMPTY = 0xFFFFFFFFu;
@@ -186,89 +187,125 @@ __global__ __launch_bounds__(SP_THREADS, 1) void k_sparse(const uint32_t *__rest
             }
             if (tid == 0) s_ucount = 0;
             __syncthreads();
-            // 2a. insert the band's keys of this chunk
+            // 2a. insert the band's keys of this chunk (SR entries per lane per pass, all
+            // loads of a pass independent)
             int64_t rp = rpos;
             while (true) {
-                const int64_t p = rp + lane;
-                const bool in = p < rend && (uint64_t)k32[p] < K1;
-                if (in) {
-                    const uint32_t key = k32[p];
-                    uint32_t h = hslot(key);
-                    while (true) {
-                        const uint32_t old = atomicCAS(&hkey[h], EMPTY, key);
-                        if (old == EMPTY) {
-                            hidx[h] = (uint16_t)atomicAdd(&s_ucount, 1);
-                            break;
-                        }
-                        if (old == key) break;
-                        h = (h + 1) & (HSIZE - 1);
-                    }
+                uint32_t kk[SR];
+#pragma unroll
+                for (int r = 0; r < SR; ++r) {
+                    const int64_t p = rp + r * 64 + lane;
+                    kk[r] = p < rend ? k32[p] : EMPTY;
                 }
-                const int nin = __popcll(__ballot(in));
+                int nin = 0;
+#pragma unroll
+                for (int r = 0; r < SR; ++r) {
+                    const bool in = kk[r] != EMPTY && (uint64_t)kk[r] < K1;
+                    if (in) {
+                        const uint32_t key = kk[r];
+                        uint32_t h = hslot(key);
+                        while (true) {
+                            const uint32_t old = atomicCAS(&hkey[h], EMPTY, key);
+                            if (old == EMPTY) {
+                                hidx[h] = (uint16_t)atomicAdd(&s_ucount, 1);
+                                break;
+                            }
+                            if (old == key) break;
+                            h = (h + 1) & (HSIZE - 1);
+                        }
+                    }
+                    nin += __popcll(__ballot(in));
+                }
                 rp += nin;
-                if (nin < 64) break;
+                if (nin < SR * 64) break;
             }
             __syncthreads();
             // 2b. scatter the row values and presence bytes
             while (true) {
-                const int64_t p = rpos + lane;
-                const bool in = p < rend && (uint64_t)k32[p] < K1;
-                if (in) {
-                    const uint32_t key = k32[p];
-                    uint32_t h = hslot(key);
-                    while (hkey[h] != key) h = (h + 1) & (HSIZE - 1);
-                    const int u = hidx[h];
-                    uval[u * RB + wave] = vals[p];
-                    atomicOr(&upres[u * (RB / 4) + (wave >> 2)], 1u << (8 * (wave & 3)));
+                uint32_t kk[SR];
+                float vv[SR];
+#pragma unroll
+                for (int r = 0; r < SR; ++r) {
+                    const int64_t p = rpos + r * 64 + lane;
+                    const bool ok = p < rend;
+                    kk[r] = ok ? k32[p] : EMPTY;
+                    vv[r] = ok ? vals[p] : 0.f;
                 }
-                const int nin = __popcll(__ballot(in));
+                int nin = 0;
+#pragma unroll
+                for (int r = 0; r < SR; ++r) {
+                    const bool in = kk[r] != EMPTY && (uint64_t)kk[r] < K1;
+                    if (in) {
+                        const uint32_t key = kk[r];
+                        uint32_t h = hslot(key);
+                        while (hkey[h] != key) h = (h + 1) & (HSIZE - 1);
+                        const int u = hidx[h];
+                        uval[u * RB + ((((wave >> 2) + u) & 3) << 2) + (wave & 3)] = vv[r];
+                        atomicOr(&upres[u * (RB / 4) + (wave >> 2)], 1u << (8 * (wave & 3)));
+                    }
+                    nin += __popcll(__ballot(in));
+                }
                 rpos += nin;
-                if (nin < 64) break;
+                if (nin < SR * 64) break;
             }
             __syncthreads();
             prev_u = min(s_ucount, UMAX);
-            // 3. stream this column's keys of the chunk and probe
+            // 3. stream this column's keys of the chunk and probe.  Each pass loads SR keys
+            // (and values) per lane, SR*LPC consecutive entries per column, with no
+            // dependence between the loads, so one memory latency covers SR*LPC entries.
             float cd[RB];
 #pragma unroll
             for (int t = 0; t < RB; ++t) cd[t] = 0.f;
             uint32_t pk[RB / 4] = {0u, 0u, 0u, 0u};
             int since = 0;
             while (true) {
-                const int64_t p = cpos + sub;
-                const bool in = p < cend && (uint64_t)k32[p] < K1;
-                if (in) {
-                    const uint32_t key = k32[p];
-                    const float vj = vals[p];
-                    uint32_t h = hslot(key);
-                    uint32_t hk;
-                    while ((hk = hkey[h]) != key && hk != EMPTY) h = (h + 1) & (HSIZE - 1);
-                    if (hk == key) {
-                        const int u = hidx[h];
-                        const float4 *uv = (const float4 *)&uval[u * RB];
+                uint32_t kk[SR];
+                float vv[SR];
 #pragma unroll
-                        for (int qd = 0; qd < RB / 4; ++qd) {
-                            const float4 v4 = uv[qd];
-                            cd[4 * qd] = fmaf(v4.x, vj, cd[4 * qd]);
-                            cd[4 * qd + 1] = fmaf(v4.y, vj, cd[4 * qd + 1]);
-                            cd[4 * qd + 2] = fmaf(v4.z, vj, cd[4 * qd + 2]);
-                            cd[4 * qd + 3] = fmaf(v4.w, vj, cd[4 * qd + 3]);
-                        }
-                        const uint4 pr = *(const uint4 *)&upres[u * (RB / 4)];
-                        pk[0] += pr.x;
-                        pk[1] += pr.y;
-                        pk[2] += pr.z;
-                        pk[3] += pr.w;
-                        if (++since == 255) {  // unpack before a byte counter can wrap
+                for (int r = 0; r < SR; ++r) {
+                    const int64_t p = cpos + r * LPC + sub;
+                    const bool ok = p < cend;
+                    kk[r] = ok ? k32[p] : EMPTY;
+                    vv[r] = ok ? vals[p] : 0.f;
+                }
+                int nin = 0;
 #pragma unroll
-                            for (int t = 0; t < RB; ++t) cnt[t] += (pk[t >> 2] >> (8 * (t & 3))) & 0xFFu;
-                            pk[0] = pk[1] = pk[2] = pk[3] = 0u;
-                            since = 0;
+                for (int r = 0; r < SR; ++r) {
+                    const bool in = kk[r] != EMPTY && (uint64_t)kk[r] < K1;
+                    if (in) {
+                        const uint32_t key = kk[r];
+                        const float vj = vv[r];
+                        uint32_t h = hslot(key);
+                        uint32_t hk;
+                        while ((hk = hkey[h]) != key && hk != EMPTY) h = (h + 1) & (HSIZE - 1);
+                        if (hk == key) {
+                            const int u = hidx[h];
+                            const float4 *uv = (const float4 *)&uval[u * RB];
+#pragma unroll
+                            for (int qd = 0; qd < RB / 4; ++qd) {
+                                const float4 v4 = uv[(qd + u) & 3];  // rows 4 qd .. 4 qd + 3 (swizzled)
+                                cd[4 * qd] = fmaf(v4.x, vj, cd[4 * qd]);
+                                cd[4 * qd + 1] = fmaf(v4.y, vj, cd[4 * qd + 1]);
+                                cd[4 * qd + 2] = fmaf(v4.z, vj, cd[4 * qd + 2]);
+                                cd[4 * qd + 3] = fmaf(v4.w, vj, cd[4 * qd + 3]);
+                            }
+                            const uint4 pr = *(const uint4 *)&upres[u * (RB / 4)];
+                            pk[0] += pr.x;
+                            pk[1] += pr.y;
+                            pk[2] += pr.z;
+                            pk[3] += pr.w;
+                            if (++since == 255) {  // unpack before a byte counter can wrap
+#pragma unroll
+                                for (int t = 0; t < RB; ++t) cnt[t] += (pk[t >> 2] >> (8 * (t & 3))) & 0xFFu;
+                                pk[0] = pk[1] = pk[2] = pk[3] = 0u;
+                                since = 0;
+                            }
                         }
                     }
+                    nin += __popcll(__ballot(in) & gmask);
                 }
-                const int nin = __popcll(__ballot(in) & gmask);
                 cpos += nin;
-                if (nin < LPC) break;
+                if (nin < SR * LPC) break;
             }
 #pragma unroll
             for (int t = 0; t < RB; ++t) {
