@@ -398,7 +398,7 @@ def main():
                    "kchunk": st["kchunk"], "work_items": st["work_items"], "grid": st["grid"]},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_BF16, "traffic": traffic,
-                     "kernel": "k_ncc_gram<256, bf16x6>", "kernel_ms": kern * 1e3,
+                     "kernel": "k_ncc_gram<256, 256, bf16x6, 8 waves>", "kernel_ms": kern * 1e3,
                      "algorithmic_flop_per_launch": flop, "issued_mfma_flop_per_launch": issued,
                      "issued_frac": issued / kern / 1e12 / PEAK_BF16},
     }
