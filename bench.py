@@ -205,13 +205,13 @@ def pce_pair_fn(ctx, with_cpu=True):
     out = torch.empty(P, device="cuda")
     dt, kern = _time_fn(ctx, Xd, "pce", out, 3, 1)
     # LDS bytes per pair of the in-LDS design, per FFT shared by two pairs: product tile
-    # written, four FFT steps read and write the L x L complex tile, two statistics passes
-    lds_bytes = (1 + 8 + 2) * L * L * 8 / 2
+    # written, four FFT steps read and write the L x L complex tile, one statistics pass
+    lds_bytes = (1 + 8 + 1) * L * L * 8 / 2
     res = {"workload": "1024 noise images 128 x 128 (16 sources, amp 0.3, 25 % shifted crops), h = 5",
            "pairs_per_s": 3 * P / dt, "kernel_ms": kern * 1e3,
            "roofline": {"bound": "lds", "achieved": P * lds_bytes / kern / 1e9, "peak": PEAK_LDS, "unit": "GB/s",
                         "frac": P * lds_bytes / kern / 1e9 / PEAK_LDS,
-                        "model": "11 L^2 complex f32 LDS passes per FFT, one FFT per two pairs"}}
+                        "model": "10 L^2 complex f32 LDS passes per FFT, one FFT per two pairs"}}
     if with_cpu:
         import oracle.pce as opce
         g = np.random.default_rng(8)

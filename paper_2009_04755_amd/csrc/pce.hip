@@ -197,11 +197,13 @@ __global__ __launch_bounds__(PCE_CMP_THREADS, 1) void k_pce(const float2 *__rest
     constexpr int RS = L + 1;
     constexpr int NV = L * L;
     constexpr int NT = PCE_CMP_THREADS, NW = NT / 64;
+    static_assert(NT == 512 && NT % L == 0, "two channels of 256 threads; whole rows per pass");
     extern __shared__ float2 sm[];
     float2 *a = sm, *tw = sm + L * RS;
     __shared__ float s_val[2][NW];
     __shared__ int s_idx[2][NW];
     __shared__ double s_sum[2][NW];
+    __shared__ double s_in[NW];
     __shared__ int s_item;
     fill_twiddles<L>(tw);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -232,34 +234,55 @@ __global__ __launch_bounds__(PCE_CMP_THREADS, 1) void k_pce(const float2 *__rest
             const float2 *fa0 = F + (int64_t)pi[0] * NV, *fb0 = F + (int64_t)pj[0] * NV;
             const float2 *fa1 = F + (int64_t)pi[np - 1] * NV, *fb1 = F + (int64_t)pj[np - 1] * NV;
             const bool two = np == 2;
-#pragma unroll 4
-            for (int e = threadIdx.x; e < NV; e += NT) {
-                // conj(Z) = conj(F_a) F_b for each pair; pack the second as the imaginary part
-                const float2 u = fa0[e], v = fb0[e];
-                float2 z = make_float2(fmaf(u.x, v.x, u.y * v.y), fmaf(u.x, v.y, -(u.y * v.x)));
-                if (two) {
-                    const float2 u2 = fa1[e], v2 = fb1[e];
-                    const float2 z2 = make_float2(fmaf(u2.x, v2.x, u2.y * v2.y), fmaf(u2.x, v2.y, -(u2.y * v2.x)));
-                    z = make_float2(z.x - z2.y, z.y + z2.x);  // z + i z2
+            // conj(Z) = conj(F_a) F_b for each pair; the second is packed as the imaginary part.
+            // The spectra come from L2/HBM: LB elements per thread are loaded before any is
+            // used, so LB x 4 loads per thread are in flight at once.
+            constexpr int PER = NV / NT, LB = PER < 8 ? PER : 8;
+            static_assert(PER % LB == 0, "load batches");
+#pragma unroll 1
+            for (int e0 = 0; e0 < PER; e0 += LB) {
+                float2 u[LB], v[LB], u2[LB], v2[LB];
+#pragma unroll
+                for (int b = 0; b < LB; ++b) {
+                    const int e = (e0 + b) * NT + threadIdx.x;
+                    u[b] = fa0[e];
+                    v[b] = fb0[e];
+                    u2[b] = two ? fa1[e] : make_float2(0.f, 0.f);
+                    v2[b] = two ? fb1[e] : make_float2(0.f, 0.f);
                 }
-                a[(e / L) * RS + e % L] = z;
+#pragma unroll
+                for (int b = 0; b < LB; ++b) {
+                    const int e = (e0 + b) * NT + threadIdx.x;
+                    const float2 z = make_float2(fmaf(u[b].x, v[b].x, u[b].y * v[b].y),
+                                                 fmaf(u[b].x, v[b].y, -(u[b].y * v[b].x)));
+                    const float2 z2 = make_float2(fmaf(u2[b].x, v2[b].x, u2[b].y * v2[b].y),
+                                                  fmaf(u2[b].x, v2[b].y, -(u2[b].y * v2[b].x)));
+                    a[(e / L) * RS + e % L] = make_float2(z.x - z2.y, z.y + z2.x);  // z + i z2
+                }
             }
             __syncthreads();
             fft2d<L, N1, N2, NT>(a, tw);
-            // peaks: largest value per channel, smallest shift index on ties
+            // one pass: peak per channel (largest value, smallest shift index on ties) and the
+            // total energy (FP64).  Thread = one column position, every (NT / L)-th row.
             float best[2] = {-INFINITY, -INFINITY};
             int bidx[2] = {0x7fffffff, 0x7fffffff};
-            for (int e = threadIdx.x; e < NV; e += NT) {
-                const int pr = e / L, pc = e % L;
-                const float2 v = a[pr * RS + pc];
-                const int k = freq_of<N1, N2>(pr) * L + freq_of<N1, N2>(pc);
-                if (v.x > best[0] || (v.x == best[0] && k < bidx[0])) {
-                    best[0] = v.x;
-                    bidx[0] = k;
-                }
-                if (v.y > best[1] || (v.y == best[1] && k < bidx[1])) {
-                    best[1] = v.y;
-                    bidx[1] = k;
+            double en[2] = {0.0, 0.0};
+            {
+                constexpr int RSTEP = NT / L;
+                const int pc = threadIdx.x % L, kc = freq_of<N1, N2>(pc);
+                for (int pr = threadIdx.x / L; pr < L; pr += RSTEP) {
+                    const float2 v = a[pr * RS + pc];
+                    const int k = freq_of<N1, N2>(pr) * L + kc;
+                    if (v.x > best[0] || (v.x == best[0] && k < bidx[0])) {
+                        best[0] = v.x;
+                        bidx[0] = k;
+                    }
+                    if (v.y > best[1] || (v.y == best[1] && k < bidx[1])) {
+                        best[1] = v.y;
+                        bidx[1] = k;
+                    }
+                    en[0] = fma((double)v.x, (double)v.x, en[0]);
+                    en[1] = fma((double)v.y, (double)v.y, en[1]);
                 }
             }
 #pragma unroll
@@ -271,10 +294,12 @@ __global__ __launch_bounds__(PCE_CMP_THREADS, 1) void k_pce(const float2 *__rest
                         best[ch] = ov;
                         bidx[ch] = oi;
                     }
+                    en[ch] += __shfl_xor(en[ch], o);
                 }
                 if (lane == 0) {
                     s_val[ch][wave] = best[ch];
                     s_idx[ch][wave] = bidx[ch];
+                    s_sum[ch][wave] = en[ch];
                 }
             }
             __syncthreads();
@@ -290,35 +315,29 @@ __global__ __launch_bounds__(PCE_CMP_THREADS, 1) void k_pce(const float2 *__rest
                         pk[ch] = s_idx[ch][ww];
                     }
             }
-            // energy outside the cyclic neighbourhood of each peak, FP64, fixed order
-            double en[2] = {0.0, 0.0};
-            const int r0[2] = {pk[0] / L, pk[1] / L}, c0[2] = {pk[0] % L, pk[1] % L};
-            for (int e = threadIdx.x; e < NV; e += NT) {
-                const int pr = e / L, pc = e % L;
-                const int kr = freq_of<N1, N2>(pr), kc = freq_of<N1, N2>(pc);
-                const float2 v = a[pr * RS + pc];
-#pragma unroll
-                for (int ch = 0; ch < 2; ++ch) {
-                    int dr = kr - r0[ch], dc = kc - c0[ch];
-                    dr = dr < 0 ? -dr : dr;
-                    dc = dc < 0 ? -dc : dc;
-                    dr = min(dr, L - dr);
-                    dc = min(dc, L - dc);
-                    if (dr <= h && dc <= h) continue;
+            // energy inside the cyclic neighbourhood of each peak: one thread per shift of it
+            {
+                const int side = nb_side, cells = side * side;
+                const int ch = threadIdx.x >= 256 ? 1 : 0, c = threadIdx.x & 255;
+                double inside = 0.0;
+                const int r0 = pk[ch] / L, c0 = pk[ch] % L;
+                for (int cc = c; cc < cells; cc += 256) {
+                    const int kr = (r0 + cc / side - h + L) % L, kc = (c0 + cc % side - h + L) % L;
+                    const float2 v = a[pos_of<N1, N2>(kr) * RS + pos_of<N1, N2>(kc)];
                     const double x = (double)(ch ? v.y : v.x);
-                    en[ch] = fma(x, x, en[ch]);
+                    inside = fma(x, x, inside);
                 }
-            }
-#pragma unroll
-            for (int ch = 0; ch < 2; ++ch) {
-                for (int o = 32; o > 0; o >>= 1) en[ch] += __shfl_xor(en[ch], o);
-                if (lane == 0) s_sum[ch][wave] = en[ch];
+                for (int o = 32; o > 0; o >>= 1) inside += __shfl_xor(inside, o);
+                if (lane == 0) s_in[wave] = inside;
             }
             __syncthreads();
             if (threadIdx.x < np) {
                 const int ch = threadIdx.x;
-                double rest = 0.0;
-                for (int ww = 0; ww < NW; ++ww) rest += s_sum[ch][ww];
+                double total = 0.0, inside = 0.0;
+                for (int ww = 0; ww < NW; ++ww) total += s_sum[ch][ww];
+                for (int ww = ch * (NW / 2); ww < (ch + 1) * (NW / 2); ++ww) inside += s_in[ww];
+                // FP64 sums of FP32 squares: the difference keeps ~1e-16 of the total
+                const double rest = total - inside;
                 const double num = (double)pv[ch] * (double)pv[ch] * (double)(NV - nb_side * nb_side);
                 const int i = pi[ch], j = pj[ch];
                 const int64_t pidx = (int64_t)i * n - (int64_t)i * (i + 1) / 2 + (j - i - 1);
