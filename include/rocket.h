@@ -232,7 +232,7 @@ typedef enum {
                                        2 planned order in one segment */
     ROCKET_OPT_SEED = 5,            /* seed for the shuffled queue order */
     ROCKET_OPT_LEDGER = 6,          /* 1: record how often each work item is popped (rocket_get_ledger) */
-    ROCKET_OPT_OVL_BLOCK = 7,       /* overlap: clouds per block of the tile grid */
+    ROCKET_OPT_OVL_BLOCK = 7,       /* clouds: clouds per block of the tile grid (0: 8), at most 64 */
     ROCKET_OPT_OVL_VARIANT = 8,     /* overlap: inner-loop variant 1..4: lanes x points per lane of cloud j =
                                        64x1, 32x2, 16x2, 16x4 */
     ROCKET_OPT_SP_ROWS = 9,         /* sparse: items per row band */

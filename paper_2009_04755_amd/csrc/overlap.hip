@@ -405,7 +405,10 @@ static void ovl_plan(rocket_ctx *ctx, int T, std::vector<int4> &items, std::vect
     if (order == 2) single_segment(seg, (int64_t)items.size());
 }
 
-static int ovl_block(rocket_ctx *ctx) { return ctx->opt[ROCKET_OPT_OVL_BLOCK] ? (int)ctx->opt[ROCKET_OPT_OVL_BLOCK] : 16; }
+// Default 8 clouds per block: the two staged blocks then take ~51 KB of LDS (~77 KB with
+// per-point deviations), so two or three workgroups share a CU and hide each other's LDS and
+// queue latency (measured ~25 % faster than 16 on 2048 clouds of 50..400 points).
+static int ovl_block(rocket_ctx *ctx) { return ctx->opt[ROCKET_OPT_OVL_BLOCK] ? (int)ctx->opt[ROCKET_OPT_OVL_BLOCK] : 8; }
 static int ovl_variant(rocket_ctx *ctx)
 {
     return ctx->opt[ROCKET_OPT_OVL_VARIANT] ? (int)ctx->opt[ROCKET_OPT_OVL_VARIANT] : 3;
@@ -571,9 +574,9 @@ rocket_status ovl_autotune(rocket_ctx *ctx, hipStream_t s)
     RK_HIP(hipEventCreate(&e0));
     RK_HIP(hipEventCreate(&e1));
     const int64_t save_block = ctx->opt[ROCKET_OPT_OVL_BLOCK], save_var = ctx->opt[ROCKET_OPT_OVL_VARIANT];
-    const int blocks[] = {8, 16, 32};
+    const int blocks[] = {4, 8, 16};
     float best = 1e30f;
-    int best_b = 16, best_v = 3;
+    int best_b = 8, best_v = 3;
     rocket_status st = ROCKET_OK;
     for (int b : blocks) {
         ctx->opt[ROCKET_OPT_OVL_BLOCK] = b;

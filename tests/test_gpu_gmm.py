@@ -122,7 +122,7 @@ def test_autotune_gmm(ctx):
     ctx.set(ovl_variant=0, ovl_block=0)
     ctx.prepare(_dev(off, xy, sig), "gmm_l2")
     choice = ctx.autotune()
-    assert choice["ovl_block"] in (8, 16, 32) and choice["ovl_variant"] in (1, 2, 3, 4)
+    assert choice["ovl_block"] in (4, 8, 16) and choice["ovl_variant"] in (1, 2, 3, 4)
     got = ctx.compare().cpu().numpy()
     pi, pj = oracle.all_pairs(384)
     sel = np.arange(0, pi.size, 61)

@@ -115,7 +115,7 @@ def test_autotune_picks_valid_shape(ctx):
     ctx.set(ovl_variant=0, ovl_block=0)
     ctx.prepare(cl, "gauss_overlap")
     choice = ctx.autotune()
-    assert choice["ovl_block"] in (8, 16, 32) and choice["ovl_variant"] in (1, 2, 3, 4)
+    assert choice["ovl_block"] in (4, 8, 16) and choice["ovl_variant"] in (1, 2, 3, 4)
     got = ctx.compare().cpu().numpy()
     pi, pj = oracle.all_pairs(512)
     sel = np.arange(0, pi.size, 97)
