@@ -5,12 +5,15 @@
 // one entry per K-string that occurs, keyed by its base-20 code, keys ascending.
 //
 // Species are processed in groups.  Per species the counts of K-, (K-1)- and (K-2)-strings
-// are dense arrays over the code space (20^K u32; 256 MB at K = 6) filled with atomics,
-// one thread per window start; a K-string's first occurrence also bumps the occupancy
-// count of its 1024-code chunk.  A scan of the chunk counts gives every chunk its output
-// base; an emit pass streams the dense K array chunk by chunk, ranks the non-zero codes
-// with a workgroup prefix sum (so keys come out ascending), writes key and a(s) (FP64,
-// rounded once to f32) and writes zeros back, so the K array is clean for the next group.
+// are dense arrays over the code space (20^K u32; 256 MB at K = 6).  The K array is filled
+// with atomics, one thread per window start, and a K-string's first occurrence also bumps
+// the occupancy count of its 1024-code chunk; the shorter arrays get atomics only for the
+// windows at a protein end and are then folded from the longer ones (a (K-1)-string's count
+// is the sum over the 20 K-strings that extend it, plus its protein-end windows).  A scan
+// of the chunk counts gives every chunk its output base; an emit pass streams the dense K
+// array chunk by chunk (one wave per chunk), ranks the non-zero codes with a wave prefix
+// sum (so keys come out ascending), writes key and a(s) (FP64, rounded once to f32) and
+// writes zeros back, so the K array is clean for the next group.
 #include <algorithm>
 #include <vector>
 
@@ -65,19 +68,24 @@ __global__ __launch_bounds__(256) void k_cv_count(const uint8_t *__restrict__ re
     uint32_t *chy = chunk_cnt + y * nchunks;
     unsigned nk = 0, n1 = 0, n2 = 0;
     for (int64_t p = b + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < e; p += (int64_t)gridDim.x * blockDim.x) {
+        // Only K-windows are counted here; a shorter window that extends to a valid longer
+        // one is counted when the (K-1)- and (K-2)-string arrays are folded from the longer
+        // counts, so only windows at a protein end need their own atomic.
         const int64_t w2 = window_code(res, p, e, K - 2);
         if (w2 < 0) continue;  // a shorter window is a prefix of the longer ones
-        atomicAdd(c2y + w2, 1u);
         ++n2;
-        if (p + K - 1 > e) continue;
-        const int r1 = res[p + K - 2];
-        if (r1 >= CV_ALPHA) continue;
+        const int r1 = p + K - 1 <= e ? res[p + K - 2] : CV_ALPHA;
+        if (r1 >= CV_ALPHA) {
+            atomicAdd(c2y + w2, 1u);
+            continue;
+        }
         const int64_t w1 = w2 * CV_ALPHA + r1;
-        atomicAdd(c1y + w1, 1u);
         ++n1;
-        if (p + K > e) continue;
-        const int rK = res[p + K - 1];
-        if (rK >= CV_ALPHA) continue;
+        const int rK = p + K <= e ? res[p + K - 1] : CV_ALPHA;
+        if (rK >= CV_ALPHA) {
+            atomicAdd(c1y + w1, 1u);
+            continue;
+        }
         const int64_t wK = w1 * CV_ALPHA + rK;
         if (atomicAdd(cKy + wK, 1u) == 0u) atomicAdd(chy + (wK >> CV_CHLOG), 1u);
         ++nk;
@@ -92,6 +100,26 @@ __global__ __launch_bounds__(256) void k_cv_count(const uint8_t *__restrict__ re
         atomicAdd(tot + 3 * y, (unsigned long long)nk);
         atomicAdd(tot + 3 * y + 1, (unsigned long long)n1);
         atomicAdd(tot + 3 * y + 2, (unsigned long long)n2);
+    }
+}
+
+// c_short[w] += sum_a c_long[20 w + a]: every window of the longer length starts with a
+// valid window of the shorter one.  grid (x, group size), one thread per shorter string.
+__global__ __launch_bounds__(256) void k_cv_fold(const uint32_t *__restrict__ c_long, uint32_t *__restrict__ c_short,
+                                                 int64_t n_short)
+{
+    const int y = blockIdx.y;
+    const uint32_t *cl = c_long + y * n_short * CV_ALPHA;
+    uint32_t *cs = c_short + y * n_short;
+    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < n_short; w += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t *q = cl + w * CV_ALPHA;  // 80 bytes, 16-byte aligned
+        uint32_t t = 0;
+#pragma unroll
+        for (int a = 0; a < CV_ALPHA; a += 4) {
+            const uint4 v = *(const uint4 *)(q + a);
+            t += v.x + v.y + v.z + v.w;
+        }
+        cs[w] += t;
     }
 }
 
@@ -135,7 +163,8 @@ __global__ void k_cv_base(const int64_t *__restrict__ nnz, int G, int64_t s0, in
     }
 }
 
-// grid (chunks, group size), 256 threads x 4 codes = one 1024-code chunk per workgroup.
+// grid (chunks / 4, group size), 256 threads: one wave per 1024-code chunk, 16 codes per lane
+// (four 16-byte loads); a wave prefix sum ranks the non-zero codes, so no workgroup barrier.
 __global__ __launch_bounds__(256) void k_cv_emit(uint32_t *__restrict__ cK, const uint32_t *__restrict__ c1,
                                                  const uint32_t *__restrict__ c2,
                                                  const uint32_t *__restrict__ chunk_base, int64_t nchunks,
@@ -144,46 +173,47 @@ __global__ __launch_bounds__(256) void k_cv_emit(uint32_t *__restrict__ cK, cons
                                                  int64_t *__restrict__ keys, float *__restrict__ vals,
                                                  int64_t capacity, int *__restrict__ overflow)
 {
-    __shared__ int wsum[4];
     const int y = blockIdx.y;
+    const int64_t chunk = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (chunk >= nchunks) return;
+    const int lane = threadIdx.x & 63;
     const int64_t szK = ipow20(K), sz1 = szK / CV_ALPHA, sz2 = sz1 / CV_ALPHA;
     uint32_t *cKy = cK + y * szK;
     const uint32_t *c1y = c1 + y * sz1, *c2y = c2 + y * sz2;
-    const int64_t code0 = ((int64_t)blockIdx.x << CV_CHLOG) + 4 * threadIdx.x;
-    uint32_t v[4] = {0u, 0u, 0u, 0u};
-    if (code0 + 3 < szK) {
-        const uint4 q = *(const uint4 *)(cKy + code0);
-        v[0] = q.x;
-        v[1] = q.y;
-        v[2] = q.z;
-        v[3] = q.w;
+    const int64_t code0 = (chunk << CV_CHLOG) + 16 * lane;
+    uint32_t v[16];
+    if (code0 + 15 < szK) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint4 u = *(const uint4 *)(cKy + code0 + 4 * q);
+            v[4 * q] = u.x;
+            v[4 * q + 1] = u.y;
+            v[4 * q + 2] = u.z;
+            v[4 * q + 3] = u.w;
+        }
     } else {
-        for (int t = 0; t < 4; ++t)
-            if (code0 + t < szK) v[t] = cKy[code0 + t];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) v[t] = code0 + t < szK ? cKy[code0 + t] : 0u;
     }
-    const int mine = (v[0] != 0) + (v[1] != 0) + (v[2] != 0) + (v[3] != 0);
-    // exclusive prefix of `mine` over the workgroup: wave scan, then wave totals
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int mine = 0;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) mine += v[t] != 0u;
     int incl = mine;
     for (int o = 1; o < 64; o <<= 1) {
         const int t = __shfl_up(incl, o);
         if (lane >= o) incl += t;
     }
-    if (lane == 63) wsum[wave] = incl;
-    __syncthreads();
-    int before = incl - mine;
-    for (int w = 0; w < wave; ++w) before += wsum[w];
     if (mine == 0) return;
     const double NK = (double)tot[3 * y], N1 = (double)tot[3 * y + 1], N2 = (double)tot[3 * y + 2];
-    int64_t pos = cv_off[s0 + y] + chunk_base[y * nchunks + blockIdx.x] + before;
-    const int64_t m1 = sz1, m2 = sz2;
-    for (int t = 0; t < 4; ++t) {
+    int64_t pos = cv_off[s0 + y] + chunk_base[y * nchunks + chunk] + (incl - mine);
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
         if (v[t] == 0u) continue;
         const int64_t code = code0 + t;
         if (pos >= capacity) {
             *overflow = 1;
         } else {
-            const int64_t pre = code / CV_ALPHA, suf = code % m1, mid = pre % m2;
+            const int64_t pre = code / CV_ALPHA, suf = code % sz1, mid = pre % sz2;
             const double f = (double)v[t] / NK;
             const double f0 = ((double)c1y[pre] / N1) * ((double)c1y[suf] / N1) / ((double)c2y[mid] / N2);
             keys[pos] = code;
@@ -258,9 +288,13 @@ rocket_status cv_build(rocket_ctx *ctx, const uint8_t *res, const int64_t *offse
             hipLaunchKernelGGL(k_cv_count, dim3(bx, g), dim3(256), 0, s, res, offsets, s0, K, (uint32_t *)pK,
                                (uint32_t *)p1, (uint32_t *)p2, (uint32_t *)pch, nchunks, (unsigned long long *)ptot);
         }
+        hipLaunchKernelGGL(k_cv_fold, dim3((unsigned)std::min<int64_t>(4096, (sz1 + 255) / 256), g), dim3(256), 0, s,
+                           (const uint32_t *)pK, (uint32_t *)p1, sz1);
+        hipLaunchKernelGGL(k_cv_fold, dim3((unsigned)std::min<int64_t>(4096, (sz2 + 255) / 256), g), dim3(256), 0, s,
+                           (const uint32_t *)p1, (uint32_t *)p2, sz2);
         hipLaunchKernelGGL(k_cv_scan, dim3(g), dim3(1024), 0, s, (uint32_t *)pch, nchunks, (int64_t *)pnnz);
         hipLaunchKernelGGL(k_cv_base, dim3(1), dim3(64), 0, s, (const int64_t *)pnnz, g, s0, cv_off);
-        hipLaunchKernelGGL(k_cv_emit, dim3((unsigned)nchunks, g), dim3(256), 0, s, (uint32_t *)pK,
+        hipLaunchKernelGGL(k_cv_emit, dim3((unsigned)((nchunks + 3) / 4), g), dim3(256), 0, s, (uint32_t *)pK,
                            (const uint32_t *)p1, (const uint32_t *)p2, (const uint32_t *)pch, nchunks,
                            (const unsigned long long *)ptot, (const int64_t *)cv_off, s0, K, keys, vals, capacity,
                            (int *)pflag);
