@@ -99,7 +99,11 @@ __device__ void fft2d(float2 *a, const float2 *tw)
         // rows: vector v at v*RS, element stride 1; columns: vector v at v, stride RS
         const int vstride = dim == 0 ? RS : 1, estride = dim == 0 ? 1 : RS;
         // step A: for every (v, n2): N1-point DFT over n1 of x[N2 n1 + n2], twiddle W_L^(n2 k1)
-        for (int id = threadIdx.x; id < L * N2; id += NT) {
+        // tasks of a thread are unrolled so the LDS reads of all of them are in flight together
+#pragma unroll
+        for (int it = 0; it < (L * N2 + NT - 1) / NT; ++it) {
+            const int id = it * NT + threadIdx.x;
+            if (id >= L * N2) break;
             const int v = id % L, n2 = id / L;
             float2 *p = a + v * vstride + n2 * estride;
             float2 x[N1];
@@ -111,7 +115,10 @@ __device__ void fft2d(float2 *a, const float2 *tw)
         }
         __syncthreads();
         // step B: for every (v, k1): N2-point DFT over n2 of y[N2 k1 + n2], written back in place
-        for (int id = threadIdx.x; id < L * N1; id += NT) {
+#pragma unroll
+        for (int it = 0; it < (L * N1 + NT - 1) / NT; ++it) {
+            const int id = it * NT + threadIdx.x;
+            if (id >= L * N1) break;
             const int v = id % L, k1 = id / L;
             float2 *p = a + v * vstride + k1 * N2 * estride;
             float2 x[N2];
