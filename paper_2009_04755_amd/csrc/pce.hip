@@ -7,7 +7,8 @@
 //
 // Prepare (l's GPU stage): one workgroup per item removes the mean and scales to unit norm
 // (FP64; PCE does not depend on either) and transforms the item with a 2-D FFT in LDS;
-// spectra F are stored in natural order, complex f32.
+// spectra F are stored in natural order, complex f32, columns 0 .. L/2 only (the rest is
+// the conjugate mirror).
 // Compare: a persistent kernel pulls tiles of T x T item pairs from the work queue (the
 // spectra of a tile's 2T items stay in L2); per two pairs one workgroup forms
 // conj(F_a) F_b + i conj(F_c) F_d in LDS and transforms it forward: the real part is L^2 times
@@ -188,9 +189,11 @@ __global__ __launch_bounds__(PCE_THREADS) void k_pce_prepare(const float *__rest
         a[(i / L) * RS + i % L] = make_float2((float)(((double)x[i] - mean) * inv), 0.f);
     __syncthreads();
     fft2d<L, N1, N2, PCE_THREADS>(a, tw);
-    float2 *f = F + (int64_t)blockIdx.x * L * L;
-    for (int i = threadIdx.x; i < L * L; i += PCE_THREADS)
-        f[i] = a[pos_of<N1, N2>(i / L) * RS + pos_of<N1, N2>(i % L)];
+    // real input: F(-k) = conj F(k), so only columns kc = 0 .. L/2 are stored
+    constexpr int LH = L / 2 + 1;
+    float2 *f = F + (int64_t)blockIdx.x * L * LH;
+    for (int i = threadIdx.x; i < L * LH; i += PCE_THREADS)
+        f[i] = a[pos_of<N1, N2>(i / LH) * RS + pos_of<N1, N2>(i % LH)];
 }
 
 // Compare: persistent; work item = tile (bi, bj) of PCE_T-item blocks, bi <= bj.  The
@@ -238,33 +241,39 @@ __global__ __launch_bounds__(PCE_CMP_THREADS, 1) void k_pce(const float2 *__rest
             if (next_pair(pi[0], pj[0])) ++np;
             if (np == 1 && next_pair(pi[1], pj[1])) ++np;
             if (np == 0) break;
-            const float2 *fa0 = F + (int64_t)pi[0] * NV, *fb0 = F + (int64_t)pj[0] * NV;
-            const float2 *fa1 = F + (int64_t)pi[np - 1] * NV, *fb1 = F + (int64_t)pj[np - 1] * NV;
+            constexpr int LH = L / 2 + 1, NH = L * LH;  // stored half spectrum per item
+            const float2 *fa0 = F + (int64_t)pi[0] * NH, *fb0 = F + (int64_t)pj[0] * NH;
+            const float2 *fa1 = F + (int64_t)pi[np - 1] * NH, *fb1 = F + (int64_t)pj[np - 1] * NH;
             const bool two = np == 2;
             // conj(Z) = conj(F_a) F_b for each pair; the second is packed as the imaginary part.
-            // The spectra come from L2/HBM: LB elements per thread are loaded before any is
-            // used, so LB x 4 loads per thread are in flight at once.
-            constexpr int PER = NV / NT, LB = PER < 8 ? PER : 8;
-            static_assert(PER % LB == 0, "load batches");
+            // Both are Hermitian (real items), so the half spectrum gives every column: column
+            // L - kc of row L - kr holds conj of column kc of row kr for each pair.  The spectra
+            // come from L2/HBM: LB elements per thread are loaded before any is used.
+            constexpr int LB = 8;
 #pragma unroll 1
-            for (int e0 = 0; e0 < PER; e0 += LB) {
+            for (int e0 = 0; e0 < NH; e0 += LB * NT) {
                 float2 u[LB], v[LB], u2[LB], v2[LB];
 #pragma unroll
                 for (int b = 0; b < LB; ++b) {
-                    const int e = (e0 + b) * NT + threadIdx.x;
-                    u[b] = fa0[e];
-                    v[b] = fb0[e];
-                    u2[b] = two ? fa1[e] : make_float2(0.f, 0.f);
-                    v2[b] = two ? fb1[e] : make_float2(0.f, 0.f);
+                    const int e = e0 + b * NT + threadIdx.x;
+                    const bool ok = e < NH;
+                    u[b] = ok ? fa0[e] : make_float2(0.f, 0.f);
+                    v[b] = ok ? fb0[e] : make_float2(0.f, 0.f);
+                    u2[b] = ok && two ? fa1[e] : make_float2(0.f, 0.f);
+                    v2[b] = ok && two ? fb1[e] : make_float2(0.f, 0.f);
                 }
 #pragma unroll
                 for (int b = 0; b < LB; ++b) {
-                    const int e = (e0 + b) * NT + threadIdx.x;
+                    const int e = e0 + b * NT + threadIdx.x;
+                    if (e >= NH) break;
+                    const int kr = e / LH, kc = e % LH;
                     const float2 z = make_float2(fmaf(u[b].x, v[b].x, u[b].y * v[b].y),
                                                  fmaf(u[b].x, v[b].y, -(u[b].y * v[b].x)));
                     const float2 z2 = make_float2(fmaf(u2[b].x, v2[b].x, u2[b].y * v2[b].y),
                                                   fmaf(u2[b].x, v2[b].y, -(u2[b].y * v2[b].x)));
-                    a[(e / L) * RS + e % L] = make_float2(z.x - z2.y, z.y + z2.x);  // z + i z2
+                    a[kr * RS + kc] = make_float2(z.x - z2.y, z.y + z2.x);  // z + i z2
+                    if (kc > 0 && kc < L / 2)  // conj(z) + i conj(z2) at the mirrored frequency
+                        a[((L - kr) % L) * RS + (L - kc)] = make_float2(z.x + z2.y, z2.x - z.y);
                 }
             }
             __syncthreads();
@@ -401,7 +410,7 @@ rocket_status pce_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, hi
     p.n = n;
     p.L = L;
     void *spec = nullptr;
-    const size_t spec_bytes = (size_t)std::max<int64_t>(n, 1) * L * L * sizeof(float2);
+    const size_t spec_bytes = (size_t)std::max<int64_t>(n, 1) * L * (L / 2 + 1) * sizeof(float2);
     RK_TRY(ws_get(ctx, WS_PCE_SPEC, spec_bytes + sizeof(int) * (size_t)std::max<int64_t>(n, 1), &spec));
     int *live = (int *)((char *)spec + spec_bytes);  // per item: non-zero variance
     if (n > 0) {
@@ -457,7 +466,7 @@ rocket_status pce_compare(rocket_ctx *ctx, float *out, uint32_t *peak, hipStream
     ctx->stats.grid = grid;
     RK_TRY(reset_queue(ctx, s, p.qa));
     const float2 *F = (const float2 *)ctx->ws[WS_PCE_SPEC].ptr;
-    const int *live = (const int *)((const char *)F + (size_t)p.n * L * L * sizeof(float2));
+    const int *live = (const int *)((const char *)F + (size_t)p.n * L * (L / 2 + 1) * sizeof(float2));
     RK_TRY(timing_begin(ctx, s));
     if (L == 32)
         hipLaunchKernelGGL((k_pce<32, 8, 4>), dim3(grid), dim3(PCE_CMP_THREADS), lds, s, F, live, (int)p.n, h, p.qa, out,
