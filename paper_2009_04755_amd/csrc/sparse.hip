@@ -135,8 +135,8 @@ __global__ __launch_bounds__(SP_THREADS, 1) void k_sparse(const uint32_t *__rest
                                                          const int *__restrict__ bounds, QueueArgs q,
                                                          float *__restrict__ out, uint32_t *__restrict__ counts)
 {
-    __shared__ uint32_t hkey[HSIZE];
-    __shared__ uint16_t hidx[HSIZE];
+    // hash slot = key (low 32 bits) | union index (high 32 bits): one 8-byte read per probe
+    __shared__ uint64_t htab[HSIZE];
     __shared__ __align__(16) float uval[UMAX * RB];       // row values per union entry
     __shared__ __align__(16) uint32_t upres[UMAX * RB / 4];  // presence bytes per union entry
     __shared__ int s_item, s_ucount;
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(SP_THREADS, 1) void k_sparse(const uint32_t *__rest
         for (int ch = 0; ch < nch; ++ch) {
             const uint64_t K1 = (uint64_t)bnd[ch + 1] << wlog;
             // 1. clear the table
-            for (int k = tid; k < HSIZE; k += SP_THREADS) hkey[k] = EMPTY;
+            for (int k = tid; k < HSIZE; k += SP_THREADS) htab[k] = ~0ull;
             for (int k = tid; k < prev_u * RB / 4; k += SP_THREADS) {
                 upres[k] = 0u;
                 *(float4 *)&uval[4 * k] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -205,12 +205,13 @@ __global__ __launch_bounds__(SP_THREADS, 1) void k_sparse(const uint32_t *__rest
                         const uint32_t key = kk[r];
                         uint32_t h = hslot(key);
                         while (true) {
-                            const uint32_t old = atomicCAS(&hkey[h], EMPTY, key);
-                            if (old == EMPTY) {
-                                hidx[h] = (uint16_t)atomicAdd(&s_ucount, 1);
+                            const unsigned long long old =
+                                atomicCAS((unsigned long long *)&htab[h], ~0ull, (unsigned long long)key | (~0ull << 32));
+                            if (old == ~0ull) {  // claimed: the union index goes in the high half
+                                ((uint32_t *)&htab[h])[1] = (uint32_t)atomicAdd(&s_ucount, 1);
                                 break;
                             }
-                            if (old == key) break;
+                            if ((uint32_t)old == key) break;
                             h = (h + 1) & (HSIZE - 1);
                         }
                     }
@@ -238,8 +239,9 @@ __global__ __launch_bounds__(SP_THREADS, 1) void k_sparse(const uint32_t *__rest
                     if (in) {
                         const uint32_t key = kk[r];
                         uint32_t h = hslot(key);
-                        while (hkey[h] != key) h = (h + 1) & (HSIZE - 1);
-                        const int u = hidx[h];
+                        uint64_t t;
+                        while ((uint32_t)(t = htab[h]) != key) h = (h + 1) & (HSIZE - 1);
+                        const int u = (int)(t >> 32);
                         uval[u * RB + ((((wave >> 2) + u) & 3) << 2) + (wave & 3)] = vv[r];
                         atomicOr(&upres[u * (RB / 4) + (wave >> 2)], 1u << (8 * (wave & 3)));
                     }
@@ -276,10 +278,10 @@ __global__ __launch_bounds__(SP_THREADS, 1) void k_sparse(const uint32_t *__rest
                         const uint32_t key = kk[r];
                         const float vj = vv[r];
                         uint32_t h = hslot(key);
-                        uint32_t hk;
-                        while ((hk = hkey[h]) != key && hk != EMPTY) h = (h + 1) & (HSIZE - 1);
-                        if (hk == key) {
-                            const int u = hidx[h];
+                        uint64_t t;
+                        while ((uint32_t)(t = htab[h]) != key && (uint32_t)t != EMPTY) h = (h + 1) & (HSIZE - 1);
+                        if ((uint32_t)t == key) {
+                            const int u = (int)(t >> 32);
                             const float4 *uv = (const float4 *)&uval[u * RB];
 #pragma unroll
                             for (int qd = 0; qd < RB / 4; ++qd) {
