@@ -119,53 +119,71 @@ __global__ __launch_bounds__(256) void k_ncc_stats(const float *__restrict__ X, 
 }
 
 // ------------------------------------------------------------------------------------------
-// Centre and split.  Thread = (row r, four consecutive K slices): reads 64 contiguous values
-// of row r (256 bytes), writes for each slice kt 16 outputs per plane at ((kt * T + r % T) *
-// 16) of block r / T, so consecutive threads write consecutive 32-byte (bf16) or 64-byte
-// (fp32) runs.  grid.x = groups of four K slices, grid.y = groups of 256 rows.  Rows >= n
-// (up to rows_pad) and columns >= d become zeros.
+// Centre and split.  Workgroup = tile of 16 rows x 256 values (16 K slices).  Each wave reads
+// 4 rows of the tile with 1 KiB coalesced loads (lane = four consecutive values), centres
+// them in FP64 and stores them to LDS; then thread (row, slice) reads its 16 values back
+// (padded rows: conflict-free 16-byte reads), splits them and writes 32-byte pieces per
+// plane, consecutive threads writing consecutive rows of one slice.  Rows >= n (up to
+// rows_pad) and values >= d become zeros.  grid = (ceil(nkt / 16), rows_pad / 16).
 // ------------------------------------------------------------------------------------------
 template <int SCH>
 __global__ __launch_bounds__(256) void k_ncc_split(const float *__restrict__ X, int64_t ld, int64_t d, int64_t n,
                                                    const double *__restrict__ mu, int64_t rows_pad, int64_t nkt,
                                                    int64_t T, char *__restrict__ planes)
 {
-    const int64_t r = (int64_t)blockIdx.y * 256 + threadIdx.x;
+    // 16 rows x 256 values: 16.6 KB of LDS, so up to eight workgroups (32 waves) share a CU
+    constexpr int TR = 16, TK = 256, LS = TK + 4;  // LDS row stride 1040 bytes
+    constexpr int SPT = (TK / 16) * TR / 256;       // slices per thread in the write phase
+    __shared__ __align__(16) float tile[TR * LS];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t r0 = (int64_t)blockIdx.y * TR, k0 = (int64_t)blockIdx.x * TK;
+    const bool vec = ((ld & 3) == 0) && ((((uintptr_t)X) & 15) == 0);
+    for (int i = 0; i < TR / 4; ++i) {
+        const int row = wave * (TR / 4) + i;
+        const int64_t r = r0 + row, k = k0 + 4 * lane;
+        float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (r < n) {
+            const double m = mu[r];
+            const float *a = X + r * ld + k;
+            if (vec && k + 4 <= d) {
+                const float4 v = *(const float4 *)a;
+                c = make_float4((float)((double)v.x - m), (float)((double)v.y - m), (float)((double)v.z - m),
+                                (float)((double)v.w - m));
+            } else {
+                if (k < d) c.x = (float)((double)a[0] - m);
+                if (k + 1 < d) c.y = (float)((double)a[1] - m);
+                if (k + 2 < d) c.z = (float)((double)a[2] - m);
+                if (k + 3 < d) c.w = (float)((double)a[3] - m);
+            }
+        }
+        *(float4 *)&tile[row * LS + 4 * lane] = c;
+    }
+    __syncthreads();
+    const int row = threadIdx.x % TR, sg = threadIdx.x / TR;  // slices sg*SPT .. sg*SPT + SPT - 1
+    static_assert(SPT >= 1 && (TK / 16) % SPT == 0, "whole slices per thread");
+    const int64_t r = r0 + row;
     if (r >= rows_pad) return;
     const int64_t blk = r / T, rr = r - blk * T;
     constexpr int NC = Scheme<SCH>::NC;
     const int64_t plane_bytes = T * 16 * Scheme<SCH>::ES;  // one component of one K slice of a block
-    planes += blk * nkt * NC * plane_bytes;
-    const bool vec = ((ld & 3) == 0) && ((((uintptr_t)X) & 15) == 0);
-    const double m = r < n ? mu[r] : 0.0;
+    char *pb = planes + blk * nkt * NC * plane_bytes;
 #pragma unroll
-    for (int sl = 0; sl < 4; ++sl) {
-        const int64_t kt = (int64_t)blockIdx.x * 4 + sl;
+    for (int sl = 0; sl < SPT; ++sl) {
+        const int ktl = sg * SPT + sl;
+        const int64_t kt = (int64_t)blockIdx.x * (TK / 16) + ktl;
         if (kt >= nkt) break;
-        const int64_t k0 = kt * 16;
         float x[16];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) x[e] = 0.f;
-        if (r < n) {
-            const float *a = X + r * ld + k0;
-            if (vec && k0 + 16 <= d) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const float4 v = ((const float4 *)a)[q];
-                    x[4 * q] = (float)((double)v.x - m);
-                    x[4 * q + 1] = (float)((double)v.y - m);
-                    x[4 * q + 2] = (float)((double)v.z - m);
-                    x[4 * q + 3] = (float)((double)v.w - m);
-                }
-            } else {
-#pragma unroll
-                for (int e = 0; e < 16; ++e)
-                    if (k0 + e < d) x[e] = (float)((double)a[e] - m);
-            }
+        for (int q = 0; q < 4; ++q) {
+            const float4 v = *(const float4 *)&tile[row * LS + ktl * 16 + 4 * q];
+            x[4 * q] = v.x;
+            x[4 * q + 1] = v.y;
+            x[4 * q + 2] = v.z;
+            x[4 * q + 3] = v.w;
         }
         const int64_t dst = (kt * NC * T + rr) * 16;
         if constexpr (SCH == SCH_FP32) {
-            float4 *p = (float4 *)((float *)planes + dst);
+            float4 *p = (float4 *)((float *)pb + dst);
 #pragma unroll
             for (int q = 0; q < 4; ++q) p[q] = make_float4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
         } else {
@@ -185,14 +203,14 @@ __global__ __launch_bounds__(256) void k_ncc_split(const float *__restrict__ X, 
                 mw[e / 2] = m2[0] | (m2[1] << 16);
                 lw[e / 2] = l2[0] | (l2[1] << 16);
             }
-            uint4 *p0 = (uint4 *)((uint16_t *)planes + dst);
+            uint4 *p0 = (uint4 *)((uint16_t *)pb + dst);
             p0[0] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
             p0[1] = make_uint4(hw[4], hw[5], hw[6], hw[7]);
-            uint4 *p1 = (uint4 *)((uint16_t *)(planes + plane_bytes) + dst);
+            uint4 *p1 = (uint4 *)((uint16_t *)(pb + plane_bytes) + dst);
             p1[0] = make_uint4(mw[0], mw[1], mw[2], mw[3]);
             p1[1] = make_uint4(mw[4], mw[5], mw[6], mw[7]);
             if constexpr (SCH == SCH_X6) {
-                uint4 *p2 = (uint4 *)((uint16_t *)(planes + 2 * plane_bytes) + dst);
+                uint4 *p2 = (uint4 *)((uint16_t *)(pb + 2 * plane_bytes) + dst);
                 p2[0] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
                 p2[1] = make_uint4(lw[4], lw[5], lw[6], lw[7]);
             }
@@ -676,7 +694,7 @@ rocket_status ncc_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, in
     float *inv_s = (float *)((char *)stats + (((size_t)n * 8 + 255) & ~(size_t)255));
     hipLaunchKernelGGL(k_ncc_stats, dim3((unsigned)n), dim3(256), 0, s, it->dense, it->ld, it->dim, mu, inv_s);
     RK_HIP(hipGetLastError());
-    const dim3 g((unsigned)((st.nkt + 3) / 4), (unsigned)((st.n_pad + 255) / 256));
+    const dim3 g((unsigned)((st.nkt + 15) / 16), (unsigned)((st.n_pad + 15) / 16));
     if (scheme == SCH_FP32)
         hipLaunchKernelGGL(k_ncc_split<SCH_FP32>, g, dim3(256), 0, s, it->dense, it->ld, it->dim, n, mu, st.n_pad,
                            (int64_t)st.nkt, (int64_t)bm, (char *)planes);
@@ -936,7 +954,7 @@ rocket_status ncc_allpairs_host(rocket_ctx *ctx, const float *host, int64_t n, i
     }
     double *mu = (double *)stats;
     float *inv_s = (float *)((char *)stats + (((size_t)n * 8 + 255) & ~(size_t)255));
-    const dim3 sg((unsigned)((st.nkt + 3) / 4), (unsigned)((T + 255) / 256));
+    const dim3 sg((unsigned)((st.nkt + 15) / 16), (unsigned)((T + 15) / 16));
 
     // --- enqueue -------------------------------------------------------------------------
     RK_HIP(hipEventRecord(oc.start, s));  // staging buffers are free once earlier work on s is done
