@@ -87,35 +87,51 @@ __global__ __launch_bounds__(256) void k_sp_hist(const uint32_t *__restrict__ k3
     for (int64_t p = off[i] + threadIdx.x; p < off[i + 1]; p += 256) atomicAdd(h + (k32[p] >> wlog), 1u);
 }
 
-// Greedy cut of each band's micro-chunks into chunks of at most UMAX entries.  Pass 0 counts
-// chunks per band, pass 1 writes their starting micro-chunk.  One workgroup per band; the
-// counts are staged through LDS and scanned by one thread.
+// Greedy cut of each band's micro-chunks into chunks of at most UMAX entries: a chunk is
+// closed before the micro-chunk that would overflow it.  Pass 0 counts chunks per band,
+// pass 1 writes their starting micro-chunk.  One workgroup per band stages the counts in
+// LDS; one wave runs the greedy scan 64 counts at a time: a prefix sum over the lanes finds
+// the next overflowing lane with one ballot, so a window costs one step plus one per cut.
 __global__ __launch_bounds__(256) void k_sp_cut(const unsigned *__restrict__ hist, int64_t nmc, int pass,
                                                 int *__restrict__ nchunks, const int64_t *__restrict__ cstart,
                                                 int *__restrict__ bounds, unsigned *__restrict__ flags)
 {
     const int band = blockIdx.x;
     const unsigned *h = hist + (int64_t)band * nmc;
-    __shared__ unsigned buf[1024];
-    unsigned acc = 0;
+    __shared__ unsigned buf[4096];
+    const int lane = threadIdx.x & 63;
+    unsigned acc = 0;  // fill of the open chunk (wave-uniform)
     int cnt = 0;
     int *out = pass ? bounds + cstart[band] : nullptr;
     if (pass && threadIdx.x == 0) out[0] = 0;
-    for (int64_t m0 = 0; m0 < nmc; m0 += 1024) {
+    for (int64_t m0 = 0; m0 < nmc; m0 += 4096) {
         __syncthreads();
-        for (int k = threadIdx.x; k < 1024; k += 256) buf[k] = m0 + k < nmc ? h[m0 + k] : 0u;
+        for (int k = threadIdx.x; k < 4096; k += 256) buf[k] = m0 + k < nmc ? h[m0 + k] : 0u;
         __syncthreads();
-        if (threadIdx.x == 0) {
-            const int lim = (int)min<int64_t>(1024, nmc - m0);
-            for (int k = 0; k < lim; ++k) {
-                const unsigned c = buf[k];
-                if (c > (unsigned)UMAX) atomicOr(flags, (unsigned)FLAG_OVERFLOW);
-                if (acc + c > (unsigned)UMAX && acc > 0) {
-                    ++cnt;
-                    if (pass) out[cnt] = (int)(m0 + k);
-                    acc = 0;
+        if (threadIdx.x >= 64) continue;
+        const int lim = (int)min<int64_t>(4096, nmc - m0);
+        for (int b = 0; b < lim; b += 64) {
+            const unsigned c = b + lane < lim ? buf[b + lane] : 0u;
+            if (__ballot(c > (unsigned)UMAX) && lane == 0) atomicOr(flags, (unsigned)FLAG_OVERFLOW);
+            int start = 0;
+            for (;;) {
+                const unsigned v = lane >= start ? c : 0u;
+                unsigned sum = v;  // inclusive prefix over the lanes
+                for (int o = 1; o < 64; o <<= 1) {
+                    const unsigned t = __shfl_up(sum, o);
+                    if (lane >= o) sum += t;
                 }
-                acc += c;
+                const bool cut = lane >= start && acc + sum > (unsigned)UMAX && acc + sum - v > 0u;
+                const uint64_t m = __ballot(cut);
+                if (m == 0) {
+                    acc += __shfl(sum, 63);
+                    break;
+                }
+                const int i = __ffsll((unsigned long long)m) - 1;
+                ++cnt;
+                if (pass && lane == 0) out[cnt] = (int)(m0 + b + i);
+                acc = 0;
+                start = i;
             }
         }
     }
