@@ -235,8 +235,11 @@ typedef enum {
     ROCKET_OPT_OVL_BLOCK = 7,       /* clouds: clouds per block of the tile grid (0: 8), at most 64 */
     ROCKET_OPT_OVL_VARIANT = 8,     /* overlap: inner-loop variant 1..4: lanes x points per lane of cloud j =
                                        64x1, 32x2, 16x2, 16x4 */
-    ROCKET_OPT_SP_ROWS = 9,         /* sparse: items per row band */
-    ROCKET_OPT_SP_CHUNK = 10,       /* sparse: key-range chunk width (power of two) */
+    ROCKET_OPT_SP_LANES = 9,        /* sparse: lanes per column item, 4 or 8 (0: 4 when that leaves at least 8
+                                       work items per CU, else 8); a work item covers
+                                       1024 / lanes column items */
+    ROCKET_OPT_SP_CHUNK = 10,       /* sparse: least micro-chunk width of the key-range cut, a power of two
+                                       (0: automatic, the smallest width giving at most 2^20 micro-chunks) */
     ROCKET_OPT_WORKSPACE_CAP = 11,  /* bytes; workspace growth beyond it fails with ROCKET_E_OOM */
     ROCKET_OPT_AUTOTUNE = 12,       /* 1: rocket_prepare of ragged sets runs the tile-shape autotuner */
     ROCKET_OPT_TIMING = 13,         /* 1: bracket each compare's main persistent kernel with HIP events on the

@@ -21,7 +21,7 @@ FN_BY_NAME = {"ncc_fp32": NCC_FP32, "ncc_bf16x3": NCC_BF16X3, "ncc_bf16x6": NCC_
               "gmm_bhattacharya": GMM_BHATTACHARYA, "pce": PCE}
 
 OPT = {"ncc_tile": 1, "ncc_kchunk": 2, "grid": 3, "queue_order": 4, "seed": 5, "ledger": 6, "ovl_block": 7,
-       "ovl_variant": 8, "sp_rows": 9, "sp_chunk": 10, "workspace_cap": 11, "autotune": 12, "timing": 13,
+       "ovl_variant": 8, "sp_lanes": 9, "sp_chunk": 10, "workspace_cap": 11, "autotune": 12, "timing": 13,
        "cache_slots": 14, "pce_radius": 15, "ncc_waves": 16}
 
 # every symbol include/rocket.h declares

@@ -86,7 +86,7 @@ struct SpState {
     const int64_t *offsets = nullptr;
     const int64_t *keys = nullptr;
     const float *vals = nullptr;
-    int wlog = 0;
+    int wlog = 0, lpc = 8;
     int64_t tiles = 0, nchunks_total = 0;
     std::vector<int64_t> h_offsets;
     std::vector<int> perm;

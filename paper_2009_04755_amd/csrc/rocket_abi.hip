@@ -355,6 +355,10 @@ rocket_status rocket_set_option(rocket_ctx *ctx, rocket_option opt, int64_t valu
         return rk::fail(ctx, ROCKET_E_INVALID, "NCC waves must be 0, 4 or 8");
     if (opt == ROCKET_OPT_OVL_VARIANT && value > 4) return rk::fail(ctx, ROCKET_E_INVALID, "overlap variant 0..4");
     if (opt == ROCKET_OPT_OVL_BLOCK && value > 64) return rk::fail(ctx, ROCKET_E_INVALID, "overlap block <= 64");
+    if (opt == ROCKET_OPT_SP_LANES && value != 0 && value != 4 && value != 8)
+        return rk::fail(ctx, ROCKET_E_INVALID, "sparse lanes per column must be 0, 4 or 8");
+    if (opt == ROCKET_OPT_SP_CHUNK && (value & (value - 1)) != 0)
+        return rk::fail(ctx, ROCKET_E_INVALID, "sparse chunk width must be 0 or a power of two");
     ctx->opt[opt] = value;
     return ROCKET_OK;
 }

@@ -6,14 +6,15 @@
 // Prepare validates the keys (strictly ascending per item, in [0, 2^32 - 1)), packs them to
 // u32, reduces every item's L2 norm in FP64, and sorts items by nnz (largest first) so the
 // streams processed side by side have similar lengths.  Work item = (band of RB=16 sorted
-// row items) x (block of CB=128 sorted column items).  The key space is cut, per band, into
+// row items) x (block of CB = 1024 / LPC sorted column items, LPC = 4 or 8 lanes per column).
+// The key space is cut, per band, into
 // chunks holding at most UMAX row entries (counted on a histogram of the band's keys over
 // fixed-width micro-chunks).  For every chunk the workgroup builds in LDS a hash table of the
 // band's keys whose slots carry the 16 row values (zero when absent) and 16 presence bytes;
-// then each column streams its keys of that chunk (8 lanes per column, coalesced), probes the
-// table and accumulates 16 dot products and 16 counts in registers.  Keys match by integer
-// equality, so counts are exact; chunk sums are added with compensation and the 8 lanes of a
-// column combine in a fixed butterfly, so results do not depend on scheduling.
+// then each column streams its keys of that chunk (LPC lanes per column, coalesced), probes
+// the table and accumulates 16 dot products and 16 counts in registers.  Keys match by
+// integer equality, so counts are exact; chunk sums are added with compensation and the LPC
+// lanes of a column combine in a fixed butterfly, so results do not depend on scheduling.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -25,9 +26,7 @@ namespace rk {
 namespace {
 
 constexpr int RB = 16;          // rows per band
-constexpr int LPC = 8;          // lanes per column
 constexpr int SP_THREADS = 1024;
-constexpr int CB = SP_THREADS / LPC;  // columns per block
 constexpr int UMAX = 1536;      // union capacity of one chunk (row entries)
 constexpr int SR = 4;           // column entries per lane per streaming pass
 constexpr int HBITS = 12;
@@ -144,6 +143,7 @@ __global__ __launch_bounds__(256) void k_sp_cut(const unsigned *__restrict__ his
     }
 }
 
+template <int LPC>
 __global__ __launch_bounds__(SP_THREADS, 1) void k_sparse(const uint32_t *__restrict__ k32, const float *__restrict__ vals,
                                                          const int64_t *__restrict__ off, const int *__restrict__ perm,
                                                          const float *__restrict__ inv_norm, int n, int wlog,
@@ -157,23 +157,32 @@ __global__ __launch_bounds__(SP_THREADS, 1) void k_sparse(const uint32_t *__rest
     __shared__ __align__(16) uint32_t upres[UMAX * RB / 4];  // presence bytes per union entry
     __shared__ int s_item, s_ucount;
 
+    constexpr int CB = SP_THREADS / LPC;  // columns per block
+    static_assert(LPC == 4 || LPC == 8, "4 or 8 lanes per column");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int sub = lane & (LPC - 1);        // lane within the column group
     const int col = tid / LPC;               // column within the block
-    const uint64_t gmask = 0xFFull << (lane & ~(LPC - 1));
+    const uint64_t gmask = ((1ull << LPC) - 1) << (lane & ~(LPC - 1));
 
+    // the work item and this wave's row are wave-uniform: keep them in scalar registers
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    auto uni64 = [](int64_t v) {
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+        return (int64_t)(((uint64_t)hi << 32) | lo);
+    };
     for (;;) {
-        const int it = queue_pop_wg(q, &s_item);
+        const int it = __builtin_amdgcn_readfirstlane(queue_pop_wg(q, &s_item));
         if (it < 0) break;
         const int4 w = q.items[it];
-        const int band = w.x, cblk = w.y;
+        const int band = __builtin_amdgcn_readfirstlane(w.x), cblk = __builtin_amdgcn_readfirstlane(w.y);
         const int r0 = band * RB, c0 = cblk * CB;
         // this wave stages row r0 + wave (16 waves, 16 rows)
-        const int srow = r0 + wave;
+        const int srow = r0 + wv;
         const bool row_ok = srow < n;
-        const int irow = row_ok ? perm[srow] : 0;
-        int64_t rpos = row_ok ? off[irow] : 0;
-        const int64_t rend = row_ok ? off[irow + 1] : 0;
+        const int irow = row_ok ? __builtin_amdgcn_readfirstlane(perm[srow]) : 0;
+        int64_t rpos = row_ok ? uni64(off[irow]) : 0;
+        const int64_t rend = row_ok ? uni64(off[irow + 1]) : 0;
         // this lane group's column
         const int scol = c0 + col;
         const bool col_ok = scol < n;
@@ -204,14 +213,26 @@ __global__ __launch_bounds__(SP_THREADS, 1) void k_sparse(const uint32_t *__rest
             if (tid == 0) s_ucount = 0;
             __syncthreads();
             // 2a. insert the band's keys of this chunk (SR entries per lane per pass, all
-            // loads of a pass independent)
+            // loads of a pass independent).  The first pass also loads the values and keeps
+            // both for 2b, which then needs no second trip to memory when the row's entries
+            // of the chunk fit in one pass (the common case).
+            uint32_t rk0[SR];
+            float rv0[SR];
+#pragma unroll
+            for (int r = 0; r < SR; ++r) {
+                const int64_t p = rpos + r * 64 + lane;
+                const bool ok = p < rend;
+                rk0[r] = ok ? k32[p] : EMPTY;
+                rv0[r] = ok ? vals[p] : 0.f;
+            }
             int64_t rp = rpos;
-            while (true) {
+            bool one_pass = true;
+            for (int pass = 0;; ++pass) {
                 uint32_t kk[SR];
 #pragma unroll
                 for (int r = 0; r < SR; ++r) {
                     const int64_t p = rp + r * 64 + lane;
-                    kk[r] = p < rend ? k32[p] : EMPTY;
+                    kk[r] = pass == 0 ? rk0[r] : p < rend ? k32[p] : EMPTY;
                 }
                 int nin = 0;
 #pragma unroll
@@ -235,18 +256,24 @@ __global__ __launch_bounds__(SP_THREADS, 1) void k_sparse(const uint32_t *__rest
                 }
                 rp += nin;
                 if (nin < SR * 64) break;
+                one_pass = false;
             }
             __syncthreads();
             // 2b. scatter the row values and presence bytes
-            while (true) {
+            for (int pass = 0;; ++pass) {
                 uint32_t kk[SR];
                 float vv[SR];
 #pragma unroll
                 for (int r = 0; r < SR; ++r) {
                     const int64_t p = rpos + r * 64 + lane;
                     const bool ok = p < rend;
-                    kk[r] = ok ? k32[p] : EMPTY;
-                    vv[r] = ok ? vals[p] : 0.f;
+                    if (pass == 0 && one_pass) {
+                        kk[r] = rk0[r];
+                        vv[r] = rv0[r];
+                    } else {
+                        kk[r] = ok ? k32[p] : EMPTY;
+                        vv[r] = ok ? vals[p] : 0.f;
+                    }
                 }
                 int nin = 0;
 #pragma unroll
@@ -325,6 +352,7 @@ __global__ __launch_bounds__(SP_THREADS, 1) void k_sparse(const uint32_t *__rest
                 cpos += nin;
                 if (nin < SR * LPC) break;
             }
+
 #pragma unroll
             for (int t = 0; t < RB; ++t) {
                 cnt[t] += (pk[t >> 2] >> (8 * (t & 3))) & 0xFFu;
@@ -336,7 +364,7 @@ __global__ __launch_bounds__(SP_THREADS, 1) void k_sparse(const uint32_t *__rest
             }
             __syncthreads();
         }
-        // combine the 8 lanes of each column (fixed butterfly) and write
+        // combine the LPC lanes of each column (fixed butterfly) and write
 #pragma unroll
         for (int t = 0; t < RB; ++t) {
 #pragma unroll
@@ -348,7 +376,7 @@ __global__ __launch_bounds__(SP_THREADS, 1) void k_sparse(const uint32_t *__rest
         if (col_ok) {
 #pragma unroll
             for (int t = 0; t < RB; ++t) {
-                if ((t >> 1) != sub) continue;  // lane sub writes rows 2*sub, 2*sub+1
+                if (t / (RB / LPC) != sub) continue;  // lane sub writes rows RB/LPC * sub ..
                 const int srow2 = r0 + t;
                 if (srow2 >= n || srow2 >= scol) continue;
                 const int a = perm[srow2], b = icol;
@@ -393,7 +421,15 @@ rocket_status sp_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, hip
     std::stable_sort(sp.perm.begin(), sp.perm.end(), [&](int a, int b) {
         return sp.h_offsets[a + 1] - sp.h_offsets[a] > sp.h_offsets[b + 1] - sp.h_offsets[b];
     });
-    const int64_t nbands = (n + RB - 1) / RB, nblk = (n + CB - 1) / CB;
+    // 4 lanes per column (256-column work items, half as many band-table builds) once that
+    // still leaves at least 8 work items per CU, else 8 lanes (128-column work items)
+    const int64_t nbands = (n + RB - 1) / RB;
+    const int64_t wide_items = nbands * ((n + 255) / 256) / 2 + nbands;
+    sp.lpc = ctx->opt[ROCKET_OPT_SP_LANES] ? (int)ctx->opt[ROCKET_OPT_SP_LANES]
+             : wide_items >= 8 * (int64_t)ctx->num_cu ? 4
+                                                       : 8;
+    const int64_t CB = SP_THREADS / sp.lpc;
+    const int64_t nblk = (n + CB - 1) / CB;
     // device buffers: u32 keys; meta = flags (2 words) | inverse norms | sorted-position -> item
     void *kp = nullptr, *meta = nullptr;
     RK_TRY(ws_get(ctx, WS_SP_KEYS, sizeof(uint32_t) * (size_t)std::max<int64_t>(sp.total, 1), &kp));
@@ -416,6 +452,7 @@ rocket_status sp_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, hip
     int wlog = 0;
     while (((maxkey >> wlog) + 1) > (uint64_t)(1 << 20)) ++wlog;
     while ((uint64_t)nbands * ((maxkey >> wlog) + 1) * 4 > ((uint64_t)4 << 30)) ++wlog;
+    while (ctx->opt[ROCKET_OPT_SP_CHUNK] > ((int64_t)1 << wlog)) ++wlog;  // caller's lower bound
     const int64_t nmc = (int64_t)(maxkey >> wlog) + 1;
     void *hp = nullptr;
     RK_TRY(ws_get(ctx, WS_SP_CHUNKS, sizeof(unsigned) * (size_t)(nbands * nmc) + sizeof(int) * (nbands + 1), &hp));
@@ -489,12 +526,16 @@ rocket_status sp_compare(rocket_ctx *ctx, float *out, uint32_t *counts, hipStrea
     if (sp.n < 2 || sp.tiles == 0) return ROCKET_OK;
     if (ctx->queue_owner != QOWN_SP) return fail(ctx, ROCKET_E_STATE, "queue was replanned by another prepare");
     RK_TRY(reset_queue(ctx, s, sp.qa));
-    const int grid = auto_grid(ctx, (const void *)&k_sparse, SP_THREADS, 0, sp.tiles);
+    const void *kern = sp.lpc == 4 ? (const void *)&k_sparse<4> : (const void *)&k_sparse<8>;
+    const int grid = auto_grid(ctx, kern, SP_THREADS, 0, sp.tiles);
     ctx->stats.grid = grid;
     RK_TRY(timing_begin(ctx, s));
-    hipLaunchKernelGGL(k_sparse, dim3(grid), dim3(SP_THREADS), 0, s, sp.k32, sp.vals, sp.offsets, sp.dperm, sp.inv_norm,
-                       (int)sp.n, sp.wlog, sp.cshift, sp.bounds, sp.qa,
-                       out, counts);
+    if (sp.lpc == 4)
+        hipLaunchKernelGGL(k_sparse<4>, dim3(grid), dim3(SP_THREADS), 0, s, sp.k32, sp.vals, sp.offsets, sp.dperm,
+                           sp.inv_norm, (int)sp.n, sp.wlog, sp.cshift, sp.bounds, sp.qa, out, counts);
+    else
+        hipLaunchKernelGGL(k_sparse<8>, dim3(grid), dim3(SP_THREADS), 0, s, sp.k32, sp.vals, sp.offsets, sp.dperm,
+                           sp.inv_norm, (int)sp.n, sp.wlog, sp.cshift, sp.bounds, sp.qa, out, counts);
     RK_HIP(hipGetLastError());
     RK_TRY(timing_end(ctx, s));
     return ROCKET_OK;

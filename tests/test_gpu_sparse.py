@@ -45,12 +45,14 @@ def _check(got, cnt, off, keys, vals, pi, pj):
     (2, 50, 200, 1000), (17, 300, 2000, 5000), (40, 500, 3000, 20 ** 4), (130, 800, 5000, 20 ** 4),
     (300, 2000, 20000, 20 ** 6),
 ])
-def test_all_pairs_small(ctx, n, nnz_mean, nnz_max, key_space):
-    announce("sparse all pairs n=%d nnz~%d keys<%d" % (n, nnz_mean, key_space))
+@pytest.mark.parametrize("lanes", [4, 8])
+def test_all_pairs_small(ctx, n, nnz_mean, nnz_max, key_space, lanes):
+    announce("sparse all pairs n=%d nnz~%d keys<%d lanes=%d" % (n, nnz_mean, key_space, lanes))
     off, keys, vals = synth.sparse_vectors(n, key_space=key_space, nnz_mean=nnz_mean, nnz_min=1, nnz_max=nnz_max,
                                            config=4, salt=n)
-    ctx.set(queue_order=0)
+    ctx.set(queue_order=0, sp_lanes=lanes)
     got, cnt = ctx.allpairs(_dev(off, keys, vals), "sparse_cosine", counts=True)
+    ctx.set(sp_lanes=0)
     pi, pj = oracle.all_pairs(n)
     _check(got.cpu().numpy(), cnt.cpu().numpy(), off, keys, vals, pi, pj)
 
@@ -101,6 +103,35 @@ def test_workload_shaped_sampled_and_deterministic(ctx):
     idx = pi * 600 - pi * (pi + 1) // 2 + (pj - pi - 1)
     err = _check(a.cpu().numpy()[idx], ca.cpu().numpy()[idx], off, keys, vals, pi, pj)
     announce("max rel err %.2e" % err)
+
+
+def test_lanes_and_chunk_width_options(ctx):
+    # 4 or 8 lanes per column and a coarser micro-chunk grid change the work split and the
+    # summation order, never the intersections
+    import torch
+    announce("sparse lanes 4/8 x chunk width auto/2^14")
+    off, keys, vals = synth.sparse_vectors(300, nnz_mean=6_000, nnz_min=500, nnz_max=40_000, config=4, salt=21)
+    S = _dev(off, keys, vals)
+    pi, pj = oracle.all_pairs(300)
+    sel = np.arange(0, pi.size, 7)
+    counts = []
+    for lanes in (4, 8):
+        for width in (0, 1 << 14):
+            ctx.set(sp_lanes=lanes, sp_chunk=width)
+            got, cnt = ctx.allpairs(S, "sparse_cosine", counts=True)
+            counts.append(cnt)
+            _check(got.cpu().numpy()[sel], cnt.cpu().numpy()[sel], off, keys, vals, pi[sel], pj[sel])
+    ctx.set(sp_lanes=0, sp_chunk=0)
+    assert all(torch.equal(counts[0], c) for c in counts[1:])
+
+
+def test_option_validation(ctx):
+    from paper_2009_04755_amd._lib import RocketError, E_INVALID
+    announce("sparse option validation")
+    for name, bad in (("sp_lanes", 2), ("sp_lanes", 16), ("sp_chunk", 3), ("sp_chunk", 1000)):
+        with pytest.raises(RocketError) as e:
+            ctx.set(**{name: bad})
+        assert e.value.status == E_INVALID
 
 
 def test_errors(ctx):
