@@ -354,6 +354,9 @@ def main():
     ap.add_argument("--no-variants", action="store_true", help="skip the FP32 and two-term split comparison runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM counter scaling)")
+    ap.add_argument("--only", choices=["clouds", "sparse", "cv", "pce", "ooc"],
+                    help="run only this secondary workload (for profiling it) and print its record; "
+                         "clouds = overlap, GMM L2 / Bhattacharya and the registration gradient")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path (requested %d)" % args.gpus,
@@ -376,10 +379,25 @@ def main():
         del a, b
     n, d = 4096, 1 << 20
     P = n * (n - 1) // 2
+    if args.only and args.only != "ooc":
+        ctx = Context(0)
+        ctx.set(timing=1)
+        cpu = not args.no_cpu_baseline
+        run = {"clouds": lambda: other_pair_fns(ctx, cpu), "sparse": lambda: sparse_pair_fn(ctx, cpu),
+               "cv": lambda: cv_pipeline(ctx, cpu), "pce": lambda: pce_pair_fn(ctx, cpu)}[args.only]
+        print(json.dumps({"only": args.only, "record": run()}))
+        sys.stdout.flush()
+        return
     X, _ = synth.dense_patterns_device(n, d, 64, 0.02, seed=1, device="cuda")
     ctx = Context(0)
     ctx.set(timing=1)
     out = torch.empty(P, dtype=torch.float32, device="cuda")
+    if args.only == "ooc":
+        ctx.allpairs(X, "ncc_bf16x6", out=out)
+        torch.cuda.synchronize()
+        print(json.dumps({"only": args.only, "record": out_of_core(ctx, X, out)}))
+        sys.stdout.flush()
+        return
 
     dt, kern = _time_fn(ctx, X, "ncc_bf16x6", out, args.steps, args.warmup)
     st = ctx.stats()
