@@ -404,7 +404,11 @@ def main():
     value = P * args.steps / dt
     flop = 2.0 * d * P
     achieved = flop / kern / 1e12
-    issued = 6 * 2.0 * st["tile"] ** 2 * ((d + 15) // 16 * 16) * st["tiles"]
+    # issued MFMA flops: 32x32 output blocks x 16-deep slices x 6 products; the 256-tile kernel
+    # skips the 28 blocks below the diagonal of each of the n/256 diagonal tiles
+    T = st["tile"]
+    blocks = st["tiles"] * (T // 32) ** 2 - (28 * ((n + T - 1) // T) if T == 256 else 0)
+    issued = 6 * 2.0 * 32 * 32 * ((d + 15) // 16 * 16) * blocks
     traffic = _traffic_from_profile()
     rec = {
         "metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,

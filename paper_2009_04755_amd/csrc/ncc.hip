@@ -242,8 +242,11 @@ typedef __attribute__((address_space(3))) void *lds_ptr_t;
 typedef __attribute__((address_space(1))) void *gbl_ptr_t;
 
 // ------------------------------------------------------------------------------------------
-// Persistent Gram kernel.  256 threads = 4 waves in a 2x2 arrangement over a BM x BN
-// output block; each wave owns (BM/2) x (BN/2) made of 32x32 MFMA blocks.  One stage = a
+// Persistent Gram kernel.  NWV = 4 waves (2 x 2, one per SIMD) or 8 waves (2 x 4, two per
+// SIMD) over a BM x BN output block; each wave owns (BM/2) x (BN/(NWV/2)) made of 32x32 MFMA
+// blocks (with 8 waves on a 256 tile, two 32-column blocks four apart, so that a diagonal
+// tile's blocks above the diagonal spread evenly over the SIMDs and the rest are skipped).
+// One stage = a
 // 16-deep K slice of all NC operand planes for both row blocks (A = BM rows of block bi,
 // B = BN rows of block bj), copied HBM -> LDS with global_load_lds (no register staging)
 // two slices ahead through three LDS buffers, so a copy has two slices of matrix work to
@@ -291,6 +294,14 @@ __global__ __launch_bounds__(64 * NWV, 1) void k_ncc_gram(const char *__restrict
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wv = __builtin_amdgcn_readfirstlane(wave);
     const int wm = wave / WAVES_N, wn = wave % WAVES_N;
+    // Column blocks of a wave.  With 8 waves on a 256 tile, wave (wm, wn) owns the 32-column
+    // blocks g and g + 4 (g = wn for wm = 0, 3 - wn for wm = 1) with its four 32-row blocks.
+    // On a diagonal tile (bi == bj) the 36 blocks on or above the diagonal then fall 9 to each
+    // SIMD (waves w and w + 4 share one), and the MFMAs of the 28 blocks below it are skipped;
+    // a kept block's MFMA sequence does not depend on which wave runs it.
+    constexpr bool IL = NWV == 8 && BM == 256 && BN == 256;
+    const int g = IL ? (wm == 0 ? wn : WAVES_N - 1 - wn) : 0;
+    auto colblk = [&](int n) { return IL ? g + WAVES_N * n : wn * MBN + n; };
     const int h = lane >> 5;
     const int lrow = lane / SEGS, pseg = lane % SEGS;
 
@@ -303,6 +314,15 @@ __global__ __launch_bounds__(64 * NWV, 1) void k_ncc_gram(const char *__restrict
         const int kc = __builtin_amdgcn_readfirstlane(w.z), slot = __builtin_amdgcn_readfirstlane(w.w);
         const int kt0 = kc * kt_per_chunk;
         const int kt1 = min(kt0 + kt_per_chunk, nkt);
+        // bit m * MBN + n: block (m, n) of this wave lies on or above the diagonal
+        unsigned live = 0;
+#pragma unroll
+        for (int m = 0; m < MA; ++m)
+#pragma unroll
+            for (int n = 0; n < MBN; ++n)
+                if (wm * MA + m <= colblk(n)) live |= 1u << (m * MBN + n);
+        live = __builtin_amdgcn_readfirstlane(live);
+        const bool diag = IL && bi == bj;
 
         f32x16 acc[MA][MBN];
 #pragma unroll
@@ -334,8 +354,10 @@ __global__ __launch_bounds__(64 * NWV, 1) void k_ncc_gram(const char *__restrict
                 __builtin_amdgcn_global_load_lds((gbl_ptr_t)(sbase + loff), (lds_ptr_t)(dstbuf + b * 1024), 16, 0, 0);
             }
         };
-        // one 16-deep K slice from `base`; the copy of slice kt + 2 into `nbuf` starts first
-        auto stage = [&](int kt, const char *base, char *nbuf) {
+        // one 16-deep K slice from `base`; the copy of slice kt + 2 into `nbuf` starts first.
+        // DG: a diagonal tile, whose blocks below the diagonal get no MFMAs.
+        auto stage = [&](auto dg, int kt, const char *base, char *nbuf) {
+            constexpr bool DG = decltype(dg)::value;
             const bool ahead2 = kt + 2 < kt1;
             if (ahead2) issue(kt + 2, nbuf);
             if constexpr (SCH == SCH_FP32) {
@@ -351,7 +373,7 @@ __global__ __launch_bounds__(64 * NWV, 1) void k_ncc_gram(const char *__restrict
                 }
 #pragma unroll
                 for (int n = 0; n < MBN; ++n) {
-                    const int rb = wn * WN + n * 32 + (lane & 31);
+                    const int rb = colblk(n) * 32 + (lane & 31);
                     const char *pb = base + TA + rb * ROWB;
                     const float4 b0 = *(const float4 *)(pb + (((2 * h) ^ swz<SEGS>(rb)) * 16));
                     const float4 b1 = *(const float4 *)(pb + (((2 * h + 1) ^ swz<SEGS>(rb)) * 16));
@@ -364,14 +386,16 @@ __global__ __launch_bounds__(64 * NWV, 1) void k_ncc_gram(const char *__restrict
                     for (int m = 0; m < MA; ++m)
 #pragma unroll
                         for (int n = 0; n < MBN; ++n)
-                            acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[m][ss], fb[n][ss], acc[m][n], 0, 0, 0);
+                            if (!DG || ((live >> (m * MBN + n)) & 1u))
+                                acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[m][ss], fb[n][ss], acc[m][n], 0,
+                                                                                0, 0);
             } else {
                 bf16x8 fb[NC][MBN];
 #pragma unroll
                 for (int c = 0; c < NC; ++c)
 #pragma unroll
                     for (int n = 0; n < MBN; ++n) {
-                        const int rb = wn * WN + n * 32 + (lane & 31);
+                        const int rb = colblk(n) * 32 + (lane & 31);
                         fb[c][n] = *(const bf16x8 *)(base + c * CSB + TA + rb * ROWB + ((h ^ swz<SEGS>(rb)) * 16));
                     }
                 // products grouped by the A component: h*(h, m[, l]), m*(h[, m]), [l*h]
@@ -390,8 +414,9 @@ __global__ __launch_bounds__(64 * NWV, 1) void k_ncc_gram(const char *__restrict
                         for (int m = 0; m < MA; ++m)
 #pragma unroll
                             for (int n = 0; n < MBN; ++n)
-                                acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[m], fb[PB[p]][n], acc[m][n], 0,
-                                                                                    0, 0);
+                                if (!DG || ((live >> (m * MBN + n)) & 1u))
+                                    acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[m], fb[PB[p]][n], acc[m][n],
+                                                                                        0, 0, 0);
                     }
                 }
             }
@@ -414,11 +439,17 @@ __global__ __launch_bounds__(64 * NWV, 1) void k_ncc_gram(const char *__restrict
                 wait_vmcnt<0>();
             }
             __syncthreads();
-            for (int kt = kt0; kt < kt1; kt += 3) {
-                stage(kt, lds0, lds2);
-                if (kt + 1 < kt1) stage(kt + 1, lds1, lds0);
-                if (kt + 2 < kt1) stage(kt + 2, lds2, lds1);
-            }
+            auto kloop = [&](auto dg) {
+                for (int kt = kt0; kt < kt1; kt += 3) {
+                    stage(dg, kt, lds0, lds2);
+                    if (kt + 1 < kt1) stage(dg, kt + 1, lds1, lds0);
+                    if (kt + 2 < kt1) stage(dg, kt + 2, lds2, lds1);
+                }
+            };
+            if (IL && diag)
+                kloop(std::true_type{});
+            else
+                kloop(std::false_type{});
         } else {
             // Split-phase pipeline.  The B fragments and the h fragments of A for slice s are
             // already in registers when slice s starts; its m (and l) fragments of A are read
@@ -502,9 +533,11 @@ __global__ __launch_bounds__(64 * NWV, 1) void k_ncc_gram(const char *__restrict
         // store instruction)
         // the block and wave part of the address is wave-uniform (scalar registers), the lane
         // adds a 32-bit offset, so no per-store address is kept in vector registers
-        const int wmu = __builtin_amdgcn_readfirstlane(wm), wnu = __builtin_amdgcn_readfirstlane(wn);
+        const int wmu = __builtin_amdgcn_readfirstlane(wm);
+        const int cb0 = __builtin_amdgcn_readfirstlane(colblk(0));  // column block n is cb0 + CBSTEP * n
+        constexpr int CBSTEP = IL ? WAVES_N : 1;
         char *ubase = (char *)partial + (((int64_t)slot * nchunks + kc) * (int64_t)BM * BN) * 4 +
-                      ((int64_t)(wmu * WM / 4) * BN + wnu * WN) * 16;
+                      ((int64_t)(wmu * WM / 4) * BN + cb0 * 32) * 16;
         const int loff = (h * BN + (lane & 31)) * 16;
 #pragma unroll
         for (int m = 0; m < MA; ++m)
@@ -512,7 +545,7 @@ __global__ __launch_bounds__(64 * NWV, 1) void k_ncc_gram(const char *__restrict
             for (int qq = 0; qq < 4; ++qq)
 #pragma unroll
                 for (int n = 0; n < MBN; ++n) {
-                    char *ub = ubase + ((m * 8 + 2 * qq) * BN + n * 32) * 16;
+                    char *ub = ubase + ((m * 8 + 2 * qq) * BN + n * CBSTEP * 32) * 16;
                     *(float4 *)(ub + loff) =
                         make_float4(acc[m][n][4 * qq], acc[m][n][4 * qq + 1], acc[m][n][4 * qq + 2], acc[m][n][4 * qq + 3]);
                 }
