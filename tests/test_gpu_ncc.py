@@ -176,9 +176,13 @@ def test_four_and_eight_wave_gram_agree(ctx, fn, tile):
     X = torch.from_numpy(g.standard_normal((tile * 3 + 5, 3000)).astype(np.float32)).cuda()
     ctx.set(ncc_tile=tile, ncc_waves=4)
     a = ctx.allpairs(X, fn)
-    ctx.set(ncc_waves=8)
+    # 8 waves on a 256 tile skip the blocks below the diagonal of diagonal tiles; every
+    # item is still popped exactly once
+    ctx.set(ncc_waves=8, ledger=1)
     b = ctx.allpairs(X, fn)
-    ctx.set(ncc_tile=0, ncc_waves=0)
+    led = ctx.ledger()
+    ctx.set(ncc_tile=0, ncc_waves=0, ledger=0)
+    assert led.size == ctx.stats()["work_items"] and np.all(led == 1)
     assert torch.equal(a, b)
     n = X.shape[0]
     pi, pj = oracle.all_pairs(n)
