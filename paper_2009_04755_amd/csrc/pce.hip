@@ -224,7 +224,7 @@ __global__ __launch_bounds__(PCE_CMP_THREADS, 1) void k_pce(const float2 *__rest
         const int4 w = q.items[it];
         const int i0 = w.x * PCE_T, i1 = min(n, i0 + PCE_T), j0 = w.y * PCE_T, j1 = min(n, j0 + PCE_T);
         // pairs of the tile in row-major order, i < j
-        int pi[2], pj[2], np = 0;
+        int pi[2], pj[2];
         int ci = i0, cj = max(j0, i0 + 1);
         auto next_pair = [&](int &oi, int &oj) -> bool {
             while (ci < i1 && cj >= j1) {
@@ -236,46 +236,65 @@ __global__ __launch_bounds__(PCE_CMP_THREADS, 1) void k_pce(const float2 *__rest
             oj = cj++;
             return true;
         };
-        for (;;) {
-            np = 0;
-            if (next_pair(pi[0], pj[0])) ++np;
-            if (np == 1 && next_pair(pi[1], pj[1])) ++np;
-            if (np == 0) break;
-            constexpr int LH = L / 2 + 1, NH = L * LH;  // stored half spectrum per item
-            const float2 *fa0 = F + (int64_t)pi[0] * NH, *fb0 = F + (int64_t)pj[0] * NH;
-            const float2 *fa1 = F + (int64_t)pi[np - 1] * NH, *fb1 = F + (int64_t)pj[np - 1] * NH;
-            const bool two = np == 2;
-            // conj(Z) = conj(F_a) F_b for each pair; the second is packed as the imaginary part.
-            // Both are Hermitian (real items), so the half spectrum gives every column: column
-            // L - kc of row L - kr holds conj of column kc of row kr for each pair.  The spectra
-            // come from L2/HBM: LB elements per thread are loaded before any is used.
-            constexpr int LB = 8;
-#pragma unroll 1
-            for (int e0 = 0; e0 < NH; e0 += LB * NT) {
-                float2 u[LB], v[LB], u2[LB], v2[LB];
+        // next two pairs of the tile (fewer at its end): their count
+        auto take = [&](int (&qi)[2], int (&qj)[2]) {
+            int m = 0;
+            if (next_pair(qi[0], qj[0])) ++m;
+            if (m == 1 && next_pair(qi[1], qj[1])) ++m;
+            return m;
+        };
+        // conj(Z) = conj(F_a) F_b for each pair; the second is packed as the imaginary part.
+        // Both are Hermitian (real items), so the half spectrum gives every column: column
+        // L - kc of row L - kr holds conj of column kc of row kr for each pair.  The spectra
+        // come from L2/HBM in two rounds of LB elements per thread; the first round of the
+        // next two pairs is loaded before this pair's transform, so it lands meanwhile.
+        constexpr int LH = L / 2 + 1, NH = L * LH;  // stored half spectrum per item
+        constexpr int LB = (NH + 2 * NT - 1) / (2 * NT);
+        auto load = [&](int e0, const int (&qi)[2], const int (&qj)[2], int m, float2 (&u)[LB], float2 (&v)[LB],
+                        float2 (&u2)[LB], float2 (&v2)[LB]) {
+            const float2 *fa0 = F + (int64_t)qi[0] * NH, *fb0 = F + (int64_t)qj[0] * NH;
+            const float2 *fa1 = F + (int64_t)qi[m - 1] * NH, *fb1 = F + (int64_t)qj[m - 1] * NH;
+            const bool two = m == 2;
 #pragma unroll
-                for (int b = 0; b < LB; ++b) {
-                    const int e = e0 + b * NT + threadIdx.x;
-                    const bool ok = e < NH;
-                    u[b] = ok ? fa0[e] : make_float2(0.f, 0.f);
-                    v[b] = ok ? fb0[e] : make_float2(0.f, 0.f);
-                    u2[b] = ok && two ? fa1[e] : make_float2(0.f, 0.f);
-                    v2[b] = ok && two ? fb1[e] : make_float2(0.f, 0.f);
-                }
-#pragma unroll
-                for (int b = 0; b < LB; ++b) {
-                    const int e = e0 + b * NT + threadIdx.x;
-                    if (e >= NH) break;
-                    const int kr = e / LH, kc = e % LH;
-                    const float2 z = make_float2(fmaf(u[b].x, v[b].x, u[b].y * v[b].y),
-                                                 fmaf(u[b].x, v[b].y, -(u[b].y * v[b].x)));
-                    const float2 z2 = make_float2(fmaf(u2[b].x, v2[b].x, u2[b].y * v2[b].y),
-                                                  fmaf(u2[b].x, v2[b].y, -(u2[b].y * v2[b].x)));
-                    a[kr * RS + kc] = make_float2(z.x - z2.y, z.y + z2.x);  // z + i z2
-                    if (kc > 0 && kc < L / 2)  // conj(z) + i conj(z2) at the mirrored frequency
-                        a[((L - kr) % L) * RS + (L - kc)] = make_float2(z.x + z2.y, z2.x - z.y);
-                }
+            for (int b = 0; b < LB; ++b) {
+                const int e = e0 + b * NT + threadIdx.x;
+                const bool ok = e < NH;
+                u[b] = ok ? fa0[e] : make_float2(0.f, 0.f);
+                v[b] = ok ? fb0[e] : make_float2(0.f, 0.f);
+                u2[b] = ok && two ? fa1[e] : make_float2(0.f, 0.f);
+                v2[b] = ok && two ? fb1[e] : make_float2(0.f, 0.f);
             }
+        };
+        auto product = [&](int e0, const float2 (&u)[LB], const float2 (&v)[LB], const float2 (&u2)[LB],
+                           const float2 (&v2)[LB]) {
+#pragma unroll
+            for (int b = 0; b < LB; ++b) {
+                const int e = e0 + b * NT + threadIdx.x;
+                if (e >= NH) break;
+                const int kr = e / LH, kc = e % LH;
+                const float2 z = make_float2(fmaf(u[b].x, v[b].x, u[b].y * v[b].y),
+                                             fmaf(u[b].x, v[b].y, -(u[b].y * v[b].x)));
+                const float2 z2 = make_float2(fmaf(u2[b].x, v2[b].x, u2[b].y * v2[b].y),
+                                              fmaf(u2[b].x, v2[b].y, -(u2[b].y * v2[b].x)));
+                a[kr * RS + kc] = make_float2(z.x - z2.y, z.y + z2.x);  // z + i z2
+                if (kc > 0 && kc < L / 2)  // conj(z) + i conj(z2) at the mirrored frequency
+                    a[((L - kr) % L) * RS + (L - kc)] = make_float2(z.x + z2.y, z2.x - z.y);
+            }
+        };
+        float2 p0[LB], p1[LB], p2[LB], p3[LB];  // first round of the current two pairs
+        int np = take(pi, pj);
+        if (np) load(0, pi, pj, np, p0, p1, p2, p3);
+        while (np) {
+            product(0, p0, p1, p2, p3);
+#pragma unroll 1
+            for (int e0 = LB * NT; e0 < NH; e0 += LB * NT) {
+                float2 u[LB], v[LB], u2[LB], v2[LB];
+                load(e0, pi, pj, np, u, v, u2, v2);
+                product(e0, u, v, u2, v2);
+            }
+            int ni[2], nj[2];
+            const int nnp = take(ni, nj);
+            if (nnp) load(0, ni, nj, nnp, p0, p1, p2, p3);
             __syncthreads();
             fft2d<L, N1, N2, NT>(a, tw);
             // one pass: peak per channel (largest value, smallest shift index on ties) and the
@@ -364,6 +383,11 @@ __global__ __launch_bounds__(PCE_CMP_THREADS, 1) void k_pce(const float2 *__rest
                 if (peak_out) peak_out[pidx] = ok ? (uint32_t)pk[ch] : 0u;
             }
             __syncthreads();  // LDS is refilled by the next pairs
+            pi[0] = ni[0];
+            pi[1] = ni[1];
+            pj[0] = nj[0];
+            pj[1] = nj[1];
+            np = nnp;
         }
     }
 }
