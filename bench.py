@@ -359,7 +359,7 @@ def main():
                          "clouds = overlap, GMM L2 / Bhattacharya and the registration gradient")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path (requested %d)" % args.gpus,
+        print("bench.py runs on exactly one GPU: there is no multi-GPU path (requested %d)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 

@@ -54,7 +54,7 @@
  * pointers, negative sizes, ld < dim, unknown function) happen before anything is
  * enqueued.  Data checks that need the data (ragged offsets, sparse key order and
  * range) run on the device in rocket_prepare, which then synchronises once to read
- * the verdict.  After a failure the context stays usable; rocket_last_error
+ * the result.  After a failure the context stays usable; rocket_last_error
  * returns a message describing the most recent failure.
  */
 #ifndef ROCKET_H

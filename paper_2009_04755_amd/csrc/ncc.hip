@@ -10,8 +10,9 @@
 //                 and a block is one contiguous region.  The out-of-core path's device
 //                 cache slots have exactly this block layout.
 //   k_ncc_gram    persistent: pops (tile, K chunk) items, stages both row blocks of every
-//                 16-deep K slice in LDS (double buffered) and accumulates the tile's Gram
-//                 block with MFMA, FP32 accumulation; writes one partial tile per item
+//                 16-deep K slice in LDS (three stages, copies two slices ahead) and
+//                 accumulates the tile's Gram block with MFMA, FP32 accumulation; writes
+//                 one partial tile per item
 //   k_ncc_finish  per output pair: fixed-order sum of the K-chunk partials, rescale by
 //                 1/(s_i s_j), scatter to the packed upper triangle
 #include <cmath>
