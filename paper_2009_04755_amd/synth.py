@@ -221,8 +221,8 @@ def sparse_vectors_device(n: int, key_space: int = 20 ** 6, zipf_a: float = 1.1,
     """Device-side version of :func:`sparse_vectors` for multi-GB sets (same recipe).
 
     nnz and the key bijection come from the host PCG64 stream; Zipf ranks are drawn on the
-    device by inverse-CDF lookup in the truncated distribution's FP64 CDF, from a seeded
-    ``torch.Generator``.  Returns device tensors ``(offsets int64[n+1], keys int64[total],
+    device by inverse-CDF lookup in the truncated distribution's FP64 CDF (summed on the
+    host), from a seeded ``torch.Generator``.  Returns device tensors ``(offsets int64[n+1], keys int64[total],
     vals f32[total])``.
     """
     import torch
@@ -238,10 +238,12 @@ def sparse_vectors_device(n: int, key_space: int = 20 ** 6, zipf_a: float = 1.1,
     add = int(g.integers(0, key_space))
     tg = torch.Generator(device=device)
     tg.manual_seed(SEED_BASE * 1000 + 4000 + int(seed))
-    ranks = torch.arange(1, key_space + 1, device=device, dtype=torch.float64)
-    cdf = torch.cumsum(ranks.pow_(-zipf_a), 0)
-    cdf /= cdf[-1].clone()
-    del ranks
+    # the truncated Zipf CDF by a sequential host sum (a parallel device scan need not give
+    # the same last bits on every run, and a last-bit change moves a rare draw)
+    c = np.cumsum(np.arange(1, key_space + 1, dtype=np.float64) ** -zipf_a)
+    c /= c[-1]
+    cdf = torch.from_numpy(c).to(device)
+    del c
     offsets = np.zeros(n + 1, dtype=np.int64)
     offsets[1:] = np.cumsum(nnz)
     keys = torch.empty(int(offsets[-1]), dtype=torch.int64, device=device)

@@ -125,6 +125,26 @@ def test_lanes_and_chunk_width_options(ctx):
     assert all(torch.equal(counts[0], c) for c in counts[1:])
 
 
+def test_device_generator_is_reproducible_across_processes():
+    # the seeded device generator gives the same bytes in a fresh process (its Zipf CDF is
+    # a sequential host sum, so no parallel scan can move a draw)
+    import subprocess
+    import sys
+    import torch
+    device_or_skip()
+    announce("sparse device generator: same bytes in a child process")
+    code = ("import sys; sys.path.insert(0, %r); import torch; from paper_2009_04755_amd import synth; "
+            "o, k, v = synth.sparse_vectors_device(48, nnz_mean=3000, nnz_min=500, nnz_max=20000, seed=3); "
+            "print(synth.sha256(o.cpu().numpy(), k.cpu().numpy(), v.cpu().numpy()))")
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    child = subprocess.run([sys.executable, "-c", code % root], capture_output=True, text=True, timeout=300)
+    assert child.returncode == 0, child.stderr[-2000:]
+    o, k, v = synth.sparse_vectors_device(48, nnz_mean=3000, nnz_min=500, nnz_max=20000, seed=3)
+    torch.cuda.synchronize()
+    assert child.stdout.strip().splitlines()[-1] == synth.sha256(o.cpu().numpy(), k.cpu().numpy(), v.cpu().numpy())
+
+
 def test_option_validation(ctx):
     from paper_2009_04755_amd._lib import RocketError, E_INVALID
     announce("sparse option validation")
