@@ -189,7 +189,10 @@ rocket_status rocket_allpairs(const rocket_items *items, int64_t n, rocket_pair_
  * K: 3..6.  Outputs form a ROCKET_SPARSE_COSINE item set: cv_offsets int64 [n+1], keys
  * int64 and vals float32 of `capacity` entries; capacity >= offsets[n] always suffices
  * (ROCKET_E_INVALID if the entries do not fit).  Reads offsets to the host and
- * synchronises once at the start and once at the end. */
+ * synchronises once at the start and once at the end.  Workspace: dense counts of
+ * 4 (20^K + 20^(K-1) + 20^(K-2)) bytes per species for a group of up to 64 species
+ * (~257 MB per species at K = 6), the group sized to a quarter of the free device memory
+ * and half of ROCKET_OPT_WORKSPACE_CAP when that is set; kept by the context. */
 rocket_status rocket_cv_build(rocket_ctx *ctx, const uint8_t *residues, const int64_t *offsets, int64_t n, int K,
                               int64_t *cv_offsets, int64_t *keys, float *vals, int64_t capacity, void *stream);
 
