@@ -164,7 +164,9 @@ __global__ void k_cv_base(const int64_t *__restrict__ nnz, int G, int64_t s0, in
 }
 
 // grid (chunks / 4, group size), 256 threads: one wave per 1024-code chunk, 16 codes per lane
-// (four 16-byte loads); a wave prefix sum ranks the non-zero codes, so no workgroup barrier.
+// (four 16-byte loads); a wave prefix sum ranks the non-zero codes (so no workgroup barrier)
+// and places them, in code order, in the wave's LDS list; the lanes then take the list's
+// entries one each, so the lookups and stores of all of them are in flight together.
 __global__ __launch_bounds__(256) void k_cv_emit(uint32_t *__restrict__ cK, const uint32_t *__restrict__ c1,
                                                  const uint32_t *__restrict__ c2,
                                                  const uint32_t *__restrict__ chunk_base, int64_t nchunks,
@@ -173,8 +175,11 @@ __global__ __launch_bounds__(256) void k_cv_emit(uint32_t *__restrict__ cK, cons
                                                  int64_t *__restrict__ keys, float *__restrict__ vals,
                                                  int64_t capacity, int *__restrict__ overflow)
 {
+    __shared__ uint16_t lcode[4][CV_CH];  // per wave: offset of the code in the chunk
+    __shared__ uint32_t lcnt[4][CV_CH];   // and its count
     const int y = blockIdx.y;
-    const int64_t chunk = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int wave = threadIdx.x >> 6;
+    const int64_t chunk = (int64_t)blockIdx.x * 4 + wave;
     if (chunk >= nchunks) return;
     const int lane = threadIdx.x & 63;
     const int64_t szK = ipow20(K), sz1 = szK / CV_ALPHA, sz2 = sz1 / CV_ALPHA;
@@ -203,24 +208,36 @@ __global__ __launch_bounds__(256) void k_cv_emit(uint32_t *__restrict__ cK, cons
         const int t = __shfl_up(incl, o);
         if (lane >= o) incl += t;
     }
-    if (mine == 0) return;
-    const double NK = (double)tot[3 * y], N1 = (double)tot[3 * y + 1], N2 = (double)tot[3 * y + 2];
-    int64_t pos = cv_off[s0 + y] + chunk_base[y * nchunks + chunk] + (incl - mine);
+    const int total = __shfl(incl, 63);
+    if (total == 0) return;
+    int slot = incl - mine;
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        if (v[t] == 0u) continue;
-        const int64_t code = code0 + t;
+    for (int t = 0; t < 16; ++t)
+        if (v[t] != 0u) {
+            lcode[wave][slot] = (uint16_t)(16 * lane + t);
+            lcnt[wave][slot] = v[t];
+            ++slot;
+        }
+    // the list is written and read by this wave only: a wave-wide LDS fence suffices
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const double NK = (double)tot[3 * y], N1 = (double)tot[3 * y + 1], N2 = (double)tot[3 * y + 2];
+    const int64_t base = cv_off[s0 + y] + chunk_base[y * nchunks + chunk];
+    for (int e = lane; e < total; e += 64) {
+        const int64_t code = (chunk << CV_CHLOG) + lcode[wave][e];
+        const uint32_t cnt = lcnt[wave][e];
+        const int64_t pos = base + e;
         if (pos >= capacity) {
             *overflow = 1;
         } else {
             const int64_t pre = code / CV_ALPHA, suf = code % sz1, mid = pre % sz2;
-            const double f = (double)v[t] / NK;
+            const double f = (double)cnt / NK;
             const double f0 = ((double)c1y[pre] / N1) * ((double)c1y[suf] / N1) / ((double)c2y[mid] / N2);
             keys[pos] = code;
             vals[pos] = (float)((f - f0) / f0);
         }
         cKy[code] = 0u;  // leave the K array clean for the next group
-        ++pos;
     }
 }
 
