@@ -6,11 +6,11 @@
 //
 // Species are processed in groups.  Per species the counts of K-, (K-1)- and (K-2)-strings
 // are dense arrays over the code space (20^K u32; 256 MB at K = 6).  The K array is filled
-// with atomics, one thread per window start, and a K-string's first occurrence also bumps
-// the occupancy count of its 1024-code chunk; the shorter arrays get atomics only for the
+// with atomics, one thread per window start; the shorter arrays get atomics only for the
 // windows at a protein end and are then folded from the longer ones (a (K-1)-string's count
-// is the sum over the 20 K-strings that extend it, plus its protein-end windows).  A scan
-// of the chunk counts gives every chunk its output base; an emit pass streams the dense K
+// is the sum over the 20 K-strings that extend it, plus its protein-end windows), the K ->
+// K-1 fold also counting the non-zero codes of every 1024-code chunk.  A scan of the chunk
+// counts gives every chunk its output base; an emit pass streams the dense K
 // array chunk by chunk (one wave per chunk), ranks the non-zero codes with a wave prefix
 // sum (so keys come out ascending), writes key and a(s) (FP64, rounded once to f32) and
 // writes zeros back, so the K array is clean for the next group.
@@ -58,14 +58,12 @@ __device__ inline int64_t window_code(const uint8_t *__restrict__ res, int64_t p
 __global__ __launch_bounds__(256) void k_cv_count(const uint8_t *__restrict__ res, const int64_t *__restrict__ off,
                                                   int64_t s0, int K, uint32_t *__restrict__ cK,
                                                   uint32_t *__restrict__ c1, uint32_t *__restrict__ c2,
-                                                  uint32_t *__restrict__ chunk_cnt, int64_t nchunks,
                                                   unsigned long long *__restrict__ tot)
 {
     const int y = blockIdx.y;
     const int64_t b = off[s0 + y], e = off[s0 + y + 1];
     const int64_t szK = ipow20(K), sz1 = szK / CV_ALPHA, sz2 = sz1 / CV_ALPHA;
     uint32_t *cKy = cK + y * szK, *c1y = c1 + y * sz1, *c2y = c2 + y * sz2;
-    uint32_t *chy = chunk_cnt + y * nchunks;
     unsigned nk = 0, n1 = 0, n2 = 0;
     for (int64_t p = b + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < e; p += (int64_t)gridDim.x * blockDim.x) {
         // Only K-windows are counted here; a shorter window that extends to a valid longer
@@ -86,8 +84,7 @@ __global__ __launch_bounds__(256) void k_cv_count(const uint8_t *__restrict__ re
             atomicAdd(c1y + w1, 1u);
             continue;
         }
-        const int64_t wK = w1 * CV_ALPHA + rK;
-        if (atomicAdd(cKy + wK, 1u) == 0u) atomicAdd(chy + (wK >> CV_CHLOG), 1u);
+        atomicAdd(cKy + w1 * CV_ALPHA + rK, 1u);
         ++nk;
     }
     // wave sums, one atomic per wave and total
@@ -101,6 +98,55 @@ __global__ __launch_bounds__(256) void k_cv_count(const uint8_t *__restrict__ re
         atomicAdd(tot + 3 * y + 1, (unsigned long long)n1);
         atomicAdd(tot + 3 * y + 2, (unsigned long long)n2);
     }
+}
+
+// K -> K-1 fold and the occupancy of the K array's chunks in one pass over it.  One wave per
+// block of 5120 K-codes (five 1024-code chunks = the 20 extensions of 256 (K-1)-codes): lane l
+// adds the extensions of (K-1)-codes 4l .. 4l+3 of the block into c1 and counts the non-zero
+// K counts of each chunk it touches (at most two).  grid (blocks / 4, group size).
+constexpr int CV_FOLD_W = 256;  // (K-1)-codes per block
+__global__ __launch_bounds__(256) void k_cv_fold_k(const uint32_t *__restrict__ cK, uint32_t *__restrict__ c1,
+                                                   uint32_t *__restrict__ chunk_cnt, int64_t sz1, int64_t nchunks)
+{
+    __shared__ unsigned nzc[4][CV_FOLD_W * CV_ALPHA / CV_CH];
+    const int y = blockIdx.y, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t blk = (int64_t)blockIdx.x * 4 + wave;
+    const int64_t w0 = blk * CV_FOLD_W;
+    if (w0 >= sz1) return;
+    const uint32_t *cl = cK + y * sz1 * CV_ALPHA;
+    uint32_t *cs = c1 + y * sz1;
+    constexpr int NCB = CV_FOLD_W * CV_ALPHA / CV_CH;  // chunks per block (5)
+    if (lane < NCB) nzc[wave][lane] = 0u;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // this lane's 80 K-codes start at local offset 80 l; below `split` they belong to
+    // local chunk c_lo, from it on to c_lo + 1
+    const int first = 4 * CV_ALPHA * lane, c_lo = first >> CV_CHLOG, split = (c_lo + 1) << CV_CHLOG;
+    unsigned lo = 0, hi = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t w = w0 + 4 * lane + q;
+        if (w >= sz1) break;
+        const uint32_t *p = cl + w * CV_ALPHA;  // 80 bytes, 16-byte aligned
+        uint32_t t = 0;
+#pragma unroll
+        for (int a = 0; a < CV_ALPHA; a += 4) {
+            const uint4 v = *(const uint4 *)(p + a);
+            t += v.x + v.y + v.z + v.w;
+            const int k = first + CV_ALPHA * q + a;  // local offset of v.x
+            const unsigned nz = (v.x != 0u) + (v.y != 0u) + (v.z != 0u) + (v.w != 0u);
+            if (k < split) lo += nz; else hi += nz;  // 1024 is a multiple of 4: v never straddles
+        }
+        cs[w] += t;
+    }
+    if (lo) atomicAdd(&nzc[wave][c_lo], lo);
+    if (hi) atomicAdd(&nzc[wave][c_lo + 1], hi);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int64_t ch = blk * NCB + lane;
+    if (lane < NCB && ch < nchunks) chunk_cnt[y * nchunks + ch] = nzc[wave][lane];
 }
 
 // c_short[w] += sum_a c_long[20 w + a]: every window of the longer length starts with a
@@ -313,10 +359,11 @@ rocket_status cv_build(rocket_ctx *ctx, const uint8_t *res, const int64_t *offse
         if (longest > 0) {
             const unsigned bx = (unsigned)std::min<int64_t>(2048, (longest + 255) / 256);
             hipLaunchKernelGGL(k_cv_count, dim3(bx, g), dim3(256), 0, s, res, offsets, s0, K, (uint32_t *)pK,
-                               (uint32_t *)p1, (uint32_t *)p2, (uint32_t *)pch, nchunks, (unsigned long long *)ptot);
+                               (uint32_t *)p1, (uint32_t *)p2, (unsigned long long *)ptot);
         }
-        hipLaunchKernelGGL(k_cv_fold, dim3((unsigned)std::min<int64_t>(4096, (sz1 + 255) / 256), g), dim3(256), 0, s,
-                           (const uint32_t *)pK, (uint32_t *)p1, sz1);
+        const int64_t fblocks = (sz1 + CV_FOLD_W - 1) / CV_FOLD_W;
+        hipLaunchKernelGGL(k_cv_fold_k, dim3((unsigned)((fblocks + 3) / 4), g), dim3(256), 0, s, (const uint32_t *)pK,
+                           (uint32_t *)p1, (uint32_t *)pch, sz1, nchunks);
         hipLaunchKernelGGL(k_cv_fold, dim3((unsigned)std::min<int64_t>(4096, (sz2 + 255) / 256), g), dim3(256), 0, s,
                            (const uint32_t *)p1, (uint32_t *)p2, sz2);
         hipLaunchKernelGGL(k_cv_scan, dim3(g), dim3(1024), 0, s, (uint32_t *)pch, nchunks, (int64_t *)pnnz);
