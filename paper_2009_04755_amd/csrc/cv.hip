@@ -101,52 +101,60 @@ __global__ __launch_bounds__(256) void k_cv_count(const uint8_t *__restrict__ re
 }
 
 // K -> K-1 fold and the occupancy of the K array's chunks in one pass over it.  One wave per
-// block of 5120 K-codes (five 1024-code chunks = the 20 extensions of 256 (K-1)-codes): lane l
-// adds the extensions of (K-1)-codes 4l .. 4l+3 of the block into c1 and counts the non-zero
-// K counts of each chunk it touches (at most two).  grid (blocks / 4, group size).
+// block of 5120 K-codes (five 1024-code chunks = the 20 extensions of 256 (K-1)-codes).
+// Lane l reads 16-byte vectors j * 64 + l, j < 20, so every load is one contiguous 1 KB run;
+// vector j lies in chunk j / 4 of the block, so the non-zero counts per chunk are register
+// sums reduced across the wave.  The vector sums go to LDS, where lane l adds up the five
+// vectors of (K-1)-codes l, l + 64, l + 128 and l + 192.  grid (blocks / 4, group size).
 constexpr int CV_FOLD_W = 256;  // (K-1)-codes per block
 __global__ __launch_bounds__(256) void k_cv_fold_k(const uint32_t *__restrict__ cK, uint32_t *__restrict__ c1,
                                                    uint32_t *__restrict__ chunk_cnt, int64_t sz1, int64_t nchunks)
 {
-    __shared__ unsigned nzc[4][CV_FOLD_W * CV_ALPHA / CV_CH];
+    constexpr int NV = CV_FOLD_W * CV_ALPHA / 4;  // 16-byte vectors per block (1280)
+    constexpr int NJ = NV / 64;                   // per lane (20)
+    constexpr int NCB = NJ / 4;                   // chunks per block (5)
+    static_assert(NV % 64 == 0 && NJ % 4 == 0 && 4 * 4 * 64 == CV_CH, "four vectors of each lane per chunk");
+    __shared__ uint32_t vsum[4][NV];
     const int y = blockIdx.y, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t blk = (int64_t)blockIdx.x * 4 + wave;
     const int64_t w0 = blk * CV_FOLD_W;
     if (w0 >= sz1) return;
-    const uint32_t *cl = cK + y * sz1 * CV_ALPHA;
-    uint32_t *cs = c1 + y * sz1;
-    constexpr int NCB = CV_FOLD_W * CV_ALPHA / CV_CH;  // chunks per block (5)
-    if (lane < NCB) nzc[wave][lane] = 0u;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // this lane's 80 K-codes start at local offset 80 l; below `split` they belong to
-    // local chunk c_lo, from it on to c_lo + 1
-    const int first = 4 * CV_ALPHA * lane, c_lo = first >> CV_CHLOG, split = (c_lo + 1) << CV_CHLOG;
-    unsigned lo = 0, hi = 0;
+    const int64_t nvalid = std::min<int64_t>(CV_FOLD_W, sz1 - w0) * (CV_ALPHA / 4);  // vectors of this block
+    const uint4 *cl = (const uint4 *)(cK + (y * sz1 + w0) * CV_ALPHA);
+    unsigned nz[NCB];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int64_t w = w0 + 4 * lane + q;
-        if (w >= sz1) break;
-        const uint32_t *p = cl + w * CV_ALPHA;  // 80 bytes, 16-byte aligned
-        uint32_t t = 0;
+    for (int c = 0; c < NCB; ++c) nz[c] = 0u;
+    uint4 v[NJ];
 #pragma unroll
-        for (int a = 0; a < CV_ALPHA; a += 4) {
-            const uint4 v = *(const uint4 *)(p + a);
-            t += v.x + v.y + v.z + v.w;
-            const int k = first + CV_ALPHA * q + a;  // local offset of v.x
-            const unsigned nz = (v.x != 0u) + (v.y != 0u) + (v.z != 0u) + (v.w != 0u);
-            if (k < split) lo += nz; else hi += nz;  // 1024 is a multiple of 4: v never straddles
-        }
-        cs[w] += t;
+    for (int j = 0; j < NJ; ++j) {
+        const int e = j * 64 + lane;
+        v[j] = e < nvalid ? cl[e] : make_uint4(0u, 0u, 0u, 0u);
     }
-    if (lo) atomicAdd(&nzc[wave][c_lo], lo);
-    if (hi) atomicAdd(&nzc[wave][c_lo + 1], hi);
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        nz[j / 4] += (v[j].x != 0u) + (v[j].y != 0u) + (v[j].z != 0u) + (v[j].w != 0u);
+        vsum[wave][j * 64 + lane] = v[j].x + v[j].y + v[j].z + v[j].w;
+    }
+#pragma unroll
+    for (int c = 0; c < NCB; ++c)
+        for (int o = 32; o > 0; o >>= 1) nz[c] += __shfl_xor(nz[c], o);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int64_t ch = blk * NCB + lane;
-    if (lane < NCB && ch < nchunks) chunk_cnt[y * nchunks + ch] = nzc[wave][lane];
+    uint32_t *cs = c1 + y * sz1;
+#pragma unroll
+    for (int q = 0; q < CV_FOLD_W / 64; ++q) {
+        const int wl = q * 64 + lane;  // (K-1)-code within the block: vectors 5 wl .. 5 wl + 4
+        if (w0 + wl < sz1) {
+            const uint32_t *p = &vsum[wave][5 * wl];
+            cs[w0 + wl] += p[0] + p[1] + p[2] + p[3] + p[4];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NCB; ++c) {
+        const int64_t ch = blk * NCB + c;
+        if (lane == 0 && ch < nchunks) chunk_cnt[y * nchunks + ch] = nz[c];
+    }
 }
 
 // c_short[w] += sum_a c_long[20 w + a]: every window of the longer length starts with a
