@@ -69,14 +69,21 @@ def test_edge_species(ctx):
     assert og[1] == og[0] and og[2] == og[1] and og[3] == og[2]
 
 
-def test_groups_and_reuse_across_calls(ctx):
-    # more species than one group (K = 6 groups hold ~15 species), then a call with another
-    # K, then K = 6 again: the count arrays must come back clean every time
-    announce("cv groups n=40 K=6, then K=5, then K=6")
+def test_groups_and_reuse_across_calls():
+    # a 3 GiB workspace cap limits K = 6 groups to 5 species (~257 MB of counts each), so 40
+    # species take 8 groups; then a call with another K (one group), then K = 6 again: the
+    # count arrays must come back clean every time
+    from paper_2009_04755_amd import Context
+    device_or_skip()
+    announce("cv groups n=40 K=6 (8 groups), then K=5, then K=6")
+    c = Context(0)
+    c.set(workspace_cap=3 << 30)
     res, off = synth.proteomes(40, n_families=200, config=5, salt=11)
     for K in (6, 5, 6):
-        _, og, kg, vg = _gpu_cv(ctx, res, off, K)
+        _, og, kg, vg = _gpu_cv(c, res, off, K)
         _check(og, kg, vg, res, off, K)
+    assert c.stats()["workspace_bytes"] <= 3 << 30
+    c.close()
 
 
 def test_end_to_end_cosine(ctx):
