@@ -9,9 +9,15 @@ and split (prepare), the persistent tile kernel over the divide-and-conquer queu
 split-K epilogue into the packed upper triangle (8,386,560 results).
 
 Prints ONE JSON line.  ``value`` is pairs/s; ``roofline`` is the Gram kernel's algorithmic
-2*d flop per pair against the bf16 dense MFMA peak; ``cpu_baseline`` times the FP64 oracle
-on a bounded sample of the same workload on this host.  Extra fields report the plain
-FP32 and two-term split paths at the same shape and the other two pair functions.
+2*d flop per pair against the bf16 dense MFMA peak (``traffic``: the HBM bytes of the
+committed counter file when its kernel-source hash matches); ``cpu_baseline`` times the
+FP64 oracle on a bounded sample of the same workload on this host.  Extra fields report the
+plain FP32 and two-term split paths at the same shape, the same workload through the
+out-of-core device cache, the Gaussian-overlap, GMM and registration-gradient costs over
+2048 point clouds, the sparse cosine of 8192 k-mer vectors, the PCE of 1024 images and the
+composition-vector construction of 128 proteomes, each with its own roofline and, where
+cheap enough, the oracle on a sample.  ``--only`` runs one of those workloads alone (for
+profiling).
 """
 from __future__ import annotations
 
