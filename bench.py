@@ -321,15 +321,16 @@ def sparse_pair_fn(ctx, with_cpu=True):
     kern = ctx.stats()["kernel_ns"] * 1e-9
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    # streamed bytes: every (16-item band, 128-item column block) work item reads the u32 keys
-    # and f32 values of its 16 rows and 128 columns once
+    # streamed bytes: every (16-item band, CB-item column block) work item reads the u32 keys
+    # and f32 values of its 16 rows and CB columns once; CB = 1024 / (lanes per column)
+    cb = 1024 // ctx.stats()["variant"]
     nnz = np.sort(np.diff(off.cpu().numpy()))[::-1].astype(np.float64)
     band = np.add.reduceat(nnz, np.arange(0, n, 16))
-    blk = np.add.reduceat(nnz, np.arange(0, n, 128))
+    blk = np.add.reduceat(nnz, np.arange(0, n, cb))
     byts = 0.0
     for b in range(band.size):
         for c in range(blk.size):
-            if b * 16 < min(n, (c + 1) * 128) - 1:
+            if b * 16 < min(n, (c + 1) * cb) - 1:
                 byts += 8.0 * (band[b] + blk[c])
     res = {"workload": "8192 sparse vectors over 20^6 keys, lognormal nnz (mean 2e5), Zipf(1.1) keys",
            "entries": int(nnz.sum()), "pairs_per_s": P / dt, "kernel_ms": kern * 1e3,

@@ -268,7 +268,9 @@ typedef struct {
     int64_t tile;            /* tile edge in items (NCC) or clouds/items per block */
     int64_t kchunk;          /* NCC split-K chunk length (0 otherwise) */
     int64_t workspace_bytes; /* device bytes currently held by the context */
-    int64_t variant;         /* kernel variant in use */
+    int64_t variant;         /* kernel variant in use: NCC pair function, overlap inner-loop variant, sparse
+                                lanes per column item (a work item covers 1024 / variant column items),
+                                PCE side L */
     int64_t kernel_ns;       /* duration of the last main kernel (ROCKET_OPT_TIMING=1), else -1;
                                 reading it waits for that kernel to finish */
     int64_t cache_slots;     /* rocket_allpairs_host: device cache slots used (0 otherwise) */

@@ -515,6 +515,7 @@ rocket_status sp_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, hip
     ctx->stats.work_items = sp.tiles;
     ctx->stats.tile = RB;
     ctx->stats.kchunk = sp.nchunks_total;
+    ctx->stats.variant = sp.lpc;
     sp.valid = true;
     return ROCKET_OK;
 }

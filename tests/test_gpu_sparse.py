@@ -119,6 +119,7 @@ def test_lanes_and_chunk_width_options(ctx):
         for width in (0, 1 << 14):
             ctx.set(sp_lanes=lanes, sp_chunk=width)
             got, cnt = ctx.allpairs(S, "sparse_cosine", counts=True)
+            assert ctx.stats()["variant"] == lanes
             counts.append(cnt)
             _check(got.cpu().numpy()[sel], cnt.cpu().numpy()[sel], off, keys, vals, pi[sel], pj[sel])
     ctx.set(sp_lanes=0, sp_chunk=0)
