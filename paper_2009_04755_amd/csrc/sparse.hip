@@ -471,7 +471,7 @@ rocket_status sp_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, hip
     RK_HIP(hipMemcpyAsync(hf, flags, 4, hipMemcpyDeviceToHost, s));
     RK_HIP(hipStreamSynchronize(s));
     if (hf[0] & FLAG_OVERFLOW)
-        return fail(ctx, ROCKET_E_UNSUPPORTED, "more than 1632 keys of one 16-item band fall in one micro-chunk");
+        return fail(ctx, ROCKET_E_UNSUPPORTED, "more than " + std::to_string(UMAX) + " keys of one 16-item band fall in one micro-chunk");
     // band b's nch_b + 1 boundaries live at cshift[b] = sum_{c<b} (nch_c + 1)
     std::vector<int64_t> cshift(nbands + 1, 0);
     for (int64_t b = 0; b < nbands; ++b) cshift[b + 1] = cshift[b] + hn[b] + 1;
