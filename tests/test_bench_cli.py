@@ -24,3 +24,39 @@ def test_help_lists_single_workload_flag():
     assert r.returncode == 0
     for flag in ("--steps", "--warmup", "--gpus", "--only", "--no-cpu-baseline"):
         assert flag in r.stdout
+
+
+def _bench_module():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_counter_file_matches_kernel_source_and_is_consistent():
+    # the committed Gram counter summary was taken on the current kernel source, so the bench
+    # reports its traffic; its figures agree with each other and with a physical lower bound
+    b = _bench_module()
+    vals = {}
+    with open(b.COUNTERS_FILE) as f:
+        for line in f:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                vals[k.strip()] = v.split("#")[0].strip()
+    assert vals["kernel_source_sha256_16"] == b._src_hash("ncc.hip", "queue.hpp")
+    rd, wr = float(vals["hbm_read_bytes_per_launch"]), float(vals["hbm_write_bytes_per_launch"])
+    assert abs(float(vals["fetch_scale"]) - 1048576 / float(vals["copy_fetch_size_kib"])) <= 1e-5
+    assert abs(rd - float(vals["fetch_size_kib"]) * 1024 * float(vals["fetch_scale"])) <= 1e-5 * rd
+    assert abs(wr - float(vals["write_size_kib"]) * 1024) <= 1e-5 * wr
+    total = b._traffic_from_profile()
+    assert total is not None and abs(total - (rd + wr)) <= 1e-5 * total
+    n, d = 4096, 1 << 20
+    assert rd >= n * d * 3 * 2          # every prepared bf16 operand plane is read at least once
+    assert wr >= n * (n - 1) // 2 * 4   # every pair's f32 result is written
+
+
+def test_traffic_is_dropped_when_the_kernel_source_changes(monkeypatch):
+    b = _bench_module()
+    monkeypatch.setattr(b, "_src_hash", lambda *names: "0000000000000000")
+    assert b._traffic_from_profile() is None
