@@ -323,10 +323,10 @@ rocket_status cv_build(rocket_ctx *ctx, const uint8_t *res, const int64_t *offse
     const int64_t szK = ipow20(K), sz1 = szK / CV_ALPHA, sz2 = sz1 / CV_ALPHA;
     const int64_t nchunks = (szK + CV_CH - 1) / CV_CH;
     const int64_t per_species = 4 * (szK + sz1 + sz2 + nchunks) + 8 * 4;
-    // Species per group: as many as fit (more species per launch keep more of the chip busy;
-    // measured at K = 6: 15 per group 52 ms, 63 per group 44 ms for 128 proteomes), up to 64,
-    // within a quarter of the free device memory and half the workspace cap, with the
-    // species spread evenly over the groups.
+    // Species per group: as many as fit, up to 64 (more species per launch keep more of the
+    // chip busy: at K = 6 every step from 1 to 63 species per group measured faster), within
+    // a quarter of the free device memory and half the workspace cap, with the species spread
+    // evenly over the groups.
     size_t free_b = 0, total_b = 0;
     RK_HIP(hipMemGetInfo(&free_b, &total_b));
     int64_t budget = (int64_t)(free_b / 4) + (int64_t)ctx->ws[WS_CV_K].bytes + (int64_t)ctx->ws[WS_CV_AUX].bytes;
