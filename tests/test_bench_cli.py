@@ -60,3 +60,24 @@ def test_traffic_is_dropped_when_the_kernel_source_changes(monkeypatch):
     b = _bench_module()
     monkeypatch.setattr(b, "_src_hash", lambda *names: "0000000000000000")
     assert b._traffic_from_profile() is None
+
+
+def test_profile_commands_use_existing_bench_flags():
+    # every rocprofv3 command recorded in profiles/ runs bench.py with flags it accepts
+    import glob
+    import re
+    helptext = _run("--help").stdout
+    cmds = []
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*.txt")):
+        with open(path) as f:
+            for line in f:
+                if line.startswith("#") and "rocprofv3" in line and "bench.py" in line:
+                    assert "-- python3 bench.py" in line, line  # the program runs directly after --
+                    cmds.append((os.path.basename(path), line.split("bench.py", 1)[1]))
+    assert len(cmds) >= 8
+    for name, args in cmds:
+        for flag in re.findall(r"--[a-z][a-z0-9-]*", args):
+            assert flag in helptext, (name, flag)
+        m = re.search(r"--only (\S+)", args)
+        if m:
+            assert m.group(1) in ("clouds", "sparse", "cv", "pce", "ooc"), (name, m.group(1))
