@@ -217,8 +217,11 @@ rocket_status rocket_allpairs_host(rocket_ctx *ctx, const float *host_items /* h
  * with its gradient
  *     dC/dt     = -(1/(2 sigma^2)) sum w_kl (y'_l - x_k)
  *     dC/dtheta = -(1/(2 sigma^2)) sum w_kl <y'_l - x_k, dR/dtheta (y_l - c_j)>.
- * clouds: offsets + xy + sigma as for ROCKET_GAUSS_OVERLAP (this call prepares them
- * itself, reusing the last overlap preparation when the same arrays are passed).
+ * clouds: offsets + xy + sigma as for ROCKET_GAUSS_OVERLAP; this call prepares them (size
+ * sort and packing, with one synchronisation).  clouds = NULL reuses the clouds prepared by
+ * the previous rocket_overlap_cost_grad on this context (no other prepare in between, same
+ * n): the caller guarantees that they are alive and unchanged, e.g. across the steps of one
+ * descent; else ROCKET_E_STATE.
  * centroids: float32 [n][2].  params: float32 [P][3].  out_cost: float32 [P].
  * out_grad: float32 [P][3] (theta, tx, ty), may be NULL for cost only.
  * Outputs are in packed upper-triangle order.  Enqueued on `stream`. */
@@ -242,6 +245,7 @@ typedef enum {
                                        work items per CU, else 8); a work item covers
                                        1024 / lanes column items */
     ROCKET_OPT_SP_CHUNK = 10,       /* sparse: least micro-chunk width of the key-range cut, a power of two
+                                       at most 2^31 (larger values: ROCKET_E_INVALID)
                                        (0: automatic, the smallest width giving at most 2^20 micro-chunks) */
     ROCKET_OPT_WORKSPACE_CAP = 11,  /* bytes; workspace growth beyond it fails with ROCKET_E_OOM */
     ROCKET_OPT_AUTOTUNE = 12,       /* 1: rocket_prepare of ragged sets runs the tile-shape autotuner */

@@ -106,29 +106,55 @@ class Context:
         return out
 
     # -- items ----------------------------------------------------------------------------
-    @staticmethod
-    def _items(x, fn: int):
+    def _dev(self, t, name: str, dtype, contiguous: bool = True):
+        """Check that ``t`` can be handed to the C ABI as a device pointer on this context's
+        device: a torch tensor of ``dtype`` on that device (and contiguous when the layout
+        is packed).  Raises before any pointer reaches the library."""
+        if not isinstance(t, torch.Tensor):
+            raise TypeError("%s must be a torch.Tensor, got %s" % (name, type(t).__name__))
+        if t.dtype != dtype:
+            raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+        if not t.is_cuda:
+            raise ValueError("%s must be a device tensor (got one on %s)" % (name, t.device))
+        if t.device.index != self.device:
+            raise ValueError("%s is on %s but the context is on cuda:%d" % (name, t.device, self.device))
+        if contiguous and not t.is_contiguous():
+            raise ValueError("%s must be contiguous" % name)
+        return t
+
+    def _items(self, x, fn: int):
         it = _lib.Items()
         if fn in (_lib.NCC_FP32, _lib.NCC_BF16X3, _lib.NCC_BF16X6, _lib.PCE):
-            assert x.dtype == torch.float32 and x.dim() == 2 and x.stride(1) == 1 and x.is_cuda
+            self._dev(x, "items", torch.float32, contiguous=False)
+            if x.dim() != 2 or (x.shape[0] > 1 and x.stride(1) != 1) or (x.shape[0] > 1 and x.stride(0) < x.shape[1]):
+                raise ValueError("dense items must be a 2-D [n][d] tensor with unit column stride and rows "
+                                 "at least d apart")
             it.dense = x.data_ptr()
             it.dim = x.shape[1]
             it.ld = x.stride(0) if x.shape[0] > 1 else x.shape[1]
             return it, x.shape[0]
         if fn in (_lib.GAUSS_OVERLAP, _lib.GMM_L2, _lib.GMM_BHATTACHARYA):
-            assert isinstance(x, Clouds)
-            assert x.offsets.dtype == torch.int64 and x.xy.dtype == torch.float32 and x.xy.is_cuda
+            if not isinstance(x, Clouds):
+                raise TypeError("point-cloud pair functions take a Clouds set")
+            self._dev(x.offsets, "offsets", torch.int64)
+            self._dev(x.xy, "xy", torch.float32)
             it.offsets = x.offsets.data_ptr()
             it.xy = x.xy.data_ptr()
             it.sigma = float(x.sigma)
             if fn != _lib.GAUSS_OVERLAP and x.point_sigma is not None:
-                ps = x.point_sigma
-                assert ps.dtype == torch.float32 and ps.is_cuda and ps.is_contiguous() and ps.numel() * 2 == x.xy.numel()
+                ps = self._dev(x.point_sigma, "point_sigma", torch.float32)
+                if ps.numel() * 2 != x.xy.numel():
+                    raise ValueError("point_sigma must hold one value per point")
                 it.point_sigma = ps.data_ptr()
             return it, x.n
         if fn == _lib.SPARSE_COSINE:
-            assert isinstance(x, SparseSet)
-            assert x.offsets.dtype == torch.int64 and x.keys.dtype == torch.int64 and x.vals.dtype == torch.float32
+            if not isinstance(x, SparseSet):
+                raise TypeError("sparse_cosine takes a SparseSet")
+            self._dev(x.offsets, "offsets", torch.int64)
+            self._dev(x.keys, "keys", torch.int64)
+            self._dev(x.vals, "vals", torch.float32)
+            if x.keys.numel() != x.vals.numel():
+                raise ValueError("keys and vals must have the same length")
             it.offsets = x.offsets.data_ptr()
             it.keys = x.keys.data_ptr()
             it.vals = x.vals.data_ptr()
@@ -162,7 +188,10 @@ class Context:
         """All pairs of NCC items kept in host memory (float32 [n][d] CPU tensor, ideally
         pinned) through the device cache; ``set(cache_slots=S)`` bounds the cache."""
         code = _lib.FN_BY_NAME[fn]
-        assert not x.is_cuda and x.dtype == torch.float32 and x.dim() == 2 and x.stride(1) == 1
+        if not isinstance(x, torch.Tensor) or x.is_cuda or x.dtype != torch.float32 or x.dim() != 2:
+            raise ValueError("host items must be a float32 [n][d] CPU tensor")
+        if x.shape[0] > 1 and (x.stride(1) != 1 or x.stride(0) < x.shape[1]):
+            raise ValueError("host items need unit column stride and rows at least d apart")
         n, d = x.shape
         ld = x.stride(0) if n > 1 else d
         if out is None:
@@ -176,7 +205,8 @@ class Context:
     def cv_build(self, residues, offsets, K: int = 6):
         """Composition vectors of n species (uint8 residue codes on the device, int64
         offsets [n+1]) as a :class:`SparseSet` ready for ``sparse_cosine``."""
-        assert residues.dtype == torch.uint8 and residues.is_cuda and offsets.dtype == torch.int64
+        self._dev(residues, "residues", torch.uint8)
+        self._dev(offsets, "offsets", torch.int64)
         n = offsets.numel() - 1
         cap = max(int(residues.numel()), 1)
         dev = residues.device
@@ -192,17 +222,31 @@ class Context:
         _lib.check(_lib.load().rocket_autotune(self.handle, _stream()), self.handle)
         return {k: self.get(k) for k in ("ovl_block", "ovl_variant")}
 
-    def overlap_cost_grad(self, clouds: Clouds, centroids, params, with_grad: bool = True):
+    def overlap_cost_grad(self, clouds: Clouds, centroids, params, with_grad: bool = True, reuse: bool = False):
+        """Cost and gradient of every pair's rigid transform ``params`` [P, 3].
+
+        With ``reuse=True`` the library reuses the clouds that the previous call on this
+        context prepared, skipping the size sort and packing, provided ``clouds`` is the
+        same object with the same, unmodified tensors (the context keeps a reference to
+        it); otherwise the clouds are prepared again."""
         n = clouds.n
         P = num_pairs(n)
         it, _ = self._items(clouds, _lib.GAUSS_OVERLAP)
-        assert params.shape == (P, 3) and params.dtype == torch.float32 and params.is_contiguous()
-        assert centroids.shape == (n, 2) and centroids.dtype == torch.float32 and centroids.is_contiguous()
+        self._dev(params, "params", torch.float32)
+        self._dev(centroids, "centroids", torch.float32)
+        if tuple(params.shape) != (P, 3) or tuple(centroids.shape) != (n, 2):
+            raise ValueError("params must be [P, 3] and centroids [n, 2]")
+        # reuse only what this context prepared from these very tensors, unmodified since
+        key = (clouds.offsets.data_ptr(), clouds.offsets._version, clouds.xy.data_ptr(), clouds.xy._version,
+               float(clouds.sigma), n)
+        prev = getattr(self, "_grad_clouds", None)
+        reuse = reuse and prev is not None and prev[0] is clouds and prev[1] == key
         cost = torch.empty(P, dtype=torch.float32, device=params.device)
         grad = torch.empty((P, 3), dtype=torch.float32, device=params.device) if with_grad else None
-        _lib.check(_lib.load().rocket_overlap_cost_grad(self.handle, ctypes.byref(it), n, _ptr(centroids),
-                                                        _ptr(params), _ptr(cost), _ptr(grad), _stream()),
-                   self.handle)
+        _lib.check(_lib.load().rocket_overlap_cost_grad(self.handle, None if reuse else ctypes.byref(it), n,
+                                                        _ptr(centroids), _ptr(params), _ptr(cost), _ptr(grad),
+                                                        _stream()), self.handle)
+        self._grad_clouds = (clouds, key)
         return cost, grad
 
 
@@ -251,16 +295,17 @@ class OverlapCost(torch.autograd.Function):
     """
 
     @staticmethod
-    def forward(ctx_, params, clouds: Clouds, centroids, rctx: Context | None = None):
+    def forward(ctx_, params, clouds: Clouds, centroids, rctx: Context | None = None, reuse: bool = False):
         rc = rctx or default_context()
-        cost, grad = rc.overlap_cost_grad(clouds, centroids, params.detach().contiguous(), with_grad=True)
+        cost, grad = rc.overlap_cost_grad(clouds, centroids, params.detach().contiguous(), with_grad=True,
+                                          reuse=reuse)
         ctx_.save_for_backward(grad)
         return cost
 
     @staticmethod
     def backward(ctx_, g):
         (grad,) = ctx_.saved_tensors
-        return g[:, None] * grad, None, None, None
+        return g[:, None] * grad, None, None, None, None
 
 
 def register(clouds: Clouds, centroids, params0, steps: int = 20, lr: float = 0.01, ctx: Context | None = None,
@@ -277,8 +322,10 @@ def register(clouds: Clouds, centroids, params0, steps: int = 20, lr: float = 0.
     norm = (counts[iu[0]] * counts[iu[1]]).clamp_min(1.0)
     p = params0.detach().clone().contiguous().requires_grad_(True)
     hist = [p.detach().clone()] if record else None
-    for _ in range(steps):
-        cost = OverlapCost.apply(p, clouds, centroids, ctx)
+    rc = ctx or default_context()
+    for step in range(steps):
+        # the clouds do not change during the descent: prepare them once, reuse afterwards
+        cost = OverlapCost.apply(p, clouds, centroids, rc, step > 0)
         energy = -(cost / norm).sum()
         (g,) = torch.autograd.grad(energy, p)
         with torch.no_grad():

@@ -79,6 +79,7 @@ struct OvlState {
     QueueArgs qa{};
     int64_t pc_block = -1, pc_order = -1, pc_seed = -1, pc_ledger = -1;
     bool valid = false;
+    bool grad_ready = false;  // prepared by rocket_overlap_cost_grad (reusable with clouds = NULL)
 };
 
 struct SpState {

@@ -441,6 +441,7 @@ rocket_status ovl_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, in
 {
     OvlState &o = ctx->ovl;
     o.valid = false;
+    o.grad_ready = false;
     if (n > 0 && (!it->offsets || !it->xy)) return fail(ctx, ROCKET_E_INVALID, "offsets or xy is NULL");
     if (mode == MODE_OVERLAP && (!(it->sigma > 0.0) || !std::isfinite(it->sigma)))
         return fail(ctx, ROCKET_E_INVALID, "sigma must be > 0");

@@ -222,6 +222,7 @@ rocket_status rocket_prepare(rocket_ctx *ctx, const rocket_items *items, int64_t
     if (!valid_fn(fn)) return rk::fail(ctx, ROCKET_E_UNSUPPORTED, "unknown pair function");
     hipStream_t s = (hipStream_t)stream;
     ctx->prepared_fn = 0;
+    ctx->ovl.grad_ready = false;
     ctx->stats.cache_slots = 0;
     ctx->stats.cache_loads = 0;
     rocket_status st;
@@ -300,6 +301,7 @@ rocket_status rocket_allpairs_host(rocket_ctx *ctx, const float *host_items, int
     if (fn != ROCKET_NCC_FP32 && fn != ROCKET_NCC_BF16X3 && fn != ROCKET_NCC_BF16X6)
         return rk::fail(ctx, ROCKET_E_UNSUPPORTED, "host-resident items: NCC pair functions only");
     ctx->prepared_fn = 0;  // the plane workspace is reused as the device cache
+    ctx->ovl.grad_ready = false;
     rocket_status st = rk::ncc_allpairs_host(ctx, host_items, n, dim, ld, (int)fn, out, (hipStream_t)stream);
     ctx->stats.n = n;
     ctx->stats.pairs = n > 1 ? n * (n - 1) / 2 : 0;
@@ -320,19 +322,20 @@ rocket_status rocket_overlap_cost_grad(rocket_ctx *ctx, const rocket_items *clou
                                        const float *params, float *out_cost, float *out_grad, void *stream)
 {
     RK_TRY(enter(ctx));
-    if (!clouds) return rk::fail(ctx, ROCKET_E_INVALID, "clouds is NULL");
     if (n < 0) return rk::fail(ctx, ROCKET_E_INVALID, "n < 0");
     const int64_t P = n * (n - 1) / 2;
     if (P > 0 && (!centroids || !params || !out_cost))
         return rk::fail(ctx, ROCKET_E_INVALID, "centroids, params and out_cost are required");
     hipStream_t s = (hipStream_t)stream;
-    const rk::OvlState &o = ctx->ovl;
-    const bool reuse = o.valid && o.mode == 0 && o.n == n && o.offsets == clouds->offsets && o.xy == clouds->xy &&
-                       o.sigma == clouds->sigma;
-    if (!reuse) {
+    rk::OvlState &o = ctx->ovl;
+    if (clouds) {
         ctx->prepared_fn = 0;
         RK_TRY(rk::ovl_prepare(ctx, clouds, n, 0, s));
         ctx->prepared_fn = ROCKET_GAUSS_OVERLAP;
+        o.grad_ready = true;
+    } else if (!(o.valid && o.grad_ready && o.mode == 0 && o.n == n)) {
+        return rk::fail(ctx, ROCKET_E_STATE, "clouds is NULL but no clouds of this size were prepared by the previous "
+                                             "rocket_overlap_cost_grad");
     }
     ctx->stats.n = n;
     ctx->stats.pairs = P;
@@ -357,8 +360,8 @@ rocket_status rocket_set_option(rocket_ctx *ctx, rocket_option opt, int64_t valu
     if (opt == ROCKET_OPT_OVL_BLOCK && value > 64) return rk::fail(ctx, ROCKET_E_INVALID, "overlap block <= 64");
     if (opt == ROCKET_OPT_SP_LANES && value != 0 && value != 4 && value != 8)
         return rk::fail(ctx, ROCKET_E_INVALID, "sparse lanes per column must be 0, 4 or 8");
-    if (opt == ROCKET_OPT_SP_CHUNK && (value & (value - 1)) != 0)
-        return rk::fail(ctx, ROCKET_E_INVALID, "sparse chunk width must be 0 or a power of two");
+    if (opt == ROCKET_OPT_SP_CHUNK && ((value & (value - 1)) != 0 || value > ((int64_t)1 << 31)))
+        return rk::fail(ctx, ROCKET_E_INVALID, "sparse chunk width must be 0 or a power of two up to 2^31");
     ctx->opt[opt] = value;
     return ROCKET_OK;
 }

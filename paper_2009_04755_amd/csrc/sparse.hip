@@ -454,6 +454,8 @@ rocket_status sp_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, hip
     while (((maxkey >> wlog) + 1) > (uint64_t)(1 << 20)) ++wlog;
     while ((uint64_t)nbands * ((maxkey >> wlog) + 1) * 4 > ((uint64_t)4 << 30)) ++wlog;
     while (ctx->opt[ROCKET_OPT_SP_CHUNK] > ((int64_t)1 << wlog)) ++wlog;  // caller's lower bound
+    // keys are u32, so a shift by wlog must stay below 32 (set_option caps the width at 2^31)
+    if (wlog > 31) return fail(ctx, ROCKET_E_INVALID, "sparse micro-chunk width above 2^31");
     const int64_t nmc = (int64_t)(maxkey >> wlog) + 1;
     void *hp = nullptr;
     RK_TRY(ws_get(ctx, WS_SP_CHUNKS, sizeof(unsigned) * (size_t)(nbands * nmc) + sizeof(int) * (nbands + 1), &hp));

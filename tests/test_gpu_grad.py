@@ -125,3 +125,36 @@ def test_registration_20_steps_full_scale_sampled(ctx):
         c = cost[torch.from_numpy(sel).cuda()].cpu().numpy()
         gr = grad[torch.from_numpy(sel).cuda()].cpu().numpy()
         _check_grad(off, xy, cen, pi, pj, ps.cpu().numpy(), c, gr)
+
+
+def test_new_contents_at_same_address_are_prepared_again(ctx):
+    """Clouds overwritten in place (same device addresses, same n) must not reuse the old
+    preparation: the binding re-prepares when a tensor's version changed, and the C entry
+    point only reuses when the caller passes clouds = NULL."""
+    import ctypes
+    import torch
+    from paper_2009_04755_amd import Clouds, Context, _lib
+    announce("grad: in-place change of the clouds at the same address")
+    off, xy, cen, cl, cen_d = _setup(32, 8, nmin=10, nmax=80)
+    off2, xy2 = synth.point_clouds(32, nmin=10, nmax=80, config=3, salt=9)
+    xy2 = xy2[: xy.size] if xy2.size >= xy.size else np.resize(xy2, xy.size)
+    P = 32 * 31 // 2
+    params = torch.from_numpy(synth.rigid_starts(P, config=3, salt=10) * np.float32(0.02)).cuda()
+    c1, g1 = ctx.overlap_cost_grad(cl, cen_d, params)
+    c1r, g1r = ctx.overlap_cost_grad(cl, cen_d, params, reuse=True)  # unchanged: reused
+    assert torch.equal(c1, c1r) and torch.equal(g1, g1r)
+    ptr = cl.xy.data_ptr()
+    cl.xy.copy_(torch.from_numpy(xy2.astype(np.float32)).cuda())
+    assert cl.xy.data_ptr() == ptr
+    c2, g2 = ctx.overlap_cost_grad(cl, cen_d, params, reuse=True)  # version changed: prepared again
+    fresh = Context(0)
+    c3, g3 = fresh.overlap_cost_grad(Clouds(cl.offsets, cl.xy.clone(), SIG), cen_d, params)
+    assert torch.equal(c2, c3) and torch.equal(g2, g3)
+    assert not torch.equal(c1, c2)
+    # the C entry point: clouds = NULL without a matching earlier call is a state error
+    L = _lib.load()
+    st = L.rocket_overlap_cost_grad(fresh.handle, None, 31, ctypes.c_void_p(cen_d.data_ptr()),
+                                    ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(c3.data_ptr()), None, None)
+    assert st == _lib.E_STATE
+    torch.cuda.synchronize()
+    fresh.close()

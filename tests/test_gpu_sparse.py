@@ -149,7 +149,7 @@ def test_device_generator_is_reproducible_across_processes():
 def test_option_validation(ctx):
     from paper_2009_04755_amd._lib import RocketError, E_INVALID
     announce("sparse option validation")
-    for name, bad in (("sp_lanes", 2), ("sp_lanes", 16), ("sp_chunk", 3), ("sp_chunk", 1000)):
+    for name, bad in (("sp_lanes", 2), ("sp_lanes", 16), ("sp_chunk", 3), ("sp_chunk", 1000), ("sp_chunk", 1 << 32), ("sp_chunk", 1 << 40)):
         with pytest.raises(RocketError) as e:
             ctx.set(**{name: bad})
         assert e.value.status == E_INVALID
