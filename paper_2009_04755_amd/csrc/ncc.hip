@@ -630,6 +630,11 @@ int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 int nc_of(int sch) { return sch == SCH_X6 ? 3 : sch == SCH_X3 ? 2 : 1; }
 int es_of(int sch) { return sch == SCH_FP32 ? 4 : 2; }
 
+// Statistics workspace: FP64 means [n], then the f32 inverse norms [n] at the next 256-byte
+// boundary.
+size_t inv_s_offset(int64_t n) { return ((size_t)n * 8 + 255) & ~(size_t)255; }
+size_t stats_bytes(int64_t n) { return inv_s_offset(n) + (size_t)n * 4; }
+
 }  // namespace
 
 static int ncc_tile(rocket_ctx *ctx, int64_t n)
@@ -721,11 +726,11 @@ rocket_status ncc_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, in
     if (n == 0) return ROCKET_OK;
 
     void *stats = nullptr, *planes = nullptr;
-    RK_TRY(ws_get(ctx, WS_NCC_STATS, (size_t)n * 12 + 64, &stats));
+    RK_TRY(ws_get(ctx, WS_NCC_STATS, stats_bytes(n), &stats));
     const int64_t plane_bytes = st.n_pad * st.d_pad * es_of(scheme);
     RK_TRY(ws_get(ctx, WS_NCC_PLANES, (size_t)(plane_bytes * nc_of(scheme)), &planes));
     double *mu = (double *)stats;
-    float *inv_s = (float *)((char *)stats + (((size_t)n * 8 + 255) & ~(size_t)255));
+    float *inv_s = (float *)((char *)stats + inv_s_offset(n));
     hipLaunchKernelGGL(k_ncc_stats, dim3((unsigned)n), dim3(256), 0, s, it->dense, it->ld, it->dim, mu, inv_s);
     RK_HIP(hipGetLastError());
     const dim3 g((unsigned)((st.nkt + 15) / 16), (unsigned)((st.n_pad + 15) / 16));
@@ -813,7 +818,7 @@ rocket_status ncc_compare(rocket_ctx *ctx, float *out, hipStream_t s)
     launch_gram_any(grid, s, planes, st, pc.qa, (float *)partial);
     RK_HIP(hipGetLastError());
     RK_TRY(timing_end(ctx, s));
-    const float *inv_s = (const float *)((char *)ctx->ws[WS_NCC_STATS].ptr + (((size_t)st.n * 8 + 255) & ~(size_t)255));
+    const float *inv_s = (const float *)((char *)ctx->ws[WS_NCC_STATS].ptr + inv_s_offset(st.n));
     launch_finish(s, st, st.tiles, (const float *)partial, (const int2 *)ctx->ws[WS_NCC_TILES].ptr, inv_s, out);
     RK_HIP(hipGetLastError());
     return ROCKET_OK;
@@ -965,7 +970,7 @@ rocket_status ncc_allpairs_host(rocket_ctx *ctx, const float *host, int64_t n, i
     const int64_t stage_bytes = (int64_t)T * ld * 4;
     RK_TRY(ws_get(ctx, WS_NCC_PLANES, (size_t)(S * slot_bytes), &slots));
     RK_TRY(ws_get(ctx, WS_OOC_STAGE, (size_t)(2 * stage_bytes), &stage));
-    RK_TRY(ws_get(ctx, WS_NCC_STATS, (size_t)n * 12 + 64, &stats));
+    RK_TRY(ws_get(ctx, WS_NCC_STATS, stats_bytes(n), &stats));
     int64_t maxb = 0;
     for (const OocBatch &b : batches) maxb = std::max(maxb, b.ntiles);
     RK_TRY(ws_get(ctx, WS_NCC_PARTIAL, (size_t)(maxb * tile_partial), &partial));
@@ -987,7 +992,7 @@ rocket_status ncc_allpairs_host(rocket_ctx *ctx, const float *host, int64_t n, i
         }
     }
     double *mu = (double *)stats;
-    float *inv_s = (float *)((char *)stats + (((size_t)n * 8 + 255) & ~(size_t)255));
+    float *inv_s = (float *)((char *)stats + inv_s_offset(n));
     const dim3 sg((unsigned)((st.nkt + 15) / 16), (unsigned)((T + 15) / 16));
 
     // --- enqueue -------------------------------------------------------------------------
