@@ -46,7 +46,7 @@ def lib():
         L.oracle_ncc_pairs.argtypes = [P, I64, I64, P, P, P, P, I64, P, P]
         L.oracle_overlap_pairs.argtypes = [P, P, D, P, P, I64, P, P]
         L.oracle_overlap_grad_pairs.argtypes = [P, P, P, D, P, P, P, I64, P, P, P, P]
-        L.oracle_sparse_pairs.argtypes = [P, P, P, P, P, I64, P, P, P]
+        L.oracle_sparse_pairs.argtypes = [P, P, P, P, P, I64, P, P, P, P]
         L.oracle_gmm_pairs.argtypes = [P, P, P, ctypes.c_int, P, P, I64, P, P]
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
@@ -144,8 +144,9 @@ def gmm(offsets, xy, sig, pi, pj, mode: str = "l2", with_kappa: bool = False):
     return (cost, kappa) if with_kappa else cost
 
 
-def sparse_cosine(offsets, keys, vals, pi, pj):
-    """(cos f64[np], count int64[np], keysum uint64[np]) for the listed pairs."""
+def sparse_cosine(offsets, keys, vals, pi, pj, with_tau: bool = False):
+    """(cos f64[np], count int64[np], keysum uint64[np]) for the listed pairs; with
+    ``with_tau`` also the error scale tau f64[np] of each cosine."""
     offsets = np.ascontiguousarray(offsets, dtype=np.int64)
     keys = np.ascontiguousarray(keys, dtype=np.int64)
     vals = np.ascontiguousarray(vals, dtype=np.float32)
@@ -153,5 +154,7 @@ def sparse_cosine(offsets, keys, vals, pi, pj):
     cosv = np.empty(pi.size)
     cnt = np.empty(pi.size, dtype=np.int64)
     ks = np.empty(pi.size, dtype=np.uint64)
-    lib().oracle_sparse_pairs(_p(keys), _p(vals), _p(offsets), _p(pi), _p(pj), pi.size, _p(cosv), _p(cnt), _p(ks))
-    return cosv, cnt, ks
+    tau = np.empty(pi.size) if with_tau else None
+    lib().oracle_sparse_pairs(_p(keys), _p(vals), _p(offsets), _p(pi), _p(pj), pi.size, _p(cosv), _p(cnt), _p(ks),
+                              _p(tau))
+    return (cosv, cnt, ks, tau) if with_tau else (cosv, cnt, ks)

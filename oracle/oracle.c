@@ -229,10 +229,15 @@ void oracle_overlap_grad_pairs(const float *xy, const int64_t *off, const float 
  * Sparse cosine.  Each item is a list of strictly ascending int64 keys with f32 values.
  * count = |K_i intersect K_j| by a two-pointer merge; dot = sum over shared keys of
  * v_i * v_j; cos = dot / (|v_i|_2 |v_j|_2) with the norms over all entries of each item;
- * keysum = wrapping 64-bit sum of the shared keys (an exactness witness).
+ * keysum = wrapping 64-bit sum of the shared keys (an exactness witness);
+ * tau = sqrt(sum over shared keys of (v_i v_j)^2) / (|v_i|_2 |v_j|_2), the error scale of
+ * the dot product when every product carries one unit rounding (signed values, such as
+ * background-corrected composition vectors, can cancel to a cosine near 0; for values of
+ * one sign tau <= |cos|).
  * ------------------------------------------------------------------------------------- */
 void oracle_sparse_pairs(const int64_t *keys, const float *vals, const int64_t *off, const int64_t *pi,
-                         const int64_t *pj, int64_t np, double *cosv, int64_t *count, uint64_t *keysum)
+                         const int64_t *pj, int64_t np, double *cosv, int64_t *count, uint64_t *keysum,
+                         double *tau)
 {
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t p = 0; p < np; ++p) {
@@ -241,7 +246,7 @@ void oracle_sparse_pairs(const int64_t *keys, const float *vals, const int64_t *
         double ni = 0.0, nj = 0.0;
         for (int64_t k = a; k < ae; ++k) ni += (double)vals[k] * (double)vals[k];
         for (int64_t k = b; k < be; ++k) nj += (double)vals[k] * (double)vals[k];
-        double dot = 0.0;
+        double dot = 0.0, sq = 0.0;
         int64_t m = 0;
         uint64_t ks = 0;
         while (a < ae && b < be) {
@@ -250,7 +255,9 @@ void oracle_sparse_pairs(const int64_t *keys, const float *vals, const int64_t *
             } else if (keys[b] < keys[a]) {
                 ++b;
             } else {
-                dot += (double)vals[a] * (double)vals[b];
+                const double pr = (double)vals[a] * (double)vals[b];
+                dot += pr;
+                sq += pr * pr;
                 ++m;
                 ks += (uint64_t)keys[a];
                 ++a;
@@ -258,6 +265,7 @@ void oracle_sparse_pairs(const int64_t *keys, const float *vals, const int64_t *
             }
         }
         cosv[p] = dot / (sqrt(ni) * sqrt(nj));
+        if (tau) tau[p] = sqrt(sq) / (sqrt(ni) * sqrt(nj));
         if (count) count[p] = m;
         if (keysum) keysum[p] = ks;
     }

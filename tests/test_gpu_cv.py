@@ -95,9 +95,10 @@ def test_end_to_end_cosine(ctx):
     got, cnt = ctx.allpairs(S, "sparse_cosine", counts=True)
     got, cnt = got.cpu().numpy(), cnt.cpu().numpy()
     pi, pj = oracle.all_pairs(24)
-    ref, rcnt, _ = oracle.sparse_cosine(co, ck, cvv.astype(np.float32), pi, pj)
+    ref, rcnt, _, tau = oracle.sparse_cosine(co, ck, cvv.astype(np.float32), pi, pj, with_tau=True)
     assert np.array_equal(cnt.astype(np.int64), rcnt)
-    assert np.max(np.abs(got - ref) / np.abs(ref)) <= 1e-5
+    # composition vectors are signed: the cosine is a signed sum, held to the floored bar
+    assert np.max(np.abs(got - ref) / np.maximum(np.abs(ref), tau)) <= 1e-5
 
 
 def test_errors(ctx):

@@ -1,7 +1,8 @@
 """GPU parity of the sparse cosine against the FP64 oracle.
 
-Intersection sizes must be bit-exact.  Cosines: all products are positive, so no floor is
-needed: |g - r| <= 1e-5 * r, and a pair with no shared key must give exactly 0.
+Intersection sizes must be bit-exact.  Cosines: |g - r| <= 1e-5 max(|r|, tau), tau the
+oracle's error scale of the dot product; for the non-negative frequencies here tau <= r,
+so this is the plain 1e-5 relative bar.  A pair with no shared key must give exactly 0.
 """
 import numpy as np
 import pytest
@@ -28,14 +29,16 @@ def _dev(off, keys, vals):
 
 
 def _check(got, cnt, off, keys, vals, pi, pj):
-    ref, rcnt, _ = oracle.sparse_cosine(off, keys, vals, pi, pj)
+    ref, rcnt, _, tau = oracle.sparse_cosine(off, keys, vals, pi, pj, with_tau=True)
     assert np.array_equal(cnt.astype(np.int64), rcnt), np.nonzero(cnt != rcnt)[0][:5]
     zero = rcnt == 0
     nanref = np.isnan(ref)
     assert np.all(np.isnan(got[nanref]))
     ok = ~nanref
     assert np.all(got[ok & zero] == 0.0)
-    err = np.abs(got[ok] - ref[ok]) / np.maximum(np.abs(ref[ok]), 1e-300)
+    # floored bar |g - r| <= 1e-5 max(|r|, tau): the plain relative bar for values of one
+    # sign (tau <= |r| there), the dot product's error scale where signed values cancel
+    err = np.abs(got[ok] - ref[ok]) / np.maximum(np.abs(ref[ok]), np.maximum(tau[ok], 1e-300))
     err[zero[ok]] = 0
     assert err.max() <= 1e-5, err.max()
     return err.max()

@@ -49,3 +49,35 @@ def test_symmetry_bounds_and_scale_invariance():
     v3[off[0]:off[1]] *= 4.0  # exact power-of-two scale
     c, _, _ = oracle.sparse_cosine(off, keys, v3, pi, pj)
     assert np.array_equal(c, a)
+
+
+def test_error_scale_special_cases():
+    # one shared key: the cosine is a single product, so tau = |cos|
+    off, keys, vals = _items(([3, 8, 20], [0.5, -0.25, 2.0]), ([8, 9], [-3.0, 1.0]))
+    c, _, _, tau = oracle.sparse_cosine(off, keys, vals, [0], [1], with_tau=True)
+    assert tau[0] == abs(c[0]) and c[0] > 0
+    # m shared keys with equal products: Cauchy-Schwarz holds with equality, tau = cos / sqrt(m)
+    off, keys, vals = _items(([1, 2, 3, 4], [1.0, 2.0, 4.0, 8.0]), ([1, 2, 3, 4], [8.0, 4.0, 2.0, 1.0]))
+    c, _, _, tau = oracle.sparse_cosine(off, keys, vals, [0], [1], with_tau=True)
+    assert abs(tau[0] - c[0] / 2.0) <= 1e-16 and abs(c[0] - 32.0 / 85.0) <= 1e-16
+    # two products of opposite sign cancel: cos = 0 exactly while tau = sqrt(2) p / (|a||b|)
+    off, keys, vals = _items(([5, 7], [1.0, 1.0]), ([5, 7], [0.5, -0.5]))
+    c, _, _, tau = oracle.sparse_cosine(off, keys, vals, [0], [1], with_tau=True)
+    assert c[0] == 0.0 and abs(tau[0] - np.sqrt(2) * 0.5 / (np.sqrt(2) * np.sqrt(0.5))) <= 1e-16
+    # disjoint items: no products, tau = 0
+    off, keys, vals = _items(([1], [1.0]), ([2], [1.0]))
+    _, _, _, tau = oracle.sparse_cosine(off, keys, vals, [0], [1], with_tau=True)
+    assert tau[0] == 0.0
+
+
+def test_error_scale_bounds_for_one_sign():
+    # for non-negative values tau lies in [cos / sqrt(m), cos]; a missed square root, a
+    # dropped norm or a sum of |products| breaks one of the bounds on these inputs
+    off, keys, vals = synth.sparse_vectors(8, key_space=4000, nnz_mean=500, nnz_min=20, nnz_max=1500, config=4, salt=3)
+    pi, pj = oracle.all_pairs(8)
+    c, m, _, tau = oracle.sparse_cosine(off, keys, vals, pi, pj, with_tau=True)
+    ok = m > 1
+    assert ok.sum() > 10
+    assert np.all(tau[ok] <= c[ok] * (1 + 1e-12))
+    assert np.all(tau[ok] >= c[ok] / np.sqrt(m[ok]) * (1 - 1e-12))
+    assert np.all(tau[ok] < c[ok] * 0.999)  # strictly inside: more than one product contributes
