@@ -177,6 +177,23 @@ rocket_status rocket_allpairs_ex(rocket_ctx *ctx, const rocket_items *items, int
  * before returning.  out: float32 [n(n-1)/2]. */
 rocket_status rocket_allpairs(const rocket_items *items, int64_t n, rocket_pair_fn fn, float *out_upper_triangle);
 
+/* Allocation-free all pairs, for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc).  Same items, pair
+ * functions, outputs, stream semantics and results as rocket_allpairs_ex on a context with
+ * default options, on the CURRENT device, but every workspace buffer (prepared item copies,
+ * split-K partials, work queue, flags) is carved from one static device array of
+ * ROCKET_NOALLOC_SCRATCH_BYTES per device, held until the process ends; the library then
+ * calls no hipMalloc or hipFree.  The caller still passes (and owns) inputs and outputs.
+ * A problem whose workspace does not fit fails with ROCKET_E_OOM and a message giving the
+ * sizes (rocket_last_error(NULL)); `out` is then not written.  As in rocket_prepare, the
+ * ragged and sparse functions read offsets to the host and synchronise during the call.
+ * Every call on one device shares that device's array and the next call overwrites it:
+ * calls whose work overlaps on one device (other streams, other host threads while work
+ * is still in flight) race; host calls themselves are serialised per device. */
+#define ROCKET_NOALLOC_SCRATCH_BYTES ((int64_t)64 << 20)
+rocket_status rocket_allpairs_noalloc(const rocket_items *items, int64_t n, rocket_pair_fn fn, float *out,
+                                      uint32_t *out_counts, void *stream);
+
 /* Composition vectors (the GPU pre-process stage of Section V-B's application): for each
  * species, the K-string composition vector of Qi, Wang and Hao over its proteins,
  *     f(s) = n(s) / N_K,  f0(s) = f(s_1..s_{K-1}) f(s_2..s_K) / f(s_2..s_{K-1}),

@@ -8,5 +8,5 @@ done by hand-written HIP kernels behind the C ABI in ``include/rocket.h``; this
 package is a thin ctypes binding (``api``) plus seeded input generators
 (``synth``).
 """
-from .api import (Clouds, Context, OverlapCost, SparseSet, allpairs, default_context, num_pairs,  # noqa: F401
-                  pair_index, plan_tiles, register)
+from .api import (Clouds, Context, OverlapCost, SparseSet, allpairs, allpairs_noalloc, default_context,  # noqa: F401
+                  num_pairs, pair_index, plan_tiles, register)

@@ -29,7 +29,8 @@ SYMBOLS = ["rocket_create", "rocket_destroy", "rocket_status_str", "rocket_last_
            "rocket_compare", "rocket_allpairs_ex", "rocket_allpairs", "rocket_allpairs_host", "rocket_cv_build",
            "rocket_overlap_cost_grad",
            "rocket_set_option", "rocket_get_option", "rocket_get_stats", "rocket_get_ledger", "rocket_autotune",
-           "rocket_plan_tiles", "rocket_pair_index"]
+           "rocket_plan_tiles", "rocket_pair_index", "rocket_allpairs_noalloc"]
+NOALLOC_SCRATCH_BYTES = 64 << 20  # ROCKET_NOALLOC_SCRATCH_BYTES
 
 
 class Items(ctypes.Structure):
@@ -81,6 +82,8 @@ def load():
     L.rocket_allpairs_ex.restype = I32
     L.rocket_allpairs.argtypes = [IT, I64, I32, P]
     L.rocket_allpairs.restype = I32
+    L.rocket_allpairs_noalloc.argtypes = [IT, I64, I32, P, P, P]
+    L.rocket_allpairs_noalloc.restype = I32
     L.rocket_allpairs_host.argtypes = [P, P, I64, I64, I64, I32, P, P]
     L.rocket_allpairs_host.restype = I32
     L.rocket_cv_build.argtypes = [P, P, P, I64, I32, P, P, P, I64, P]

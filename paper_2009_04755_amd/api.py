@@ -56,6 +56,64 @@ class SparseSet:
         return self.offsets.numel() - 1
 
 
+def _check_dev(t, name: str, dtype, device: int, contiguous: bool = True):
+    """Check that ``t`` can be handed to the C ABI as a device pointer on ``device``: a
+    torch tensor of ``dtype`` on that device (and contiguous when the layout is packed).
+    Raises before any pointer reaches the library."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor, got %s" % (name, type(t).__name__))
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor (got one on %s)" % (name, t.device))
+    if t.device.index != device:
+        raise ValueError("%s is on %s but the context is on cuda:%d" % (name, t.device, device))
+    if contiguous and not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t
+
+
+def _items_struct(x, fn: int, device: int):
+    """The rocket_items struct for ``x`` and its item count, after checking every tensor."""
+    it = _lib.Items()
+    if fn in (_lib.NCC_FP32, _lib.NCC_BF16X3, _lib.NCC_BF16X6, _lib.PCE):
+        _check_dev(x, "items", torch.float32, device, contiguous=False)
+        if x.dim() != 2 or (x.shape[0] > 1 and x.stride(1) != 1) or (x.shape[0] > 1 and x.stride(0) < x.shape[1]):
+            raise ValueError("dense items must be a 2-D [n][d] tensor with unit column stride and rows "
+                             "at least d apart")
+        it.dense = x.data_ptr()
+        it.dim = x.shape[1]
+        it.ld = x.stride(0) if x.shape[0] > 1 else x.shape[1]
+        return it, x.shape[0]
+    if fn in (_lib.GAUSS_OVERLAP, _lib.GMM_L2, _lib.GMM_BHATTACHARYA):
+        if not isinstance(x, Clouds):
+            raise TypeError("point-cloud pair functions take a Clouds set")
+        _check_dev(x.offsets, "offsets", torch.int64, device)
+        _check_dev(x.xy, "xy", torch.float32, device)
+        it.offsets = x.offsets.data_ptr()
+        it.xy = x.xy.data_ptr()
+        it.sigma = float(x.sigma)
+        if fn != _lib.GAUSS_OVERLAP and x.point_sigma is not None:
+            ps = _check_dev(x.point_sigma, "point_sigma", torch.float32, device)
+            if ps.numel() * 2 != x.xy.numel():
+                raise ValueError("point_sigma must hold one value per point")
+            it.point_sigma = ps.data_ptr()
+        return it, x.n
+    if fn == _lib.SPARSE_COSINE:
+        if not isinstance(x, SparseSet):
+            raise TypeError("sparse_cosine takes a SparseSet")
+        _check_dev(x.offsets, "offsets", torch.int64, device)
+        _check_dev(x.keys, "keys", torch.int64, device)
+        _check_dev(x.vals, "vals", torch.float32, device)
+        if x.keys.numel() != x.vals.numel():
+            raise ValueError("keys and vals must have the same length")
+        it.offsets = x.offsets.data_ptr()
+        it.keys = x.keys.data_ptr()
+        it.vals = x.vals.data_ptr()
+        return it, x.n
+    raise ValueError(fn)
+
+
 class Context:
     """One ``rocket_ctx``: workspace, plan cache and options on one device."""
 
@@ -107,59 +165,10 @@ class Context:
 
     # -- items ----------------------------------------------------------------------------
     def _dev(self, t, name: str, dtype, contiguous: bool = True):
-        """Check that ``t`` can be handed to the C ABI as a device pointer on this context's
-        device: a torch tensor of ``dtype`` on that device (and contiguous when the layout
-        is packed).  Raises before any pointer reaches the library."""
-        if not isinstance(t, torch.Tensor):
-            raise TypeError("%s must be a torch.Tensor, got %s" % (name, type(t).__name__))
-        if t.dtype != dtype:
-            raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
-        if not t.is_cuda:
-            raise ValueError("%s must be a device tensor (got one on %s)" % (name, t.device))
-        if t.device.index != self.device:
-            raise ValueError("%s is on %s but the context is on cuda:%d" % (name, t.device, self.device))
-        if contiguous and not t.is_contiguous():
-            raise ValueError("%s must be contiguous" % name)
-        return t
+        return _check_dev(t, name, dtype, self.device, contiguous)
 
     def _items(self, x, fn: int):
-        it = _lib.Items()
-        if fn in (_lib.NCC_FP32, _lib.NCC_BF16X3, _lib.NCC_BF16X6, _lib.PCE):
-            self._dev(x, "items", torch.float32, contiguous=False)
-            if x.dim() != 2 or (x.shape[0] > 1 and x.stride(1) != 1) or (x.shape[0] > 1 and x.stride(0) < x.shape[1]):
-                raise ValueError("dense items must be a 2-D [n][d] tensor with unit column stride and rows "
-                                 "at least d apart")
-            it.dense = x.data_ptr()
-            it.dim = x.shape[1]
-            it.ld = x.stride(0) if x.shape[0] > 1 else x.shape[1]
-            return it, x.shape[0]
-        if fn in (_lib.GAUSS_OVERLAP, _lib.GMM_L2, _lib.GMM_BHATTACHARYA):
-            if not isinstance(x, Clouds):
-                raise TypeError("point-cloud pair functions take a Clouds set")
-            self._dev(x.offsets, "offsets", torch.int64)
-            self._dev(x.xy, "xy", torch.float32)
-            it.offsets = x.offsets.data_ptr()
-            it.xy = x.xy.data_ptr()
-            it.sigma = float(x.sigma)
-            if fn != _lib.GAUSS_OVERLAP and x.point_sigma is not None:
-                ps = self._dev(x.point_sigma, "point_sigma", torch.float32)
-                if ps.numel() * 2 != x.xy.numel():
-                    raise ValueError("point_sigma must hold one value per point")
-                it.point_sigma = ps.data_ptr()
-            return it, x.n
-        if fn == _lib.SPARSE_COSINE:
-            if not isinstance(x, SparseSet):
-                raise TypeError("sparse_cosine takes a SparseSet")
-            self._dev(x.offsets, "offsets", torch.int64)
-            self._dev(x.keys, "keys", torch.int64)
-            self._dev(x.vals, "vals", torch.float32)
-            if x.keys.numel() != x.vals.numel():
-                raise ValueError("keys and vals must have the same length")
-            it.offsets = x.offsets.data_ptr()
-            it.keys = x.keys.data_ptr()
-            it.vals = x.vals.data_ptr()
-            return it, x.n
-        raise ValueError(fn)
+        return _items_struct(x, fn, self.device)
 
     def prepare(self, x, fn: str):
         code = _lib.FN_BY_NAME[fn]
@@ -269,6 +278,27 @@ def allpairs(x, fn: str, counts: bool = False, ctx: Context | None = None):
     intersection sizes).
     """
     return (ctx or default_context()).allpairs(x, fn, counts=counts)
+
+
+def allpairs_noalloc(x, fn: str, out, counts=None):
+    """All pairs like :func:`allpairs`, through ``rocket_allpairs_noalloc``: the library
+    takes every workspace buffer from its static per-device scratch array and allocates
+    nothing.  The caller passes the outputs: ``out`` float32 [P] (and for
+    ``sparse_cosine`` or ``pce`` optionally ``counts`` int32 [P]) on the current device.
+    Problems whose workspace exceeds the scratch array raise :class:`RocketError`."""
+    code = _lib.FN_BY_NAME[fn]
+    dev = torch.cuda.current_device()
+    it, n = _items_struct(x, code, dev)
+    P = num_pairs(n)
+    _check_dev(out, "out", torch.float32, dev)
+    if out.numel() < P:
+        raise ValueError("out must hold n(n-1)/2 = %d values" % P)
+    if counts is not None:
+        _check_dev(counts, "counts", torch.int32, dev)
+        if counts.numel() < P:
+            raise ValueError("counts must hold n(n-1)/2 = %d values" % P)
+    _lib.check(_lib.load().rocket_allpairs_noalloc(ctypes.byref(it), n, code, _ptr(out), _ptr(counts), _stream()))
+    return out
 
 
 def plan_tiles(n: int, T: int):

@@ -145,6 +145,10 @@ struct rocket_ctx {
     // host staging for queue uploads (kept to avoid re-allocation)
     std::vector<int4> h_items;
     std::vector<int> h_seg;
+    // Arena mode (allocation-free entry point): when `arena` is set, workspace slots are
+    // carved from [arena, arena + arena_cap) in call order instead of being allocated.
+    char *arena = nullptr;
+    size_t arena_cap = 0, arena_used = 0;
 };
 
 namespace rk {

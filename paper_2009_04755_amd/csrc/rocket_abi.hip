@@ -49,6 +49,26 @@ rocket_status ws_get(rocket_ctx *ctx, Slot slot, size_t bytes, void **out)
 {
     Buffer &b = ctx->ws[slot];
     if (bytes == 0) bytes = 256;
+    if (ctx->arena) {
+        // carve from the caller-provided arena: 256-byte aligned pieces in call order; a
+        // slot that grows gets a new piece (its old contents are not kept, as with hipMalloc)
+        if (b.bytes < bytes) {
+            const size_t want = (bytes + 255) & ~(size_t)255;
+            if (want > ctx->arena_cap - ctx->arena_used) {
+                char buf[256];
+                snprintf(buf, sizeof buf,
+                         "the allocation-free entry point's scratch holds %zu bytes; this problem needs more "
+                         "(%zu in use, %zu more requested)",
+                         ctx->arena_cap, ctx->arena_used, want);
+                return fail(ctx, ROCKET_E_OOM, buf);
+            }
+            b.ptr = ctx->arena + ctx->arena_used;
+            b.bytes = want;
+            ctx->arena_used += want;
+        }
+        *out = b.ptr;
+        return ROCKET_OK;
+    }
     if (b.bytes < bytes) {
         const size_t want = (bytes + (2u << 20) - 1) & ~(size_t)((2u << 20) - 1);
         const int64_t cap = ctx->opt[ROCKET_OPT_WORKSPACE_CAP];
@@ -191,7 +211,7 @@ void rocket_destroy(rocket_ctx *ctx)
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     for (auto &b : ctx->ws)
-        if (b.ptr) (void)hipFree(b.ptr);
+        if (b.ptr && !ctx->arena) (void)hipFree(b.ptr);
     if (ctx->ev_begin) (void)hipEventDestroy(ctx->ev_begin);
     if (ctx->ev_end) (void)hipEventDestroy(ctx->ev_end);
     rk::OocState &oc = ctx->ooc;
