@@ -264,7 +264,11 @@ typedef enum {
     ROCKET_OPT_SP_CHUNK = 10,       /* sparse: least micro-chunk width of the key-range cut, a power of two
                                        at most 2^31 (larger values: ROCKET_E_INVALID)
                                        (0: automatic, the smallest width giving at most 2^20 micro-chunks) */
-    ROCKET_OPT_WORKSPACE_CAP = 11,  /* bytes; workspace growth beyond it fails with ROCKET_E_OOM */
+    ROCKET_OPT_WORKSPACE_CAP = 11,  /* bytes; workspace growth beyond it fails with ROCKET_E_OOM.  The NCC
+                                     * compare fits its split-K partials (K chunks x tile^2 floats per tile)
+                                     * under it, or without a cap into half of the free device memory, by
+                                     * running the leaf tiles in batches of one Gram launch + epilogue each
+                                     * (same output bit for bit); E_OOM if one tile's partials do not fit */
     ROCKET_OPT_AUTOTUNE = 12,       /* 1: rocket_prepare of ragged sets runs the tile-shape autotuner */
     ROCKET_OPT_TIMING = 13,         /* 1: bracket each compare's main persistent kernel with HIP events on the
                                        launch stream; rocket_get_stats reports its duration (for

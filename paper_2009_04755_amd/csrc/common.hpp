@@ -60,8 +60,10 @@ struct NccState {
     int64_t tiles = 0, items = 0;
     const float *src = nullptr;
     int scheme = 0;
-    // plan cache: the uploaded queue matches these parameters
+    // plan cache: the uploaded queue matches these parameters (unless a batched compare
+    // has since replaced it with per-batch queues)
     QueueArgs qa{};
+    bool queue_batched = false;
     int64_t pc_n = -1, pc_tile = -1, pc_nchunks = -1, pc_order = -1, pc_seed = -1, pc_ledger = -1;
     std::vector<int2> h_tiles;
 };

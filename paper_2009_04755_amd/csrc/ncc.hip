@@ -665,6 +665,60 @@ static int64_t ncc_kchunk(rocket_ctx *ctx, int64_t d_pad, int64_t tiles)
     return std::min<int64_t>(kc, d_pad);
 }
 
+// Upload the work queue of the whole leaf list (every tile x K chunk, chunk-major in per-XCD
+// segments, or reordered by ROCKET_OPT_QUEUE_ORDER) and the tile list of the epilogue.
+static rocket_status ncc_upload_plan(rocket_ctx *ctx, hipStream_t s)
+{
+    NccState &pc = ctx->ncc;
+    const int64_t order = ctx->opt[ROCKET_OPT_QUEUE_ORDER], seed = ctx->opt[ROCKET_OPT_SEED],
+                  ledger = ctx->opt[ROCKET_OPT_LEDGER];
+    plan_chunked(pc.h_tiles, pc.nchunks, MAX_SEG, ctx->h_items, ctx->h_seg, 1);
+    if (order == 1) shuffle_items(ctx->h_items, ctx->h_seg, (uint64_t)seed);
+    if (order == 2) single_segment(ctx->h_seg, (int64_t)ctx->h_items.size());
+    RK_TRY(upload_queue(ctx, s, &pc.qa));
+    void *tl = nullptr;
+    RK_TRY(ws_get(ctx, WS_NCC_TILES, sizeof(int2) * pc.h_tiles.size(), &tl));
+    RK_HIP(hipMemcpyAsync(tl, pc.h_tiles.data(), sizeof(int2) * pc.h_tiles.size(), hipMemcpyHostToDevice, s));
+    RK_HIP(hipStreamSynchronize(s));
+    ctx->queue_owner = QOWN_NCC;
+    pc.queue_batched = false;
+    pc.pc_nchunks = pc.nchunks;
+    pc.pc_order = order;
+    pc.pc_seed = seed;
+    pc.pc_ledger = ledger;
+    return ROCKET_OK;
+}
+
+// Tiles per Gram launch so that the split-K partials (nchunks x T^2 floats per tile) fit the
+// workspace: within ROCKET_OPT_WORKSPACE_CAP next to everything else the context holds, in
+// the allocation-free arena what is left of it, otherwise half of the free device memory.
+// All tiles (one launch) when they fit; 0 when not even one tile does.
+static int64_t ncc_batch_tiles(rocket_ctx *ctx, const NccState &st)
+{
+    const int64_t tile_partial = (int64_t)st.nchunks * st.tile * st.tile * 4;
+    const int64_t full = st.tiles * tile_partial;
+    const int64_t cur = (int64_t)ctx->ws[WS_NCC_PARTIAL].bytes;
+    const int64_t cap = ctx->opt[ROCKET_OPT_WORKSPACE_CAP];
+    int64_t budget;
+    if (ctx->arena) {
+        budget = (int64_t)(ctx->arena_cap - ctx->arena_used) - (64 << 10);  // room for the batch segment table
+    } else if (cap > 0) {
+        // everything else the context holds, and up to 2 MiB of rounding for the partials
+        // and 2 MiB for the batch segment table
+        budget = cap - (ws_total(ctx) - cur) - ((int64_t)4 << 20);
+    } else {
+        if (cur >= full) return st.tiles;
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+            (void)hipGetLastError();
+            return st.tiles;
+        }
+        budget = ((int64_t)fr + cur) / 2;
+    }
+    if (full <= budget) return st.tiles;
+    return std::max<int64_t>(0, budget / tile_partial);
+}
+
 rocket_status ncc_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, int scheme, hipStream_t s)
 {
     if (n > 0 && !it->dense) return fail(ctx, ROCKET_E_INVALID, "dense is NULL");
@@ -708,21 +762,8 @@ rocket_status ncc_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, in
     const int64_t order = ctx->opt[ROCKET_OPT_QUEUE_ORDER], seed = ctx->opt[ROCKET_OPT_SEED],
                   ledger = ctx->opt[ROCKET_OPT_LEDGER];
     if (st.tiles > 0 &&
-        (pc.pc_nchunks != st.nchunks || pc.pc_order != order || pc.pc_seed != seed || pc.pc_ledger != ledger)) {
-        plan_chunked(pc.h_tiles, st.nchunks, MAX_SEG, ctx->h_items, ctx->h_seg, halves);
-        if (order == 1) shuffle_items(ctx->h_items, ctx->h_seg, (uint64_t)seed);
-        if (order == 2) single_segment(ctx->h_seg, (int64_t)ctx->h_items.size());
-        RK_TRY(upload_queue(ctx, s, &pc.qa));
-        void *tl = nullptr;
-        RK_TRY(ws_get(ctx, WS_NCC_TILES, sizeof(int2) * pc.h_tiles.size(), &tl));
-        RK_HIP(hipMemcpyAsync(tl, pc.h_tiles.data(), sizeof(int2) * pc.h_tiles.size(), hipMemcpyHostToDevice, s));
-        RK_HIP(hipStreamSynchronize(s));
-        ctx->queue_owner = QOWN_NCC;
-        pc.pc_nchunks = st.nchunks;
-        pc.pc_order = order;
-        pc.pc_seed = seed;
-        pc.pc_ledger = ledger;
-    }
+        (pc.pc_nchunks != st.nchunks || pc.pc_order != order || pc.pc_seed != seed || pc.pc_ledger != ledger))
+        RK_TRY(ncc_upload_plan(ctx, s));
     if (n == 0) return ROCKET_OK;
 
     void *stats = nullptr, *planes = nullptr;
@@ -802,25 +843,84 @@ static void launch_finish(hipStream_t s, const NccState &st, int64_t ntiles, con
 
 rocket_status ncc_compare(rocket_ctx *ctx, float *out, hipStream_t s)
 {
-    const NccState &st = ctx->ncc;
+    NccState &st = ctx->ncc;
     if (st.n < 2 || st.tiles == 0) return ROCKET_OK;
     if (ctx->queue_owner != QOWN_NCC) return fail(ctx, ROCKET_E_STATE, "queue was replanned by another prepare");
-    const NccState &pc = st;
     const int bm = st.tile;
-    void *partial = nullptr;
-    const int bn = bm;
-    RK_TRY(ws_get(ctx, WS_NCC_PARTIAL, (size_t)(st.items * bm * bn * 4), &partial));
-    RK_TRY(reset_queue(ctx, s, pc.qa));
-    const int grid = auto_grid(ctx, gram_kernel(bm, st.scheme, st.waves), 64 * st.waves, 0, st.items);
-    ctx->stats.grid = grid;
+    const int64_t tile_partial = (int64_t)st.nchunks * bm * bm * 4;
+    const int64_t tb = ncc_batch_tiles(ctx, st);
+    if (tb < 1) return fail(ctx, ROCKET_E_OOM, "workspace cap leaves no room for one tile's split-K partials");
     const char *planes = (const char *)ctx->ws[WS_NCC_PLANES].ptr;
-    RK_TRY(timing_begin(ctx, s));
-    launch_gram_any(grid, s, planes, st, pc.qa, (float *)partial);
-    RK_HIP(hipGetLastError());
-    RK_TRY(timing_end(ctx, s));
     const float *inv_s = (const float *)((char *)ctx->ws[WS_NCC_STATS].ptr + inv_s_offset(st.n));
-    launch_finish(s, st, st.tiles, (const float *)partial, (const int2 *)ctx->ws[WS_NCC_TILES].ptr, inv_s, out);
-    RK_HIP(hipGetLastError());
+    const int2 *tiles = (const int2 *)ctx->ws[WS_NCC_TILES].ptr;
+    void *partial = nullptr;
+    if (tb >= st.tiles) {
+        // one launch over every tile
+        if (st.queue_batched) RK_TRY(ncc_upload_plan(ctx, s));
+        RK_TRY(ws_get(ctx, WS_NCC_PARTIAL, (size_t)(st.tiles * tile_partial), &partial));
+        RK_TRY(reset_queue(ctx, s, st.qa));
+        const int grid = auto_grid(ctx, gram_kernel(bm, st.scheme, st.waves), 64 * st.waves, 0, st.items);
+        ctx->stats.grid = grid;
+        RK_TRY(timing_begin(ctx, s));
+        launch_gram_any(grid, s, planes, st, st.qa, (float *)partial);
+        RK_HIP(hipGetLastError());
+        RK_TRY(timing_end(ctx, s));
+        launch_finish(s, st, st.tiles, (const float *)partial, tiles, inv_s, out);
+        RK_HIP(hipGetLastError());
+        return ROCKET_OK;
+    }
+    // Batches of tb consecutive leaves (D&C order), each one Gram launch over its tiles' K
+    // chunks (chunk-major in per-XCD segments, work items naming the tile's slot in the
+    // batch) plus the epilogue, so the partials of one batch are all that is held.  Every
+    // (tile, chunk) item and the epilogue's summation order are those of the single launch,
+    // so the output is the same bit for bit.  The queue order options apply to single
+    // launches only.
+    RK_TRY(ws_get(ctx, WS_NCC_PARTIAL, (size_t)(tb * tile_partial), &partial));
+    std::vector<int4> all_items, bi;
+    std::vector<int> all_segs, bs;
+    std::vector<int64_t> item0;
+    all_items.reserve((size_t)st.items);
+    for (int64_t t0 = 0; t0 < st.tiles; t0 += tb) {
+        const std::vector<int2> sub(st.h_tiles.begin() + t0, st.h_tiles.begin() + std::min<int64_t>(st.tiles, t0 + tb));
+        plan_chunked(sub, st.nchunks, MAX_SEG, bi, bs, 1);
+        item0.push_back((int64_t)all_items.size());  // segment bounds stay relative to this
+        all_items.insert(all_items.end(), bi.begin(), bi.end());
+        all_segs.insert(all_segs.end(), bs.begin(), bs.end());
+    }
+    void *items = nullptr, *segs = nullptr;
+    RK_TRY(ws_get(ctx, WS_QUEUE_ITEMS, sizeof(int4) * all_items.size(), &items));
+    RK_TRY(ws_get(ctx, WS_QUEUE_SEGS, sizeof(int) * all_segs.size(), &segs));
+    RK_HIP(hipMemcpyAsync(items, all_items.data(), sizeof(int4) * all_items.size(), hipMemcpyHostToDevice, s));
+    RK_HIP(hipMemcpyAsync(segs, all_segs.data(), sizeof(int) * all_segs.size(), hipMemcpyHostToDevice, s));
+    RK_HIP(hipStreamSynchronize(s));  // the host vectors are local
+    st.queue_batched = true;          // the device queue no longer holds the prepared plan
+    QueueArgs qa = st.qa;
+    qa.items = (const int4 *)items;
+    qa.seg = (const int *)segs;
+    qa.nseg = MAX_SEG;
+    RK_TRY(reset_queue(ctx, s, qa));  // heads, and the ledger of every item once
+    int *ledger = qa.ledger;
+    RK_TRY(timing_begin(ctx, s));
+    for (size_t b = 0; b < item0.size(); ++b) {
+        const int64_t t0 = (int64_t)b * tb, nt = std::min<int64_t>(tb, st.tiles - t0);
+        const int64_t nit = (b + 1 < item0.size() ? item0[b + 1] : (int64_t)all_items.size()) - item0[b];
+        QueueArgs qb = qa;
+        qb.items = (const int4 *)items + item0[b];
+        qb.seg = (const int *)segs + b * (MAX_SEG + 1);
+        qb.ledger = ledger ? ledger + item0[b] : nullptr;
+        if (b > 0) {
+            QueueArgs qh = qb;
+            qh.ledger = nullptr;  // heads only: the ledger was cleared once for all batches
+            RK_TRY(reset_queue(ctx, s, qh));
+        }
+        const int grid = auto_grid(ctx, gram_kernel(bm, st.scheme, st.waves), 64 * st.waves, 0, nit);
+        ctx->stats.grid = grid;
+        launch_gram_any(grid, s, planes, st, qb, (float *)partial);
+        RK_HIP(hipGetLastError());
+        launch_finish(s, st, nt, (const float *)partial, tiles + t0, inv_s, out);
+        RK_HIP(hipGetLastError());
+    }
+    RK_TRY(timing_end(ctx, s));
     return ROCKET_OK;
 }
 
