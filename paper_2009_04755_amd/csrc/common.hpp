@@ -30,7 +30,8 @@ enum Slot {
     WS_SP_META,          // flags, inverse norms, sorted order
     WS_SP_CHUNKS,        // band histogram over key micro-chunks + chunk counts
     WS_SP_CSHIFT,        // per band start of its chunk boundaries
-    WS_SP_BOUNDS,        // chunk boundaries (micro-chunk indices)
+    WS_SP_BOUNDS,        // chunk boundaries (units of 2^ulog keys)
+    WS_SP_FINE,          // 64-key counts of micro-chunks that overflow a band's chunk
     WS_PCE_SPEC,         // PCE item spectra (complex f32, natural order)
     WS_CV_K,             // dense K-string counts of a group of species (kept zeroed between calls)
     WS_CV_AUX,           // (K-1)- and (K-2)-string counts, chunk occupancy, totals
@@ -89,7 +90,7 @@ struct SpState {
     const int64_t *offsets = nullptr;
     const int64_t *keys = nullptr;
     const float *vals = nullptr;
-    int wlog = 0, lpc = 8;
+    int wlog = 0, ulog = 0, lpc = 8;
     int64_t tiles = 0, nchunks_total = 0;
     std::vector<int64_t> h_offsets;
     std::vector<int> perm;

@@ -9,7 +9,8 @@
 // row items) x (block of CB = 1024 / LPC sorted column items, LPC = 4 or 8 lanes per column).
 // The key space is cut, per band, into
 // chunks holding at most UMAX row entries (counted on a histogram of the band's keys over
-// fixed-width micro-chunks).  For every chunk the workgroup builds in LDS a hash table of the
+// fixed-width micro-chunks; a micro-chunk wider than 64 keys that alone holds more than UMAX
+// of a band's entries is counted again in 64-key ranges and that band is cut on the host).  For every chunk the workgroup builds in LDS a hash table of the
 // band's keys whose slots carry the 16 row values (zero when absent) and 16 presence bytes;
 // then each column streams its keys of that chunk (LPC lanes per column, coalesced), probes
 // the table and accumulates 16 dot products and 16 counts in registers.  Keys match by
@@ -33,6 +34,12 @@ constexpr int SR = 4;           // column entries per lane per streaming pass
 constexpr int HBITS = 12;
 constexpr int HSIZE = 1 << HBITS;
 constexpr uint32_t EMPTY = 0xFFFFFFFFu;
+// Chunk bounds are kept in units of 2^ulog keys, ulog = min(wlog, FINE_LOG): a range of 64
+// keys holds at most 16 x 64 = 1024 entries of a band (keys are unique per item), less than
+// UMAX, so a micro-chunk wider than 64 keys that holds more than UMAX entries of a band can
+// always be cut at 64-key granularity.
+constexpr int FINE_LOG = 6;
+constexpr int OVF_MAX = 1 << 16;  // overflowing (band, micro-chunk) pairs handled per prepare
 
 enum { FLAG_UNSORTED = 1, FLAG_RANGE = 2, FLAG_OVERFLOW = 4 };
 
@@ -92,11 +99,18 @@ __global__ __launch_bounds__(256) void k_sp_hist(const uint32_t *__restrict__ k3
 // pass 1 writes their starting micro-chunk.  One workgroup per band stages the counts in
 // LDS; one wave runs the greedy scan 64 counts at a time: a prefix sum over the lanes finds
 // the next overflowing lane with one ballot, so a window costs one step plus one per cut.
-__global__ __launch_bounds__(256) void k_sp_cut(const unsigned *__restrict__ hist, int64_t nmc, int pass,
+// Pass 0 also appends every (band, micro-chunk) holding more than UMAX entries of the band
+// to `ovf` (count in ovf_n); those bands are cut on the host at 64-key granularity, and pass
+// 1 skips them (host_cut[band] != 0).  Bounds are written in units of 2^shift micro-chunk
+// widths' fractions: micro-chunk m starts at unit m << shift.
+__global__ __launch_bounds__(256) void k_sp_cut(const unsigned *__restrict__ hist, int64_t nmc, int pass, int shift,
                                                 int *__restrict__ nchunks, const int64_t *__restrict__ cstart,
-                                                int *__restrict__ bounds, unsigned *__restrict__ flags)
+                                                int *__restrict__ bounds, unsigned *__restrict__ flags,
+                                                int2 *__restrict__ ovf, unsigned *__restrict__ ovf_n,
+                                                const int *__restrict__ host_cut)
 {
     const int band = blockIdx.x;
+    if (pass && host_cut && host_cut[band]) return;
     const unsigned *h = hist + (int64_t)band * nmc;
     __shared__ unsigned buf[4096];
     const int lane = threadIdx.x & 63;
@@ -112,6 +126,10 @@ __global__ __launch_bounds__(256) void k_sp_cut(const unsigned *__restrict__ his
         const int lim = (int)min<int64_t>(4096, nmc - m0);
         for (int b = 0; b < lim; b += 64) {
             const unsigned c = b + lane < lim ? buf[b + lane] : 0u;
+            if (!pass && c > (unsigned)UMAX) {
+                const unsigned slot = atomicAdd(ovf_n, 1u);
+                if (slot < (unsigned)OVF_MAX) ovf[slot] = make_int2(band, (int)(m0 + b + lane));
+            }
             if (__ballot(c > (unsigned)UMAX) && lane == 0) atomicOr(flags, (unsigned)FLAG_OVERFLOW);
             int start = 0;
             for (;;) {
@@ -129,7 +147,7 @@ __global__ __launch_bounds__(256) void k_sp_cut(const unsigned *__restrict__ his
                 }
                 const int i = __ffsll((unsigned long long)m) - 1;
                 ++cnt;
-                if (pass && lane == 0) out[cnt] = (int)(m0 + b + i);
+                if (pass && lane == 0) out[cnt] = (int)((m0 + b + i) << shift);
                 acc = 0;
                 start = i;
             }
@@ -138,16 +156,42 @@ __global__ __launch_bounds__(256) void k_sp_cut(const unsigned *__restrict__ his
     if (threadIdx.x == 0) {
         ++cnt;  // the last (possibly empty) chunk
         if (pass)
-            out[cnt] = (int)nmc;
+            out[cnt] = (int)(nmc << shift);
         else
             nchunks[band] = cnt;
+    }
+}
+
+// Counts of a band's entries in each 64-key range of an overflowing micro-chunk: one
+// workgroup per listed (band, micro-chunk), wave w scans the keys of the band's row w that
+// fall in the micro-chunk (found by binary search in the row's ascending keys).
+__global__ __launch_bounds__(1024) void k_sp_fine(const uint32_t *__restrict__ k32, const int64_t *__restrict__ off,
+                                                  const int *__restrict__ perm, int n, int wlog,
+                                                  const int2 *__restrict__ ovf, unsigned *__restrict__ fine)
+{
+    const int2 pr = ovf[blockIdx.x];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = pr.x * RB + w;
+    if (r >= n) return;
+    const int i = perm[r];
+    const uint64_t lo = (uint64_t)pr.y << wlog, hi = lo + ((uint64_t)1 << wlog);
+    int64_t a = off[i], e = off[i + 1];
+    while (a < e) {  // first entry with key >= lo (wave-uniform search)
+        const int64_t mid = a + ((e - a) >> 1);
+        if ((uint64_t)k32[mid] < lo) a = mid + 1; else e = mid;
+    }
+    unsigned *f = fine + (int64_t)blockIdx.x * ((int64_t)1 << (wlog - FINE_LOG));
+    for (int64_t p = a + lane; p < off[i + 1]; p += 64) {
+        const uint64_t k = k32[p];
+        if (k >= hi) break;
+        atomicAdd(f + ((k - lo) >> FINE_LOG), 1u);
     }
 }
 
 template <int LPC>
 __global__ __launch_bounds__(SP_THREADS, 1) void k_sparse(const uint32_t *__restrict__ k32, const float *__restrict__ vals,
                                                          const int64_t *__restrict__ off, const int *__restrict__ perm,
-                                                         const float *__restrict__ inv_norm, int n, int wlog,
+                                                         const float *__restrict__ inv_norm, int n, int ulog,
                                                          const int64_t *__restrict__ cshift,
                                                          const int *__restrict__ bounds, QueueArgs q,
                                                          float *__restrict__ out, uint32_t *__restrict__ counts)
@@ -204,7 +248,7 @@ __global__ __launch_bounds__(SP_THREADS, 1) void k_sparse(const uint32_t *__rest
         const int *bnd = bounds + cshift[band];
         int prev_u = UMAX;
         for (int ch = 0; ch < nch; ++ch) {
-            const uint64_t K1 = (uint64_t)bnd[ch + 1] << wlog;
+            const uint64_t K1 = (uint64_t)bnd[ch + 1] << ulog;
             // 1. clear the table
             for (int k = tid; k < HSIZE; k += SP_THREADS) htab[k] = ~0ull;
             for (int k = tid; k < prev_u * RB / 4; k += SP_THREADS) {
@@ -457,35 +501,102 @@ rocket_status sp_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, hip
     // keys are u32, so a shift by wlog must stay below 32 (set_option caps the width at 2^31)
     if (wlog > 31) return fail(ctx, ROCKET_E_INVALID, "sparse micro-chunk width above 2^31");
     const int64_t nmc = (int64_t)(maxkey >> wlog) + 1;
+    const int ulog = std::min(wlog, FINE_LOG), shift = wlog - ulog;  // bounds in units of 2^ulog keys
+    // WS_SP_CHUNKS: histogram [nbands][nmc] | chunk counts [nbands] | overflow count (+pad) |
+    // overflow list [OVF_MAX] (band, micro-chunk)
+    const size_t hist_bytes = sizeof(unsigned) * (size_t)(nbands * nmc);
+    const size_t list_off = hist_bytes + sizeof(int) * (size_t)(nbands + 2);
     void *hp = nullptr;
-    RK_TRY(ws_get(ctx, WS_SP_CHUNKS, sizeof(unsigned) * (size_t)(nbands * nmc) + sizeof(int) * (nbands + 1), &hp));
+    RK_TRY(ws_get(ctx, WS_SP_CHUNKS, list_off + sizeof(int2) * OVF_MAX, &hp));
     unsigned *hist = (unsigned *)hp;
     int *nchunks = (int *)(hist + nbands * nmc);
-    RK_HIP(hipMemsetAsync(hist, 0, sizeof(unsigned) * (size_t)(nbands * nmc), s));
+    unsigned *ovf_n = (unsigned *)(nchunks + nbands);
+    int2 *ovf = (int2 *)((char *)hp + list_off);
+    RK_HIP(hipMemsetAsync(hist, 0, list_off, s));
     hipLaunchKernelGGL(k_sp_hist, dim3((unsigned)n), dim3(256), 0, s, (const uint32_t *)kp, it->offsets,
                        (const int *)perm, (int)n, wlog, nmc, hist);
     RK_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_sp_cut, dim3((unsigned)nbands), dim3(256), 0, s, (const unsigned *)hist, nmc, 0, nchunks,
-                       (const int64_t *)nullptr, (int *)nullptr, flags);
+    hipLaunchKernelGGL(k_sp_cut, dim3((unsigned)nbands), dim3(256), 0, s, (const unsigned *)hist, nmc, 0, shift,
+                       nchunks, (const int64_t *)nullptr, (int *)nullptr, flags, ovf, ovf_n, (const int *)nullptr);
     RK_HIP(hipGetLastError());
     std::vector<int> hn(nbands);
+    unsigned novf = 0;
     RK_HIP(hipMemcpyAsync(hn.data(), nchunks, sizeof(int) * nbands, hipMemcpyDeviceToHost, s));
-    RK_HIP(hipMemcpyAsync(hf, flags, 4, hipMemcpyDeviceToHost, s));
+    RK_HIP(hipMemcpyAsync(&novf, ovf_n, sizeof(unsigned), hipMemcpyDeviceToHost, s));
     RK_HIP(hipStreamSynchronize(s));
-    if (hf[0] & FLAG_OVERFLOW)
-        return fail(ctx, ROCKET_E_UNSUPPORTED, "more than " + std::to_string(UMAX) + " keys of one 16-item band fall in one micro-chunk");
-    // band b's nch_b + 1 boundaries live at cshift[b] = sum_{c<b} (nch_c + 1)
+    // Bands with a micro-chunk holding more than UMAX of their entries are cut on the host at
+    // 64-key granularity from a finer histogram of just those micro-chunks.
+    std::vector<int> host_cut(nbands, 0);
+    std::vector<std::vector<int>> hb(nbands);  // host-cut bounds (units), per band
+    if (novf > 0) {
+        if (novf > (unsigned)OVF_MAX)
+            return fail(ctx, ROCKET_E_UNSUPPORTED,
+                        "more than " + std::to_string(OVF_MAX) + " micro-chunks hold more than " +
+                            std::to_string(UMAX) + " entries of one 16-item band");
+        const int64_t nb = (int64_t)1 << shift;  // 64-key ranges per micro-chunk
+        if ((int64_t)novf * nb * 4 > ((int64_t)1 << 30))
+            return fail(ctx, ROCKET_E_UNSUPPORTED, "dense key ranges too wide for the fine histogram (1 GiB)");
+        std::vector<int2> lst(novf);
+        RK_HIP(hipMemcpyAsync(lst.data(), ovf, sizeof(int2) * novf, hipMemcpyDeviceToHost, s));
+        RK_HIP(hipStreamSynchronize(s));
+        std::sort(lst.begin(), lst.end(), [](int2 a, int2 b) { return a.x != b.x ? a.x < b.x : a.y < b.y; });
+        void *fp = nullptr;
+        RK_TRY(ws_get(ctx, WS_SP_FINE, (size_t)(novf * nb * 4), &fp));
+        RK_HIP(hipMemcpyAsync(ovf, lst.data(), sizeof(int2) * novf, hipMemcpyHostToDevice, s));
+        RK_HIP(hipMemsetAsync(fp, 0, (size_t)(novf * nb * 4), s));
+        hipLaunchKernelGGL(k_sp_fine, dim3(novf), dim3(1024), 0, s, (const uint32_t *)kp, it->offsets,
+                           (const int *)perm, (int)n, wlog, (const int2 *)ovf, (unsigned *)fp);
+        RK_HIP(hipGetLastError());
+        std::vector<unsigned> fine((size_t)(novf * nb)), row((size_t)nmc);
+        RK_HIP(hipMemcpyAsync(fine.data(), fp, sizeof(unsigned) * fine.size(), hipMemcpyDeviceToHost, s));
+        RK_HIP(hipStreamSynchronize(s));
+        for (size_t q = 0; q < lst.size();) {
+            const int b = lst[q].x;
+            RK_HIP(hipMemcpy(row.data(), hist + (int64_t)b * nmc, sizeof(unsigned) * nmc, hipMemcpyDeviceToHost));
+            // greedy: close a chunk before the unit whose entries would take it past UMAX
+            std::vector<int> &bd = hb[b];
+            bd.assign(1, 0);
+            uint64_t acc = 0;
+            auto take = [&](uint64_t c, int64_t unit) {
+                if (acc + c > (uint64_t)UMAX && acc > 0) {
+                    bd.push_back((int)unit);
+                    acc = 0;
+                }
+                acc += c;
+            };
+            for (int64_t m = 0; m < nmc; ++m) {
+                if (q < lst.size() && lst[q].x == b && lst[q].y == m) {
+                    for (int64_t f = 0; f < nb; ++f) take(fine[q * nb + f], (m << shift) + f);
+                    ++q;
+                } else {
+                    take(row[m], m << shift);
+                }
+            }
+            bd.push_back((int)(nmc << shift));
+            hn[b] = (int)bd.size() - 1;
+            host_cut[b] = 1;
+        }
+    }
+    // band b's nch_b + 1 boundaries live at cshift[b] = sum_{c<b} (nch_c + 1); the host-cut
+    // flags follow cshift in the same buffer
     std::vector<int64_t> cshift(nbands + 1, 0);
     for (int64_t b = 0; b < nbands; ++b) cshift[b + 1] = cshift[b] + hn[b] + 1;
     void *csp = nullptr, *bp = nullptr;
-    RK_TRY(ws_get(ctx, WS_SP_CSHIFT, sizeof(int64_t) * (size_t)(nbands + 1), &csp));
+    RK_TRY(ws_get(ctx, WS_SP_CSHIFT, sizeof(int64_t) * (size_t)(nbands + 1) + sizeof(int) * (size_t)nbands, &csp));
     RK_TRY(ws_get(ctx, WS_SP_BOUNDS, sizeof(int) * (size_t)cshift[nbands], &bp));
+    int *dcut = (int *)((int64_t *)csp + nbands + 1);
     RK_HIP(hipMemcpyAsync(csp, cshift.data(), sizeof(int64_t) * (nbands + 1), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_sp_cut, dim3((unsigned)nbands), dim3(256), 0, s, (const unsigned *)hist, nmc, 1, nchunks,
-                       (const int64_t *)csp, (int *)bp, flags);
+    RK_HIP(hipMemcpyAsync(dcut, host_cut.data(), sizeof(int) * nbands, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_sp_cut, dim3((unsigned)nbands), dim3(256), 0, s, (const unsigned *)hist, nmc, 1, shift,
+                       nchunks, (const int64_t *)csp, (int *)bp, flags, ovf, ovf_n, (const int *)dcut);
     RK_HIP(hipGetLastError());
-    RK_HIP(hipStreamSynchronize(s));  // cshift staging vector goes out of scope
+    for (int64_t b = 0; b < nbands; ++b)
+        if (host_cut[b])
+            RK_HIP(hipMemcpyAsync((int *)bp + cshift[b], hb[b].data(), sizeof(int) * hb[b].size(),
+                                  hipMemcpyHostToDevice, s));
+    RK_HIP(hipStreamSynchronize(s));  // the staging vectors go out of scope
     sp.wlog = wlog;
+    sp.ulog = ulog;
     sp.cshift = (const int64_t *)csp;
     sp.bounds = (const int *)bp;
     sp.inv_norm = inv_norm;
@@ -536,10 +647,10 @@ rocket_status sp_compare(rocket_ctx *ctx, float *out, uint32_t *counts, hipStrea
     RK_TRY(timing_begin(ctx, s));
     if (sp.lpc == 4)
         hipLaunchKernelGGL(k_sparse<4>, dim3(grid), dim3(SP_THREADS), 0, s, sp.k32, sp.vals, sp.offsets, sp.dperm,
-                           sp.inv_norm, (int)sp.n, sp.wlog, sp.cshift, sp.bounds, sp.qa, out, counts);
+                           sp.inv_norm, (int)sp.n, sp.ulog, sp.cshift, sp.bounds, sp.qa, out, counts);
     else
         hipLaunchKernelGGL(k_sparse<8>, dim3(grid), dim3(SP_THREADS), 0, s, sp.k32, sp.vals, sp.offsets, sp.dperm,
-                           sp.inv_norm, (int)sp.n, sp.wlog, sp.cshift, sp.bounds, sp.qa, out, counts);
+                           sp.inv_norm, (int)sp.n, sp.ulog, sp.cshift, sp.bounds, sp.qa, out, counts);
     RK_HIP(hipGetLastError());
     RK_TRY(timing_end(ctx, s));
     return ROCKET_OK;

@@ -158,6 +158,36 @@ def test_option_validation(ctx):
         assert e.value.status == E_INVALID
 
 
+@pytest.mark.parametrize("lanes", [4, 8])
+@pytest.mark.parametrize("base,span,n", [(3 << 30, 4096, 16), (2 ** 32 - 70000, 8192, 40), (1 << 31, 1500, 33)])
+def test_dense_key_ranges(ctx, base, span, n, lanes):
+    # keys near the top of the u32 range force wide micro-chunks (2^12 keys); every item
+    # holds `span` consecutive keys from `base` (shifted by item, so blocks overlap partly)
+    # plus random keys, so one micro-chunk holds far more than one chunk's capacity of a
+    # band's entries and must be cut at 64-key granularity
+    announce("sparse dense key ranges base=%d span=%d n=%d lanes=%d" % (base, span, n, lanes))
+    g = np.random.default_rng(span + n)
+    ks, vs = [], []
+    for i in range(n):
+        dense = base + 17 * i + np.arange(span, dtype=np.int64)
+        extra = g.integers(0, 2 ** 32 - 1, g.integers(50, 400))
+        k = np.unique(np.concatenate([dense, extra]))
+        k = k[k < 2 ** 32 - 1]
+        ks.append(k)
+        vs.append((g.random(k.size) - 0.3).astype(np.float32))  # signed values
+    off = np.zeros(n + 1, dtype=np.int64)
+    off[1:] = np.cumsum([k.size for k in ks])
+    keys, vals = np.concatenate(ks), np.concatenate(vs)
+    ctx.set(queue_order=0, sp_lanes=lanes)
+    got, cnt = ctx.allpairs(_dev(off, keys, vals), "sparse_cosine", counts=True)
+    st = ctx.stats()
+    ctx.set(sp_lanes=0)
+    pi, pj = oracle.all_pairs(n)
+    _check(got.cpu().numpy(), cnt.cpu().numpy(), off, keys, vals, pi, pj)
+    # the dense block alone needs several chunks per band
+    assert st["kchunk"] >= (n + 15) // 16 * (16 * span // 1632)
+
+
 def test_errors(ctx):
     from paper_2009_04755_amd._lib import RocketError, E_KEYRANGE, E_UNSORTED
     announce("sparse errors")
