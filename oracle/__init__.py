@@ -48,6 +48,7 @@ def lib():
         L.oracle_overlap_grad_pairs.argtypes = [P, P, P, D, P, P, P, I64, P, P, P, P]
         L.oracle_sparse_pairs.argtypes = [P, P, P, P, P, I64, P, P, P, P]
         L.oracle_gmm_pairs.argtypes = [P, P, P, ctypes.c_int, P, P, I64, P, P]
+        L.oracle_gmm_grad_pairs.argtypes = [P, P, P, P, P, ctypes.c_int, P, P, P, I64, P, P, P, P]
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -142,6 +143,30 @@ def gmm(offsets, xy, sig, pi, pj, mode: str = "l2", with_kappa: bool = False):
     lib().oracle_gmm_pairs(_p(xy), _p(sig), _p(offsets), {"l2": 0, "bhattacharya": 1}[mode], _p(pi), _p(pj),
                            pi.size, _p(cost), _p(kappa))
     return (cost, kappa) if with_kappa else cost
+
+
+def gmm_grad(offsets, xy, pi, pj, mode: str = "l2", sig=None, cov=None, centroids=None, params=None):
+    """Per-localisation-uncertainty score with a covariance per point (``cov`` f32 [total][3]:
+    xx, xy, yy) or an isotropic deviation (``sig`` f32 [total]), for the listed pairs, with
+    cloud j moved by ``params`` [np][3] = (theta, tx, ty) about ``centroids[j]`` (identity when
+    None).  Returns (cost [np], grad [np][3], tau [np][3], kappa [np])."""
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    xy = np.ascontiguousarray(xy, dtype=np.float32)
+    sig = None if sig is None else np.ascontiguousarray(sig, dtype=np.float32)
+    cov = None if cov is None else np.ascontiguousarray(cov, dtype=np.float32).reshape(-1)
+    assert (sig is None) != (cov is None)
+    pi, pj = _pairs(pi, pj)
+    cen = None if centroids is None else np.ascontiguousarray(centroids, dtype=np.float32)
+    prm = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
+    if prm is not None:
+        assert prm.shape == (pi.size, 3) and cen is not None
+    cost = np.empty(pi.size)
+    grad = np.empty((pi.size, 3))
+    tau = np.empty((pi.size, 3))
+    kappa = np.empty(pi.size)
+    lib().oracle_gmm_grad_pairs(_p(xy), _p(sig), _p(cov), _p(offsets), _p(cen), {"l2": 0, "bhattacharya": 1}[mode],
+                                _p(pi), _p(pj), _p(prm), pi.size, _p(cost), _p(grad), _p(tau), _p(kappa))
+    return cost, grad, tau, kappa
 
 
 def sparse_cosine(offsets, keys, vals, pi, pj, with_tau: bool = False):

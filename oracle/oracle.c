@@ -226,6 +226,121 @@ void oracle_overlap_grad_pairs(const float *xy, const int64_t *off, const float 
 }
 
 /* ---------------------------------------------------------------------------------------
+ * Per-localisation-uncertainty scores with a full covariance per point, and their gradient
+ * with respect to a rigid transform of the second cloud.  Point k of cloud i is the
+ * Gaussian N(x_k, S_k); point l of cloud j is N(y_l, T_l).  Moving cloud j by
+ * q = (theta, tx, ty) about its centroid c_j moves a point to y'_l = R(y_l - c_j) + c_j + t
+ * and turns its covariance into T'_l = R T_l R^T.  With V = S_k + T'_l and d = y'_l - x_k:
+ *   mode 0 (GMM L2 cross term):  w = exp(-d^T V^-1 d / 2) / (2 pi sqrt(det V)),
+ *                                 the integral of N(z; x_k, S_k) N(z; y'_l, T'_l) over z;
+ *   mode 1 (Bhattacharya):        w = 2 (det S_k det T_l)^(1/4) / sqrt(det V) exp(-d^T V^-1 d / 4),
+ *                                 the integral of sqrt(N(z; x_k, S_k) N(z; y'_l, T'_l)).
+ * cost = sum_kl w.  Covariances come from cov (3 floats per point: xx, xy, yy) or, when cov
+ * is NULL, from sig (isotropic s^2 I).  params (double [np][3]) may be NULL: identity.
+ * Gradient (grad may be NULL), with a = 1/2 (L2) or 1/4 (Bhattacharya), g = dd/dtheta =
+ * J (y'_l - c_j - t) and W = dV/dtheta = J T'_l - T'_l J (J the 90-degree rotation):
+ *   dw/dt     = -2 a w V^-1 d
+ *   dw/dtheta = w (-a (2 g^T V^-1 d - d^T V^-1 W V^-1 d) - tr(V^-1 W) / 2).
+ * kappa = cost-weighted mean of the exponent a d^T V^-1 d; tau[p][m] =
+ * sqrt(sum_kl (dw/dq_m)^2) max(1, kappa/50), as for the fixed-sigma overlap.
+ * ------------------------------------------------------------------------------------- */
+void oracle_gmm_grad_pairs(const float *xy, const float *sig, const float *cov, const int64_t *off, const float *cen,
+                           int mode, const int64_t *pi, const int64_t *pj, const double *params, int64_t np,
+                           double *cost, double *grad, double *tau, double *kappa)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    const double a = mode == 0 ? 0.5 : 0.25;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t p = 0; p < np; ++p) {
+        const int64_t i = pi[p], j = pj[p];
+        const double th = params ? params[3 * p] : 0.0;
+        const double tx = params ? params[3 * p + 1] : 0.0, ty = params ? params[3 * p + 2] : 0.0;
+        const double ct = cos(th), st = sin(th);
+        const double cx = cen ? (double)cen[2 * j] : 0.0, cy = cen ? (double)cen[2 * j + 1] : 0.0;
+        double c = 0.0, ce = 0.0, gth = 0.0, gx = 0.0, gy = 0.0, q0 = 0.0, q1 = 0.0, q2 = 0.0;
+        for (int64_t l = off[j]; l < off[j + 1]; ++l) {
+            /* moved point and covariance of cloud j */
+            const double rx = (double)xy[2 * l] - cx, ry = (double)xy[2 * l + 1] - cy;
+            const double ox = ct * rx - st * ry, oy = st * rx + ct * ry;
+            const double yx = ox + cx + tx, yy = oy + cy + ty;
+            const double gvx = -oy, gvy = ox; /* J R (y - c) */
+            double t00, t01, t11;
+            if (cov) {
+                t00 = cov[3 * l];
+                t01 = cov[3 * l + 1];
+                t11 = cov[3 * l + 2];
+            } else {
+                t00 = t11 = (double)sig[l] * (double)sig[l];
+                t01 = 0.0;
+            }
+            const double detT = t00 * t11 - t01 * t01;
+            /* T' = R T R^T */
+            const double m00 = ct * t00 - st * t01, m01 = ct * t01 - st * t11; /* (R T) row 0 */
+            const double m10 = st * t00 + ct * t01, m11 = st * t01 + ct * t11; /* (R T) row 1 */
+            const double r00 = m00 * ct - m01 * st, r01 = m00 * st + m01 * ct;
+            const double r11 = m10 * st + m11 * ct;
+            /* W = J T' - T' J for J = [[0, -1], [1, 0]] */
+            const double w00 = -2.0 * r01, w01 = r00 - r11, w11 = 2.0 * r01;
+            for (int64_t k = off[i]; k < off[i + 1]; ++k) {
+                double s00, s01, s11;
+                if (cov) {
+                    s00 = cov[3 * k];
+                    s01 = cov[3 * k + 1];
+                    s11 = cov[3 * k + 2];
+                } else {
+                    s00 = s11 = (double)sig[k] * (double)sig[k];
+                    s01 = 0.0;
+                }
+                const double detS = s00 * s11 - s01 * s01;
+                const double v00 = s00 + r00, v01 = s01 + r01, v11 = s11 + r11;
+                const double det = v00 * v11 - v01 * v01;
+                /* inverse of V */
+                const double i00 = v11 / det, i01 = -v01 / det, i11 = v00 / det;
+                const double dx = yx - (double)xy[2 * k], dy = yy - (double)xy[2 * k + 1];
+                const double ux = i00 * dx + i01 * dy, uy = i01 * dx + i11 * dy; /* V^-1 d */
+                const double qf = dx * ux + dy * uy;
+                const double e = a * qf;
+                double w;
+                if (mode == 0)
+                    w = exp(-e) / (two_pi * sqrt(det));
+                else
+                    w = 2.0 * pow(detS * detT, 0.25) / sqrt(det) * exp(-e);
+                c += w;
+                ce += e * w;
+                if (grad || tau) {
+                    /* V^-1 W V^-1 d and tr(V^-1 W) */
+                    const double wux = w00 * ux + w01 * uy, wuy = w01 * ux + w11 * uy;
+                    const double quad = ux * wux + uy * wuy; /* d^T V^-1 W V^-1 d */
+                    const double tr = i00 * w00 + 2.0 * i01 * w01 + i11 * w11;
+                    const double dth = w * (-a * (2.0 * (gvx * ux + gvy * uy) - quad) - 0.5 * tr);
+                    const double dtx = -2.0 * a * w * ux, dty = -2.0 * a * w * uy;
+                    gth += dth;
+                    gx += dtx;
+                    gy += dty;
+                    q0 += dth * dth;
+                    q1 += dtx * dtx;
+                    q2 += dty * dty;
+                }
+            }
+        }
+        cost[p] = c;
+        const double kap = c > 0.0 ? ce / c : 0.0;
+        if (kappa) kappa[p] = kap;
+        if (grad) {
+            grad[3 * p] = gth;
+            grad[3 * p + 1] = gx;
+            grad[3 * p + 2] = gy;
+        }
+        if (tau) {
+            const double f = kap > 50.0 ? kap / 50.0 : 1.0;
+            tau[3 * p] = sqrt(q0) * f;
+            tau[3 * p + 1] = sqrt(q1) * f;
+            tau[3 * p + 2] = sqrt(q2) * f;
+        }
+    }
+}
+
+/* ---------------------------------------------------------------------------------------
  * Sparse cosine.  Each item is a list of strictly ascending int64 keys with f32 values.
  * count = |K_i intersect K_j| by a two-pointer merge; dot = sum over shared keys of
  * v_i * v_j; cos = dot / (|v_i|_2 |v_j|_2) with the norms over all entries of each item;
