@@ -14,7 +14,8 @@ committed counter file when its kernel-source hash matches); ``cpu_baseline`` ti
 FP64 oracle on a bounded sample of the same workload on this host.  Extra fields report the
 plain FP32 and two-term split paths at the same shape, the same workload through the
 out-of-core device cache, the Gaussian-overlap, GMM and registration-gradient costs over
-2048 point clouds, the sparse cosine of 8192 k-mer vectors, the PCE of 1024 images and the
+2048 point clouds (also with a full covariance per point, and the registration on each GMM
+score), the sparse cosine of 8192 k-mer vectors, the PCE of 1024 images and the
 composition-vector construction of 128 proteomes, each with its own roofline and, where
 cheap enough, the oracle on a sample.  ``--only`` runs one of those workloads alone (for
 profiling).
@@ -508,8 +509,69 @@ def other_pair_fns(ctx, with_cpu=True):
             got = out.cpu().numpy()[pi * 2048 - pi * (pi + 1) // 2 + (pj - pi - 1)]
             res[fn]["errors"] = _errors(got, ref, scale=ref * np.maximum(1, kap / 50) + 1e5 * nn * pre * 2.0 ** -126)
             res[fn]["errors"]["kappa_over_50_frac"] = float(np.mean(kap > 50))
+    # full covariance per localisation (uncertainty ellipses, semi-axes U[0.01, 0.03]); VALU
+    # slots per term counted in the kernels' compiled inner loops (3 transcendentals at 4)
+    cov = synth.point_covs(off)
+    clc = Clouds(cl.offsets, cl.xy, 0.02, point_cov=torch.from_numpy(cov).cuda())
+    g = np.random.default_rng(12)
+    sel = np.sort(g.choice(P, 1000, replace=False))
+    iu = np.triu_indices(2048, 1)
+    spi, spj = iu[0][sel].astype(np.int64), iu[1][sel].astype(np.int64)
+    for fn, mode, slots in (("gmm_l2", "l2", 30.6), ("gmm_bhattacharya", "bhattacharya", 31.6)):
+        dtg, kg = _time_fn(ctx, clc, fn, out, 3, 1)
+        peak_g = VALU_LANE_OPS / slots
+        rec = {"workload": "2048 clouds, 50..400 points, full covariance per point (semi-axes U[0.01, 0.03])",
+               "pairs_per_s": 3 * P / dtg, "kernel_ms": kg * 1e3, "terms_per_s": terms / kg,
+               "roofline": {"bound": "alu", "achieved": terms / kg, "peak": peak_g, "unit": "terms/s",
+                            "frac": terms / kg / peak_g, "valu_slots_per_term": slots}}
+        if with_cpu:
+            import oracle
+            t0 = time.perf_counter()
+            ref, _, _, kap = oracle.gmm_grad(off, xy, spi, spj, mode, cov=cov)
+            dto = time.perf_counter() - t0
+            nn = cnt[spi] * cnt[spj]
+            pre = max(1.0, 1.0 / (2 * np.pi * 2 * 0.01 ** 2)) if mode == "l2" else 2.0
+            rec["errors"] = _errors(out.cpu().numpy()[sel], ref,
+                                    scale=ref * np.maximum(1, kap / 50) + 1e5 * nn * pre * 2.0 ** -126)
+            rec["errors"]["kappa_over_50_frac"] = float(np.mean(kap > 50))
+            rec["cpu_baseline"] = dict({"value": sel.size / dto, "unit": "pairs/s", "cores": oracle.num_threads(),
+                                        "kind": "oracle", "sample": "1000 random pairs of the 2048 clouds"},
+                                       **_host_info())
+        res[fn + "_full_cov"] = rec
     cen = torch.from_numpy(synth.cloud_centroids(off, xy)).cuda()
     p0 = torch.from_numpy(synth.rigid_starts(P, config=3)).cuda()
+    # registration on each GMM score with full covariances: 20 GD steps of the adjoint kernel;
+    # the step is scaled by the score's largest term (1 / (4 pi s^2) at s = 0.02 for L2) so the
+    # three registrations move their transforms by comparable amounts
+    for fn, mode, slots, lr in (("gmm_l2", "l2", 47.0, 0.01 * 4 * np.pi * 0.02 ** 2),
+                                ("gmm_bhattacharya", "bhattacharya", 48.0, 0.01)):
+        register(clc, cen, p0, steps=1, ctx=ctx, fn=fn, lr=lr)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pf = register(clc, cen, p0, steps=20, ctx=ctx, fn=fn, lr=lr)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        kern = ctx.stats()["kernel_ns"] * 1e-9
+        peak_g = VALU_LANE_OPS / slots
+        rec = {"workload": "same clouds with full covariances, adjoint of (theta, tx, ty) of the %s score, 20 GD "
+                           "steps" % mode,
+               "pair_steps_per_s": 20 * P / dt, "kernel_ms": kern * 1e3,
+               "roofline": {"bound": "alu", "achieved": terms / kern, "peak": peak_g, "unit": "terms/s",
+                            "frac": terms / kern / peak_g, "valu_slots_per_term": slots}}
+        if with_cpu:
+            import oracle
+            cost, grad = ctx.cost_grad(clc, cen, pf.contiguous(), fn=fn)
+            prm = pf.cpu().numpy()[sel].astype(np.float64)
+            rc, rg, tau, kap = oracle.gmm_grad(off, xy, spi, spj, mode, cov=cov, centroids=cen.cpu().numpy(),
+                                               params=prm)
+            nn = cnt[spi] * cnt[spj]
+            pre = max(1.0, 1.0 / (2 * np.pi * 2 * 0.01 ** 2)) if mode == "l2" else 2.0
+            sl = nn * pre * 2.0 ** -126
+            rec["errors"] = {
+                "cost": _errors(cost.cpu().numpy()[sel], rc, scale=rc * np.maximum(1, kap / 50) + 1e5 * sl),
+                "grad": _errors(grad.cpu().numpy()[sel], rg, floor=tau + 1e5 * (sl * 1e4)[:, None]),
+                "kappa_over_50_frac": float(np.mean(kap > 50)), "at": "final iterate of the 20 GPU steps, 1000 pairs"}
+        res["registration_%s_full_cov_20_steps" % fn] = rec
     register(cl, cen, p0, steps=1, ctx=ctx)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

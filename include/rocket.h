@@ -108,7 +108,14 @@ typedef enum {
      *                      components' Bhattacharya coefficients.
      * FP32 with one reciprocal and one exp2 per term.  Deviations come from
      * point_sigma and must lie in [1e-18, 1e18] (checked in rocket_prepare, else
-     * ROCKET_E_INVALID); the scalar sigma is ignored.  An empty cloud gives 0. */
+     * ROCKET_E_INVALID); the scalar sigma is ignored.  An empty cloud gives 0.
+     * With point_cov set, every point carries a full covariance (S_k for cloud i, T_l for
+     * cloud j; V = S_k + T_l, d = x_k - y_l) and the terms are the same integrals:
+     *   GMM_L2:            exp(-d^T V^-1 d / 2) / (2 pi sqrt(det V)),
+     *   GMM_BHATTACHARYA:  2 (det S_k det T_l)^(1/4) / sqrt(det V) exp(-d^T V^-1 d / 4);
+     * one reciprocal square root and one exp2 per term.  Each covariance must be symmetric
+     * positive definite with diagonal entries and determinant in [1e-36, 1e36] (checked in
+     * rocket_prepare, else ROCKET_E_INVALID). */
     ROCKET_GMM_L2 = 6,
     ROCKET_GMM_BHATTACHARYA = 7,
     /* Peak-to-correlation energy over all cyclic shifts (the PCE variant of the forensics
@@ -142,6 +149,9 @@ typedef struct {
     const float *vals;
     /* GMM scores: float32 standard deviation per point, [offsets[n]], same order as xy. */
     const float *point_sigma;
+    /* GMM scores with a full covariance per point: float32 (c_xx, c_xy, c_yy) per point,
+     * [3 * offsets[n]], same order as xy; when set, point_sigma is ignored. */
+    const float *point_cov;
 } rocket_items;
 
 typedef struct rocket_ctx rocket_ctx;
@@ -246,6 +256,29 @@ rocket_status rocket_overlap_cost_grad(rocket_ctx *ctx, const rocket_items *clou
                                        const float *centroids, const float *params, float *out_cost,
                                        float *out_grad, void *stream);
 
+/* Registration gradient of any of the three particle scores (Section V-C: the optimiser
+ * maximises the GMM L2 cross term or the Bhattacharya coefficient sum between particles
+ * whose localisations carry an uncertainty, or the fixed-sigma overlap).  fn:
+ * ROCKET_GAUSS_OVERLAP (exactly rocket_overlap_cost_grad), ROCKET_GMM_L2 or
+ * ROCKET_GMM_BHATTACHARYA.  For the GMM scores the second cloud of pair (i, j) is moved by
+ * q = params[idx(i,j)] = (theta, tx, ty) about c_j = centroids[j], points and covariances
+ * alike (y'_l = R(y_l - c_j) + c_j + t, T'_l = R T_l R^T; isotropic deviations give
+ * T_l = t_l^2 I), and out_cost / out_grad receive the score of the moved pair and its
+ * gradient with respect to q.  With a = 1/2 (L2) or 1/4 (Bhattacharya), V = S_k + T'_l,
+ * d = y'_l - x_k, u = V^-1 d, g = J R(y_l - c_j), W = J T'_l - T'_l J (J the 90-degree
+ * rotation), each term w contributes
+ *     dw/dt = -2 a w u,    dw/dtheta = w (-2 a g^T u + a u^T W u - tr(V^-1 W) / 2).
+ * items: offsets + xy + point_sigma or point_cov as for the pair function; this call
+ * prepares them (one synchronisation).  items = NULL reuses what the previous
+ * rocket_cost_grad (or rocket_overlap_cost_grad) on this context prepared for the same fn
+ * and n (no other prepare in between); the caller guarantees the clouds are alive and
+ * unchanged; else ROCKET_E_STATE.  Other arguments and layouts as for
+ * rocket_overlap_cost_grad.  FP32 arithmetic, per-lane partial sums reduced by a fixed
+ * wavefront tree. */
+rocket_status rocket_cost_grad(rocket_ctx *ctx, const rocket_items *items, int64_t n, rocket_pair_fn fn,
+                               const float *centroids, const float *params, float *out_cost, float *out_grad,
+                               void *stream);
+
 /* Tunables.  0 means "choose automatically" for every option. */
 typedef enum {
     ROCKET_OPT_NCC_TILE = 1,        /* NCC output tile edge: 64, 128 or 256 items */
@@ -255,7 +288,7 @@ typedef enum {
                                        2 planned order in one segment */
     ROCKET_OPT_SEED = 5,            /* seed for the shuffled queue order */
     ROCKET_OPT_LEDGER = 6,          /* 1: record how often each work item is popped (rocket_get_ledger) */
-    ROCKET_OPT_OVL_BLOCK = 7,       /* clouds: clouds per block of the tile grid (0: 8), at most 64 */
+    ROCKET_OPT_OVL_BLOCK = 7,       /* clouds: clouds per block of the tile grid (0: 8; 4 with full covariances), at most 64 */
     ROCKET_OPT_OVL_VARIANT = 8,     /* overlap: inner-loop variant 1..4: lanes x points per lane of cloud j =
                                        64x1, 32x2, 16x2, 16x4 */
     ROCKET_OPT_SP_LANES = 9,        /* sparse: lanes per column item, 4 or 8 (0: 4 when that leaves at least 8

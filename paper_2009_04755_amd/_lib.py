@@ -29,14 +29,15 @@ SYMBOLS = ["rocket_create", "rocket_destroy", "rocket_status_str", "rocket_last_
            "rocket_compare", "rocket_allpairs_ex", "rocket_allpairs", "rocket_allpairs_host", "rocket_cv_build",
            "rocket_overlap_cost_grad",
            "rocket_set_option", "rocket_get_option", "rocket_get_stats", "rocket_get_ledger", "rocket_autotune",
-           "rocket_plan_tiles", "rocket_pair_index", "rocket_allpairs_noalloc"]
+           "rocket_plan_tiles", "rocket_pair_index", "rocket_allpairs_noalloc", "rocket_cost_grad"]
 NOALLOC_SCRATCH_BYTES = 64 << 20  # ROCKET_NOALLOC_SCRATCH_BYTES
 
 
 class Items(ctypes.Structure):
     _fields_ = [("dense", ctypes.c_void_p), ("dim", ctypes.c_int64), ("ld", ctypes.c_int64),
                 ("offsets", ctypes.c_void_p), ("xy", ctypes.c_void_p), ("sigma", ctypes.c_double),
-                ("keys", ctypes.c_void_p), ("vals", ctypes.c_void_p), ("point_sigma", ctypes.c_void_p)]
+                ("keys", ctypes.c_void_p), ("vals", ctypes.c_void_p), ("point_sigma", ctypes.c_void_p),
+                ("point_cov", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -90,6 +91,8 @@ def load():
     L.rocket_cv_build.restype = I32
     L.rocket_overlap_cost_grad.argtypes = [P, IT, I64, P, P, P, P, P]
     L.rocket_overlap_cost_grad.restype = I32
+    L.rocket_cost_grad.argtypes = [P, IT, I64, I32, P, P, P, P, P]
+    L.rocket_cost_grad.restype = I32
     L.rocket_set_option.argtypes = [P, I32, I64]
     L.rocket_set_option.restype = I32
     L.rocket_get_option.argtypes = [P, I32, ctypes.POINTER(I64)]

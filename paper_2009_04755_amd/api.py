@@ -33,11 +33,14 @@ class Clouds:
     """Ragged 2-D point clouds: cloud i owns points offsets[i] .. offsets[i+1]-1 of xy.
 
     ``sigma`` is the common scale of ``gauss_overlap``; ``point_sigma`` the per-point
-    standard deviation read by ``gmm_l2`` and ``gmm_bhattacharya``."""
+    standard deviation read by ``gmm_l2`` and ``gmm_bhattacharya``; ``point_cov`` a full
+    covariance (xx, xy, yy) per point for the same two scores (used instead of
+    ``point_sigma`` when given)."""
     offsets: torch.Tensor  # int64 [n+1], device
     xy: torch.Tensor       # float32 [2 * total] interleaved (x, y), device
     sigma: float = 0.02
     point_sigma: torch.Tensor | None = None  # float32 [total], device
+    point_cov: torch.Tensor | None = None    # float32 [total][3] (or [3 * total]), device
 
     @property
     def n(self) -> int:
@@ -98,6 +101,11 @@ def _items_struct(x, fn: int, device: int):
             if ps.numel() * 2 != x.xy.numel():
                 raise ValueError("point_sigma must hold one value per point")
             it.point_sigma = ps.data_ptr()
+        if fn != _lib.GAUSS_OVERLAP and x.point_cov is not None:
+            pc = _check_dev(x.point_cov, "point_cov", torch.float32, device)
+            if pc.numel() * 2 != 3 * x.xy.numel():
+                raise ValueError("point_cov must hold three values (xx, xy, yy) per point")
+            it.point_cov = pc.data_ptr()
         return it, x.n
     if fn == _lib.SPARSE_COSINE:
         if not isinstance(x, SparseSet):
@@ -231,6 +239,37 @@ class Context:
         _lib.check(_lib.load().rocket_autotune(self.handle, _stream()), self.handle)
         return {k: self.get(k) for k in ("ovl_block", "ovl_variant")}
 
+    def cost_grad(self, clouds: Clouds, centroids, params, fn: str = "gauss_overlap", with_grad: bool = True,
+                  reuse: bool = False):
+        """Score of every pair with the second cloud moved by ``params`` [P, 3] = (theta, tx,
+        ty) about its centroid, and the gradient with respect to ``params``, for
+        ``gauss_overlap``, ``gmm_l2`` or ``gmm_bhattacharya`` (the latter two with the clouds'
+        ``point_cov`` or ``point_sigma``; covariances rotate with the cloud).  ``reuse`` as
+        for :meth:`overlap_cost_grad`."""
+        if fn == "gauss_overlap":
+            return self.overlap_cost_grad(clouds, centroids, params, with_grad=with_grad, reuse=reuse)
+        code = _lib.FN_BY_NAME[fn]
+        if code not in (_lib.GMM_L2, _lib.GMM_BHATTACHARYA):
+            raise ValueError("cost gradients exist for gauss_overlap, gmm_l2 and gmm_bhattacharya")
+        n = clouds.n
+        P = num_pairs(n)
+        it, _ = self._items(clouds, code)
+        self._dev(params, "params", torch.float32)
+        self._dev(centroids, "centroids", torch.float32)
+        if tuple(params.shape) != (P, 3) or tuple(centroids.shape) != (n, 2):
+            raise ValueError("params must be [P, 3] and centroids [n, 2]")
+        tens = [clouds.offsets, clouds.xy, clouds.point_sigma, clouds.point_cov]
+        key = (fn, n) + tuple((t.data_ptr(), t._version) if t is not None else None for t in tens)
+        prev = getattr(self, "_grad_clouds", None)
+        reuse = reuse and prev is not None and prev[0] is clouds and prev[1] == key
+        cost = torch.empty(P, dtype=torch.float32, device=params.device)
+        grad = torch.empty((P, 3), dtype=torch.float32, device=params.device) if with_grad else None
+        _lib.check(_lib.load().rocket_cost_grad(self.handle, None if reuse else ctypes.byref(it), n, code,
+                                                _ptr(centroids), _ptr(params), _ptr(cost), _ptr(grad), _stream()),
+                   self.handle)
+        self._grad_clouds = (clouds, key)
+        return cost, grad
+
     def overlap_cost_grad(self, clouds: Clouds, centroids, params, with_grad: bool = True, reuse: bool = False):
         """Cost and gradient of every pair's rigid transform ``params`` [P, 3].
 
@@ -246,8 +285,8 @@ class Context:
         if tuple(params.shape) != (P, 3) or tuple(centroids.shape) != (n, 2):
             raise ValueError("params must be [P, 3] and centroids [n, 2]")
         # reuse only what this context prepared from these very tensors, unmodified since
-        key = (clouds.offsets.data_ptr(), clouds.offsets._version, clouds.xy.data_ptr(), clouds.xy._version,
-               float(clouds.sigma), n)
+        key = ("gauss_overlap", clouds.offsets.data_ptr(), clouds.offsets._version, clouds.xy.data_ptr(),
+               clouds.xy._version, float(clouds.sigma), n)
         prev = getattr(self, "_grad_clouds", None)
         reuse = reuse and prev is not None and prev[0] is clouds and prev[1] == key
         cost = torch.empty(P, dtype=torch.float32, device=params.device)
@@ -319,28 +358,30 @@ def pair_index(i: int, j: int, n: int) -> int:
 
 
 class OverlapCost(torch.autograd.Function):
-    """Per-pair overlap cost C(params) with the hand-written adjoint as its gradient.
+    """Per-pair particle score C(params) with the hand-written adjoint as its gradient.
 
-    forward(params [P,3], clouds, centroids) -> cost [P]; backward(g [P]) -> g[:,None] * dC/dparams.
+    forward(params [P,3], clouds, centroids, rctx, reuse, fn) -> cost [P] for ``fn`` in
+    gauss_overlap (default), gmm_l2, gmm_bhattacharya; backward(g [P]) -> g[:,None] * dC/dparams.
     """
 
     @staticmethod
-    def forward(ctx_, params, clouds: Clouds, centroids, rctx: Context | None = None, reuse: bool = False):
+    def forward(ctx_, params, clouds: Clouds, centroids, rctx: Context | None = None, reuse: bool = False,
+                fn: str = "gauss_overlap"):
         rc = rctx or default_context()
-        cost, grad = rc.overlap_cost_grad(clouds, centroids, params.detach().contiguous(), with_grad=True,
-                                          reuse=reuse)
+        cost, grad = rc.cost_grad(clouds, centroids, params.detach().contiguous(), fn=fn, with_grad=True, reuse=reuse)
         ctx_.save_for_backward(grad)
         return cost
 
     @staticmethod
     def backward(ctx_, g):
         (grad,) = ctx_.saved_tensors
-        return g[:, None] * grad, None, None, None, None
+        return g[:, None] * grad, None, None, None, None, None
 
 
 def register(clouds: Clouds, centroids, params0, steps: int = 20, lr: float = 0.01, ctx: Context | None = None,
-             record: bool = False):
-    """Rigid registration of every pair by gradient descent on E = -C / (N_i N_j).
+             record: bool = False, fn: str = "gauss_overlap"):
+    """Rigid registration of every pair by gradient descent on E = -C / (N_i N_j), C the
+    pair's ``fn`` score (gauss_overlap, gmm_l2 or gmm_bhattacharya).
 
     Each step evaluates the cost and its adjoint once (one persistent launch) and moves
     params <- params - lr * dE/dparams.  Returns the final params (and, with ``record``,
@@ -355,7 +396,7 @@ def register(clouds: Clouds, centroids, params0, steps: int = 20, lr: float = 0.
     rc = ctx or default_context()
     for step in range(steps):
         # the clouds do not change during the descent: prepare them once, reuse afterwards
-        cost = OverlapCost.apply(p, clouds, centroids, rc, step > 0)
+        cost = OverlapCost.apply(p, clouds, centroids, rc, step > 0, fn)
         energy = -(cost / norm).sum()
         (g,) = torch.autograd.grad(energy, p)
         with torch.no_grad():

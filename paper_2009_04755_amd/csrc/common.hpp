@@ -69,12 +69,16 @@ struct NccState {
     std::vector<int2> h_tiles;
 };
 
+// Cloud score modes: fixed-sigma overlap, per-point-sigma GMM L2 / Bhattacharya, and the
+// same two scores for points with a full covariance (also the adjoint path of both).
+enum { OVL_OVERLAP = 0, OVL_GMM_L2 = 1, OVL_GMM_BH = 2, OVL_FULL_L2 = 3, OVL_FULL_BH = 4 };
+
 struct OvlState {
     int64_t n = 0, total = 0;
     const int64_t *offsets = nullptr;
     const float *xy = nullptr;
     double sigma = 0;
-    int mode = 0;  // 0 fixed-sigma overlap, 1 GMM L2, 2 Bhattacharya
+    int mode = 0;  // OVL_*
     int block = 0;
     int64_t tiles = 0, max_block_pts = 0;
     std::vector<int64_t> h_offsets;  // host copy of offsets

@@ -10,6 +10,8 @@
 // point k carries its own standard deviation s_k (v = s_k^2 + t_l^2, D = |x_k - y_l|^2):
 //   GMM L2 cross term   sum_kl exp(-D / (2 v)) / (2 pi v)
 //   Bhattacharya        sum_kl (2 s_k t_l / v) exp(-D / (4 v))
+// and their adjoint (isotropic points rotate onto themselves): d term / d y' = -(2 a / v) term u,
+// a = 1/2 (L2) or 1/4 (Bhattacharya).
 // Prepare stores s~ = s sqrt(2 ln 2) (L2) or s sqrt(4 ln 2) (Bhattacharya) per packed point,
 // so that with r = 1 / (s~_k^2 + t~_l^2) a term is exp2(-D r) r (L2, times ln2/pi per pair) or
 // exp2(-D r) s~_k r t~_l (Bhattacharya, times 2 per pair): one reciprocal and one exp2 per term.
@@ -36,8 +38,13 @@ constexpr int OVL_WAVES = OVL_THREADS / 64;
 constexpr int OVL_MAX_BLOCK_PTS = 10000;  // per staged block (80 KB)
 constexpr int GMM_MAX_BLOCK_PTS = 6800;   // with one f32 deviation per point (81.6 KB)
 constexpr float GMM_SIG_MIN = 1e-18f, GMM_SIG_MAX = 1e18f;
+constexpr int FULL_MAX_BLOCK_PTS = 3300;  // with a float4 shape per point (24 B): 158 KB for two blocks
 
-enum { MODE_OVERLAP = 0, MODE_GMM_L2 = 1, MODE_GMM_BH = 2 };
+// Cloud score modes (OvlState::mode): the fixed-sigma overlap, the two per-point-sigma
+// scores, and the two scores for points with a full 2 x 2 covariance (or isotropic
+// deviations packed as s^2 I), the latter with or without the rigid-transform adjoint.
+constexpr int MODE_OVERLAP = OVL_OVERLAP, MODE_GMM_L2 = OVL_GMM_L2, MODE_GMM_BH = OVL_GMM_BH,
+              MODE_FULL_L2 = OVL_FULL_L2, MODE_FULL_BH = OVL_FULL_BH;
 
 __device__ __forceinline__ float wave_sum(float v)
 {
@@ -70,6 +77,36 @@ __global__ void k_ovl_pack(const float2 *__restrict__ xy, const int64_t *__restr
     }
 }
 
+// Shape of every packed point for the full-covariance scores: (c_xx, c_xy, c_yy, (det C)^(1/4))
+// from cov (3 floats per point) or, when cov is NULL, from sig as s^2 I.  Raises *flag when a
+// covariance is not symmetric positive definite with entries and determinant in
+// [1e-36, 1e36] (so that sums, determinants and their reciprocal square roots stay finite
+// and normal in FP32).
+__global__ void k_ovl_pack_shape(const int64_t *__restrict__ offsets, const int *__restrict__ perm,
+                                 const int *__restrict__ coff, int n, const float *__restrict__ cov,
+                                 const float *__restrict__ sig, float4 *__restrict__ shape, int *__restrict__ flag)
+{
+    for (int s = blockIdx.x; s < n; s += gridDim.x) {
+        const int64_t src = offsets[perm[s]];
+        const int dst = coff[s], cnt = coff[s + 1] - coff[s];
+        for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
+            double a, b, c;
+            if (cov) {
+                a = cov[3 * (src + k)];
+                b = cov[3 * (src + k) + 1];
+                c = cov[3 * (src + k) + 2];
+            } else {
+                const double v = sig[src + k];
+                a = c = v * v;
+                b = 0.0;
+            }
+            const double det = a * c - b * b;
+            if (!(a >= 1e-36 && a <= 1e36 && c >= 1e-36 && c <= 1e36 && det >= 1e-36 && det <= 1e36)) *flag = 1;
+            shape[dst + k] = make_float4((float)a, (float)b, (float)c, (float)sqrt(sqrt(det > 0 ? det : 0.0)));
+        }
+    }
+}
+
 // MODE_OVERLAP: cexp = log2(e) / (4 sigma^2), cpost unused.  GMM modes: psig holds the packed
 // scaled deviations, LDS holds them behind the points at float offset sig_at, cpost is the
 // per-pair factor.
@@ -82,7 +119,6 @@ __global__ __launch_bounds__(OVL_THREADS, 1) void k_overlap(const float2 *__rest
                                                             float gscale, const float *__restrict__ psig, int sig_at,
                                                             float cpost)
 {
-    static_assert(MODE == MODE_OVERLAP || !GRAD, "the adjoint exists for the fixed-sigma cost only");
     constexpr bool GMM = MODE != MODE_OVERLAP;
     constexpr int P = 64 / S;  // phases over the points of cloud i
     constexpr int CH = S * R;  // points of cloud j per chunk
@@ -190,7 +226,15 @@ __global__ __launch_bounds__(OVL_THREADS, 1) void k_overlap(const float2 *__rest
                     if constexpr (GMM) {
                         const float rv = __builtin_amdgcn_rcpf(fmaf(s, s, tt[r]));
                         const float wkl = __builtin_amdgcn_exp2f(-(d2 * rv));
-                        sc[r][e] = fmaf(wkl, MODE == MODE_GMM_L2 ? rv : s * rv, sc[r][e]);
+                        const float f = wkl * (MODE == MODE_GMM_L2 ? rv : s * rv);
+                        sc[r][e] += f;
+                        if constexpr (GRAD) {
+                            // d term / d y' = -2 ln2 rv u term (the scaled deviations fold in the
+                            // 1/(2v) or 1/(4v) of the exponent); the constant is applied per pair
+                            const float fr = f * rv;
+                            sx[r][e] = fmaf(fr, ux, sx[r][e]);
+                            sy[r][e] = fmaf(fr, uy, sy[r][e]);
+                        }
                     } else {
                         const float wkl = __builtin_amdgcn_exp2f(-(d2 * cexp));
                         sc[r][e] += wkl;
@@ -236,14 +280,12 @@ __global__ __launch_bounds__(OVL_THREADS, 1) void k_overlap(const float2 *__rest
                 }
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    if constexpr (MODE == MODE_GMM_BH)
-                        accC = fmaf(sc[r][0], tq[r], accC);
-                    else
-                        accC += sc[r][0];
+                    const float fl = MODE == MODE_GMM_BH ? tq[r] : 1.f;  // the point of cloud j's factor
+                    accC = fmaf(sc[r][0], fl, accC);
                     if constexpr (GRAD) {
-                        accX += sx[r][0];
-                        accY += sy[r][0];
-                        accT = fmaf(vx[r], sx[r][0], fmaf(vy[r], sy[r][0], accT));
+                        accX = fmaf(sx[r][0], fl, accX);
+                        accY = fmaf(sy[r][0], fl, accY);
+                        accT = fmaf(vx[r] * fl, sx[r][0], fmaf(vy[r] * fl, sy[r][0], accT));
                     }
                 }
             }
@@ -251,7 +293,7 @@ __global__ __launch_bounds__(OVL_THREADS, 1) void k_overlap(const float2 *__rest
             if constexpr (GRAD) {
                 const float GX = wave_sum(accX), GY = wave_sum(accY), GT = wave_sum(accT);
                 if (lane == 0) {
-                    out[pidx] = C;
+                    out[pidx] = GMM ? C * cpost : C;
                     if (grad) {
                         grad[3 * pidx] = gscale * GT;
                         grad[3 * pidx + 1] = gscale * GX;
@@ -262,6 +304,208 @@ __global__ __launch_bounds__(OVL_THREADS, 1) void k_overlap(const float2 *__rest
                 if (lane == 0) out[pidx] = C * cpost;
             } else {
                 if (lane == 0) out[pidx] = C;
+            }
+        }
+        __syncthreads();  // LDS is restaged for the next tile
+    }
+}
+
+// Full-covariance scores.  Point k of cloud i: x_k, S_k; point l of cloud j: y_l, T_l, moved
+// (GRAD) to y'_l = R(y_l - c_j) + c_j + t with T'_l = R T_l R^T.  V = S_k + T'_l, d = y'_l - x_k:
+//   L2 (BH = false): w = exp2(-log2(e)/2 d^T V^-1 d) / sqrt(det V)            (x 1/(2 pi) per pair)
+//   BH (BH = true):  w = exp2(-log2(e)/4 d^T V^-1 d) rho_k rho_l / sqrt(det V) (x 2 per pair)
+// with rho = (det S)^(1/4); one reciprocal square root, one reciprocal and one exp2 per term.  The adjoint
+// (a = 1/2 or 1/4, u = V^-1 d, g_l = J R(y_l - c_j), W_l = J T'_l - T'_l J):
+//   dC/dt     = -2a sum w u
+//   dC/dtheta = sum w (-2a g^T u + a u^T W u - tr(V^-1 W) / 2)
+// Each lane keeps, per point l of its own, the sums over k of w, w u, w u u^T and the two
+// pieces w (v_xx - v_yy) / det V and w v_xy / det V of the trace term, and contracts them
+// with g_l and W_l once the k loop ends.  Lanes own points of cloud j, loop over a
+// contiguous run of cloud i's points, and the wavefront reduces with a fixed butterfly.
+template <bool BH, bool GRAD>
+__global__ __launch_bounds__(OVL_THREADS, 1) void k_gmm_full(const float2 *__restrict__ pts,
+                                                             const float4 *__restrict__ shape,
+                                                             const int *__restrict__ coff, const int *__restrict__ perm,
+                                                             int n, int T, QueueArgs q, float *__restrict__ out,
+                                                             const float *__restrict__ cen,
+                                                             const float *__restrict__ params,
+                                                             float *__restrict__ grad, int shape_at, float cpost)
+{
+    // lanes per chunk of cloud j, points of cloud j per lane (more for the cost, whose terms
+    // need fewer registers, so each staged point of cloud i serves more independent terms)
+    constexpr int S = 16, R = GRAD ? 2 : 4;
+    constexpr int P = 64 / S, CH = S * R;
+    constexpr float A = BH ? 0.25f : 0.5f;
+    constexpr float AL2E = A * 1.4426950408889634f;  // a log2(e)
+    extern __shared__ float2 lds_pts[];
+    float4 *lds_shape = reinterpret_cast<float4 *>(reinterpret_cast<float *>(lds_pts) + shape_at);
+    __shared__ int s_item;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int slot = lane % S, phase = lane / S;
+
+    for (;;) {
+        const int it = queue_pop_wg(q, &s_item);
+        if (it < 0) break;
+        const int4 w = q.items[it];
+        const int bI = w.x, bJ = w.y;
+        const int a0 = bI * T, a1 = min(n, a0 + T), b0 = bJ * T, b1 = min(n, b0 + T);
+        const bool diag = bI == bJ;
+        const int pI0 = coff[a0], pI1 = coff[a1];
+        const int pJ0 = coff[b0], pJ1 = coff[b1];
+        const int nI = pI1 - pI0, nJ = diag ? 0 : pJ1 - pJ0;
+        for (int k = tid; k < nI; k += OVL_THREADS) {
+            lds_pts[k] = pts[pI0 + k];
+            lds_shape[k] = shape[pI0 + k];
+        }
+        for (int k = tid; k < nJ; k += OVL_THREADS) {
+            lds_pts[nI + k] = pts[pJ0 + k];
+            lds_shape[nI + k] = shape[pJ0 + k];
+        }
+        __syncthreads();
+
+        const int na = a1 - a0, nb = b1 - b0;
+        for (int p = wave; p < na * nb; p += OVL_WAVES) {
+            const int a = a0 + p / nb, b = b0 + p % nb;
+            if (a >= b) continue;
+            const int ia = perm[a], ib = perm[b];
+            const int oi = min(ia, ib), oj = max(ia, ib);
+            const int si = ia == oi ? a : b, sj = ia == oi ? b : a;
+            const int base_i = si < b0 || diag ? coff[si] - pI0 : nI + coff[si] - pJ0;
+            const int base_j = sj < b0 || diag ? coff[sj] - pI0 : nI + coff[sj] - pJ0;
+            const int Ni = coff[si + 1] - coff[si], Nj = coff[sj + 1] - coff[sj];
+            const int64_t pidx = (int64_t)oi * n - (int64_t)oi * (oi + 1) / 2 + (oj - oi - 1);
+
+            float cx = 0.f, cy = 0.f, tx = 0.f, ty = 0.f;
+            double dct = 1.0, dst = 0.0;
+            if constexpr (GRAD) {
+                const float th = params[3 * pidx];
+                tx = params[3 * pidx + 1];
+                ty = params[3 * pidx + 2];
+                sincos((double)th, &dst, &dct);
+                cx = cen[2 * oj];
+                cy = cen[2 * oj + 1];
+            }
+            float accC = 0.f, accT = 0.f, accX = 0.f, accY = 0.f;
+            for (int c0 = 0; c0 < Nj; c0 += CH) {
+                // this lane's points of cloud j: moved point (hi + lo), moved covariance, rho
+                float yx[R], yy[R], lx[R], ly[R], r00[R], r01[R], r11[R], rl[R], gx_[R], gy_[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int l = c0 + r * S + slot;
+                    if (l < Nj) {
+                        const float2 y = lds_pts[base_j + l];
+                        const float4 tq = lds_shape[base_j + l];
+                        rl[r] = BH ? tq.w : 1.f;  // this point's factor on its sums
+                        if constexpr (GRAD) {
+                            const double rx = (double)y.x - cx, ry = (double)y.y - cy;
+                            const double ox = dct * rx - dst * ry, oy = dst * rx + dct * ry;
+                            const double px = ox + cx + tx, py = oy + cy + ty;
+                            yx[r] = (float)px;
+                            yy[r] = (float)py;
+                            lx[r] = (float)(px - (double)yx[r]);
+                            ly[r] = (float)(py - (double)yy[r]);
+                            gx_[r] = (float)(-oy);
+                            gy_[r] = (float)ox;
+                            // T' = R T R^T in FP64, rounded once
+                            const double m00 = dct * tq.x - dst * tq.y, m01 = dct * tq.y - dst * tq.z;
+                            const double m10 = dst * tq.x + dct * tq.y, m11 = dst * tq.y + dct * tq.z;
+                            r00[r] = (float)(m00 * dct - m01 * dst);
+                            r01[r] = (float)(m00 * dst + m01 * dct);
+                            r11[r] = (float)(m10 * dst + m11 * dct);
+                        } else {
+                            yx[r] = y.x;
+                            yy[r] = y.y;
+                            lx[r] = ly[r] = 0.f;
+                            gx_[r] = gy_[r] = 0.f;
+                            r00[r] = tq.x;
+                            r01[r] = tq.y;
+                            r11[r] = tq.z;
+                        }
+                    } else {
+                        // no point: finite placeholder values, and a factor of 0 on its sums
+                        yx[r] = yy[r] = 0.f;
+                        lx[r] = ly[r] = 0.f;
+                        gx_[r] = gy_[r] = 0.f;
+                        r00[r] = r11[r] = 1.f;
+                        r01[r] = 0.f;
+                        rl[r] = 0.f;
+                    }
+                }
+                float sc[R], sx[R], sy[R], sxx[R], syy[R], sxy[R], t1[R], t2[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) sc[r] = sx[r] = sy[r] = sxx[r] = syy[r] = sxy[r] = t1[r] = t2[r] = 0.f;
+                const int per = (Ni + P - 1) / P;
+                const int k0 = min(Ni, phase * per), k1 = min(Ni, k0 + per);
+                const float2 *xs = lds_pts + base_i;
+                const float4 *ss = lds_shape + base_i;
+                // cost: two points of cloud i per step, both LDS reads issued before any term
+                auto term = [&](const float2 x, const float4 sk) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const float v00 = sk.x + r00[r], v01 = sk.y + r01[r], v11 = sk.z + r11[r];
+                        const float det = fmaf(v00, v11, -(v01 * v01));
+                        const float rs = __builtin_amdgcn_rsqf(det);
+                        const float idet = __builtin_amdgcn_rcpf(det);  // 1 ulp, not rs^2's ~3
+                        const float dx = (yx[r] - x.x) + lx[r], dy = (yy[r] - x.y) + ly[r];
+                        const float hx = fmaf(v11, dx, -(v01 * dy)), hy = fmaf(v00, dy, -(v01 * dx));  // adj(V) d
+                        const float qf = fmaf(hx, dx, hy * dy) * idet;                              // d^T V^-1 d
+                        float wt = __builtin_amdgcn_exp2f(-(qf * AL2E)) * rs;
+                        if constexpr (BH) wt *= sk.w;
+                        sc[r] += wt;
+                        if constexpr (GRAD) {
+                            const float ux = hx * idet, uy = hy * idet;
+                            const float fu = wt * ux, fv = wt * uy;
+                            sx[r] += fu;
+                            sy[r] += fv;
+                            sxx[r] = fmaf(fu, ux, sxx[r]);
+                            syy[r] = fmaf(fv, uy, syy[r]);
+                            sxy[r] = fmaf(fu, uy, sxy[r]);
+                            const float wi = wt * idet;
+                            t1[r] = fmaf(wi, v00 - v11, t1[r]);
+                            t2[r] = fmaf(wi, v01, t2[r]);
+                        }
+                    }
+                };
+                int k = k0;
+                if constexpr (!GRAD) {
+                    for (; k + 2 <= k1; k += 2) {
+                        const float2 x0 = xs[k], x1 = xs[k + 1];
+                        const float4 s0 = ss[k], s1 = ss[k + 1];
+                        term(x0, s0);
+                        term(x1, s1);
+                    }
+                }
+                for (; k < k1; ++k) term(xs[k], ss[k]);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const float f = rl[r];
+                    accC = fmaf(sc[r], f, accC);
+                    if constexpr (GRAD) {
+                        accX = fmaf(sx[r], f, accX);
+                        accY = fmaf(sy[r], f, accY);
+                        // u^T W u = -2 T'01 (u_x^2 - u_y^2) + 2 (T'00 - T'11) u_x u_y;
+                        // tr(V^-1 W) = (2 T'01 (v00 - v11) - 2 (T'00 - T'11) v01) / det V
+                        const float uwu = fmaf(-2.f * r01[r], sxx[r] - syy[r], 2.f * (r00[r] - r11[r]) * sxy[r]);
+                        const float tr = fmaf(2.f * r01[r], t1[r], -2.f * (r00[r] - r11[r]) * t2[r]);
+                        const float gu = fmaf(gx_[r], sx[r], gy_[r] * sy[r]);
+                        const float th = fmaf(-2.f * A, gu, fmaf(A, uwu, -0.5f * tr));
+                        accT = fmaf(th, f, accT);
+                    }
+                }
+            }
+            const float C = wave_sum(accC);
+            if constexpr (GRAD) {
+                const float GX = wave_sum(accX), GY = wave_sum(accY), GT = wave_sum(accT);
+                if (lane == 0) {
+                    out[pidx] = C * cpost;
+                    if (grad) {
+                        grad[3 * pidx] = GT * cpost;
+                        grad[3 * pidx + 1] = (-2.f * A) * GX * cpost;
+                        grad[3 * pidx + 2] = (-2.f * A) * GY * cpost;
+                    }
+                }
+            } else {
+                if (lane == 0) out[pidx] = C * cpost;
             }
         }
         __syncthreads();  // LDS is restaged for the next tile
@@ -281,11 +525,12 @@ const void *ovl_kernel_m(int variant)
 
 const void *ovl_kernel(int mode, bool grad, int variant)
 {
-    if (grad) return ovl_kernel_m<MODE_OVERLAP, true>(variant);
+    if (mode == MODE_FULL_L2) return grad ? (const void *)&k_gmm_full<false, true> : (const void *)&k_gmm_full<false, false>;
+    if (mode == MODE_FULL_BH) return grad ? (const void *)&k_gmm_full<true, true> : (const void *)&k_gmm_full<true, false>;
     switch (mode) {
-    case MODE_GMM_L2: return ovl_kernel_m<MODE_GMM_L2, false>(variant);
-    case MODE_GMM_BH: return ovl_kernel_m<MODE_GMM_BH, false>(variant);
-    default: return ovl_kernel_m<MODE_OVERLAP, false>(variant);
+    case MODE_GMM_L2: return grad ? ovl_kernel_m<MODE_GMM_L2, true>(variant) : ovl_kernel_m<MODE_GMM_L2, false>(variant);
+    case MODE_GMM_BH: return grad ? ovl_kernel_m<MODE_GMM_BH, true>(variant) : ovl_kernel_m<MODE_GMM_BH, false>(variant);
+    default: return grad ? ovl_kernel_m<MODE_OVERLAP, true>(variant) : ovl_kernel_m<MODE_OVERLAP, false>(variant);
     }
 }
 
@@ -322,13 +567,27 @@ void launch_m(int variant, int grid, size_t lds, hipStream_t s, const OvlLaunch 
     }
 }
 
+template <bool BH, bool GRAD>
+void launch_full(int grid, size_t lds, hipStream_t s, const OvlLaunch &a)
+{
+    hipLaunchKernelGGL((k_gmm_full<BH, GRAD>), dim3(grid), dim3(OVL_THREADS), lds, s, a.pts, (const float4 *)a.psig,
+                       a.coff, a.perm, a.n, a.T, a.qa, a.out, a.cen, a.params, a.grad, a.sig_at, a.cpost);
+}
+
 void launch_ovl(int mode, bool grad, int variant, int grid, size_t lds, hipStream_t s, const OvlLaunch &a)
 {
-    if (grad) return launch_m<MODE_OVERLAP, true>(variant, grid, lds, s, a);
+    if (mode == MODE_FULL_L2) return grad ? launch_full<false, true>(grid, lds, s, a) : launch_full<false, false>(grid, lds, s, a);
+    if (mode == MODE_FULL_BH) return grad ? launch_full<true, true>(grid, lds, s, a) : launch_full<true, false>(grid, lds, s, a);
     switch (mode) {
-    case MODE_GMM_L2: launch_m<MODE_GMM_L2, false>(variant, grid, lds, s, a); break;
-    case MODE_GMM_BH: launch_m<MODE_GMM_BH, false>(variant, grid, lds, s, a); break;
-    default: launch_m<MODE_OVERLAP, false>(variant, grid, lds, s, a); break;
+    case MODE_GMM_L2:
+        grad ? launch_m<MODE_GMM_L2, true>(variant, grid, lds, s, a) : launch_m<MODE_GMM_L2, false>(variant, grid, lds, s, a);
+        break;
+    case MODE_GMM_BH:
+        grad ? launch_m<MODE_GMM_BH, true>(variant, grid, lds, s, a) : launch_m<MODE_GMM_BH, false>(variant, grid, lds, s, a);
+        break;
+    default:
+        grad ? launch_m<MODE_OVERLAP, true>(variant, grid, lds, s, a) : launch_m<MODE_OVERLAP, false>(variant, grid, lds, s, a);
+        break;
     }
 }
 
@@ -348,11 +607,19 @@ OvlDev dev_ptrs(rocket_ctx *ctx, int64_t n)
     return d;
 }
 
-int max_block_pts(int mode) { return mode == MODE_OVERLAP ? OVL_MAX_BLOCK_PTS : GMM_MAX_BLOCK_PTS; }
+bool full_mode(int mode) { return mode == MODE_FULL_L2 || mode == MODE_FULL_BH; }
 
+int max_block_pts(int mode)
+{
+    return mode == MODE_OVERLAP ? OVL_MAX_BLOCK_PTS : full_mode(mode) ? FULL_MAX_BLOCK_PTS : GMM_MAX_BLOCK_PTS;
+}
+
+// Two staged blocks of points, then (per-point-sigma and full-covariance scores) their
+// deviations or shapes in the same order.
 size_t ovl_lds_bytes(int mode, int64_t mx)
 {
-    return (size_t)2 * mx * (sizeof(float2) + (mode == MODE_OVERLAP ? 0 : sizeof(float))) + 16;
+    const size_t per = sizeof(float2) + (mode == MODE_OVERLAP ? 0 : full_mode(mode) ? sizeof(float4) : sizeof(float));
+    return (size_t)2 * mx * per + 16;
 }
 
 }  // namespace
@@ -407,8 +674,14 @@ static void ovl_plan(rocket_ctx *ctx, int T, std::vector<int4> &items, std::vect
 
 // Default 8 clouds per block: the two staged blocks then take ~51 KB of LDS (~77 KB with
 // per-point deviations), so two or three workgroups share a CU and hide each other's LDS and
-// queue latency (measured ~25 % faster than 16 on 2048 clouds of 50..400 points).
-static int ovl_block(rocket_ctx *ctx) { return ctx->opt[ROCKET_OPT_OVL_BLOCK] ? (int)ctx->opt[ROCKET_OPT_OVL_BLOCK] : 8; }
+// queue latency (measured ~25 % faster than 16 on 2048 clouds of 50..400 points).  With a
+// full covariance per point (24 bytes) 4 clouds per block (measured on the same clouds: cost
+// 64 / 79 / 74 ms and adjoint 97 / 116 / 104 ms at 4 / 3 / 8 clouds per block).
+static int ovl_block(rocket_ctx *ctx)
+{
+    if (ctx->opt[ROCKET_OPT_OVL_BLOCK]) return (int)ctx->opt[ROCKET_OPT_OVL_BLOCK];
+    return ctx->ovl.mode == MODE_FULL_L2 || ctx->ovl.mode == MODE_FULL_BH ? 4 : 8;
+}
 static int ovl_variant(rocket_ctx *ctx)
 {
     return ctx->opt[ROCKET_OPT_OVL_VARIANT] ? (int)ctx->opt[ROCKET_OPT_OVL_VARIANT] : 3;
@@ -445,7 +718,7 @@ rocket_status ovl_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, in
     if (n > 0 && (!it->offsets || !it->xy)) return fail(ctx, ROCKET_E_INVALID, "offsets or xy is NULL");
     if (mode == MODE_OVERLAP && (!(it->sigma > 0.0) || !std::isfinite(it->sigma)))
         return fail(ctx, ROCKET_E_INVALID, "sigma must be > 0");
-    if (mode != MODE_OVERLAP && n > 0 && !it->point_sigma)
+    if (mode != MODE_OVERLAP && n > 0 && !it->point_sigma && !(full_mode(mode) && it->point_cov))
         return fail(ctx, ROCKET_E_INVALID, "point_sigma is NULL");
     o.mode = mode;
     if (n >= (1 << 30)) return fail(ctx, ROCKET_E_INVALID, "n too large");
@@ -481,9 +754,10 @@ rocket_status ovl_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, in
     void *mp = nullptr, *pp = nullptr, *sp = nullptr, *fp = nullptr;
     RK_TRY(ws_get(ctx, WS_OVL_META, sizeof(int) * meta.size(), &mp));
     RK_TRY(ws_get(ctx, WS_OVL_PACK, sizeof(float2) * (size_t)std::max<int64_t>(o.total, 1), &pp));
-    const bool gmm = mode != MODE_OVERLAP;
+    const bool gmm = mode != MODE_OVERLAP, full = full_mode(mode);
     if (gmm) {
-        RK_TRY(ws_get(ctx, WS_OVL_SIG, sizeof(float) * (size_t)std::max<int64_t>(o.total, 1), &sp));
+        RK_TRY(ws_get(ctx, WS_OVL_SIG, (full ? sizeof(float4) : sizeof(float)) * (size_t)std::max<int64_t>(o.total, 1),
+                      &sp));
         RK_TRY(ws_get(ctx, WS_FLAGS, 256, &fp));
         hipLaunchKernelGGL(k_ovl_zero, dim3(1), dim3(64), 0, s, (int *)fp);
         RK_HIP(hipGetLastError());
@@ -491,16 +765,25 @@ rocket_status ovl_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, in
     RK_HIP(hipMemcpyAsync(mp, meta.data(), sizeof(int) * meta.size(), hipMemcpyHostToDevice, s));
     if (n > 0) {
         const OvlDev d = dev_ptrs(ctx, n);
+        const unsigned pg = (unsigned)std::min<int64_t>(n, 65535);
         // s~^2 = 2 ln2 s^2 (L2) or 4 ln2 s^2 (Bhattacharya): see the kernel's header comment
         const double sscale = std::sqrt((mode == MODE_GMM_L2 ? 2.0 : 4.0) * 0.69314718055994530942);
-        hipLaunchKernelGGL(k_ovl_pack, dim3((unsigned)std::min<int64_t>(n, 65535)), dim3(256), 0, s,
-                           (const float2 *)it->xy, it->offsets, d.perm, d.coff, d.pts, (int)n,
-                           gmm ? it->point_sigma : nullptr, sscale, gmm ? d.sig : nullptr, (int *)fp);
+        const bool psig = gmm && !full;
+        hipLaunchKernelGGL(k_ovl_pack, dim3(pg), dim3(256), 0, s, (const float2 *)it->xy, it->offsets, d.perm, d.coff,
+                           d.pts, (int)n, psig ? it->point_sigma : nullptr, sscale, psig ? d.sig : nullptr, (int *)fp);
         RK_HIP(hipGetLastError());
+        if (full) {
+            hipLaunchKernelGGL(k_ovl_pack_shape, dim3(pg), dim3(256), 0, s, it->offsets, (const int *)d.perm,
+                               (const int *)d.coff, (int)n, it->point_cov, it->point_cov ? nullptr : it->point_sigma,
+                               (float4 *)d.sig, (int *)fp);
+            RK_HIP(hipGetLastError());
+        }
     }
     int flag = 0;
     if (gmm) RK_HIP(hipMemcpyAsync(&flag, fp, sizeof(int), hipMemcpyDeviceToHost, s));
     RK_HIP(hipStreamSynchronize(s));  // meta staging vector goes out of scope
+    if (flag && full)
+        return fail(ctx, ROCKET_E_INVALID, "a point covariance is not positive definite within [1e-36, 1e36]");
     if (flag) return fail(ctx, ROCKET_E_INVALID, "point_sigma outside [1e-18, 1e18]");
     RK_TRY(ovl_replan(ctx, s));
     if (ctx->opt[ROCKET_OPT_AUTOTUNE] && n >= 64) RK_TRY(ovl_autotune(ctx, s));
@@ -537,12 +820,15 @@ static rocket_status ovl_launch(rocket_ctx *ctx, hipStream_t s, float *out, cons
     a.cen = g ? cen : nullptr;
     a.params = g ? params : nullptr;
     a.grad = g ? grad : nullptr;
-    a.gscale = o.mode == MODE_OVERLAP ? (float)(-1.0 / (2.0 * o.sigma * o.sigma)) : 0.f;
+    a.gscale = o.mode == MODE_OVERLAP ? (float)(-1.0 / (2.0 * o.sigma * o.sigma)) : 0.f;  // per-point sigma: below
     a.psig = o.mode == MODE_OVERLAP ? nullptr : d.sig;
     a.sig_at = (int)(2 * 2 * o.max_block_pts);  // floats: behind 2 blocks of float2 points
-    // per-pair factor: ln2 / pi (L2), 2 (Bhattacharya)
-    a.cpost = o.mode == MODE_GMM_L2 ? (float)(0.69314718055994530942 / 3.14159265358979323846)
-                                    : (o.mode == MODE_GMM_BH ? 2.f : 1.f);
+    // per-pair factor: ln2 / pi (per-point-sigma L2), 1 / (2 pi) (full-covariance L2), 2 (Bhattacharya)
+    a.cpost = o.mode == MODE_GMM_L2    ? (float)(0.69314718055994530942 / 3.14159265358979323846)
+              : o.mode == MODE_FULL_L2 ? (float)(1.0 / (2.0 * 3.14159265358979323846))
+              : (o.mode == MODE_GMM_BH || o.mode == MODE_FULL_BH) ? 2.f
+                                                                   : 1.f;
+    if (o.mode == MODE_GMM_L2 || o.mode == MODE_GMM_BH) a.gscale = (float)(-2.0 * 0.69314718055994530942) * a.cpost;
     RK_TRY(timing_begin(ctx, s));
     launch_ovl(o.mode, g, variant, grid, lds, s, a);
     RK_HIP(hipGetLastError());

@@ -251,8 +251,10 @@ rocket_status rocket_prepare(rocket_ctx *ctx, const rocket_items *items, int64_t
     case ROCKET_NCC_BF16X3:
     case ROCKET_NCC_BF16X6: st = rk::ncc_prepare(ctx, items, n, (int)fn, s); break;
     case ROCKET_GAUSS_OVERLAP: st = rk::ovl_prepare(ctx, items, n, 0, s); break;
-    case ROCKET_GMM_L2: st = rk::ovl_prepare(ctx, items, n, 1, s); break;
-    case ROCKET_GMM_BHATTACHARYA: st = rk::ovl_prepare(ctx, items, n, 2, s); break;
+    case ROCKET_GMM_L2: st = rk::ovl_prepare(ctx, items, n, items->point_cov ? rk::OVL_FULL_L2 : rk::OVL_GMM_L2, s); break;
+    case ROCKET_GMM_BHATTACHARYA:
+        st = rk::ovl_prepare(ctx, items, n, items->point_cov ? rk::OVL_FULL_BH : rk::OVL_GMM_BH, s);
+        break;
     case ROCKET_SPARSE_COSINE: st = rk::sp_prepare(ctx, items, n, s); break;
     case ROCKET_PCE: st = rk::pce_prepare(ctx, items, n, s); break;
     default: st = ROCKET_E_UNSUPPORTED;
@@ -356,6 +358,42 @@ rocket_status rocket_overlap_cost_grad(rocket_ctx *ctx, const rocket_items *clou
     } else if (!(o.valid && o.grad_ready && o.mode == 0 && o.n == n)) {
         return rk::fail(ctx, ROCKET_E_STATE, "clouds is NULL but no clouds of this size were prepared by the previous "
                                              "rocket_overlap_cost_grad");
+    }
+    ctx->stats.n = n;
+    ctx->stats.pairs = P;
+    RK_TRY(rk::ovl_compare(ctx, out_cost, centroids, params, out_grad, s));
+    ctx->stats.workspace_bytes = rk::ws_total(ctx);
+    return ROCKET_OK;
+}
+
+rocket_status rocket_cost_grad(rocket_ctx *ctx, const rocket_items *items, int64_t n, rocket_pair_fn fn,
+                               const float *centroids, const float *params, float *out_cost, float *out_grad,
+                               void *stream)
+{
+    if (fn == ROCKET_GAUSS_OVERLAP)
+        return rocket_overlap_cost_grad(ctx, items, n, centroids, params, out_cost, out_grad, stream);
+    RK_TRY(enter(ctx));
+    if (fn != ROCKET_GMM_L2 && fn != ROCKET_GMM_BHATTACHARYA)
+        return rk::fail(ctx, ROCKET_E_UNSUPPORTED, "cost gradients exist for the three particle scores only");
+    if (n < 0) return rk::fail(ctx, ROCKET_E_INVALID, "n < 0");
+    const int64_t P = n * (n - 1) / 2;
+    if (P > 0 && (!centroids || !params || !out_cost))
+        return rk::fail(ctx, ROCKET_E_INVALID, "centroids, params and out_cost are required");
+    hipStream_t s = (hipStream_t)stream;
+    // full covariances, or the per-point-sigma kernel (isotropic points rotate onto themselves);
+    // with items = NULL the previous preparation's kind is kept
+    const bool full = items ? items->point_cov != nullptr : (ctx->ovl.mode == rk::OVL_FULL_L2 || ctx->ovl.mode == rk::OVL_FULL_BH);
+    const int mode = fn == ROCKET_GMM_L2 ? (full ? rk::OVL_FULL_L2 : rk::OVL_GMM_L2)
+                                         : (full ? rk::OVL_FULL_BH : rk::OVL_GMM_BH);
+    rk::OvlState &o = ctx->ovl;
+    if (items) {
+        ctx->prepared_fn = 0;
+        RK_TRY(rk::ovl_prepare(ctx, items, n, mode, s));
+        ctx->prepared_fn = (int)fn;
+        o.grad_ready = true;
+    } else if (!(o.valid && o.grad_ready && o.mode == mode && o.n == n)) {
+        return rk::fail(ctx, ROCKET_E_STATE, "items is NULL but no clouds of this size were prepared for this score "
+                                             "by the previous rocket_cost_grad");
     }
     ctx->stats.n = n;
     ctx->stats.pairs = P;

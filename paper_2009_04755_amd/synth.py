@@ -145,6 +145,20 @@ def point_sigmas(offsets: np.ndarray, lo: float = 0.01, hi: float = 0.03, config
     return g.uniform(lo, hi, int(offsets[-1])).astype(np.float32)
 
 
+def point_covs(offsets: np.ndarray, lo: float = 0.01, hi: float = 0.03, config: int = 2, salt: int = 0):
+    """Per-localisation uncertainty ellipse as a full covariance (xx, xy, yy) per point (f32
+    [total][3]): semi-axes ~ U[lo, hi] each, orientation ~ U[0, pi)."""
+    g = rng(config, 700 + salt)
+    m = int(offsets[-1])
+    a, b = g.uniform(lo, hi, m), g.uniform(lo, hi, m)
+    th = g.uniform(0.0, np.pi, m)
+    c, s = np.cos(th), np.sin(th)
+    xx = c * c * a * a + s * s * b * b
+    yy = s * s * a * a + c * c * b * b
+    xy = c * s * (a * a - b * b)
+    return np.stack([xx, xy, yy], axis=1).astype(np.float32)
+
+
 def rigid_starts(npairs: int, config: int = 3, salt: int = 0) -> np.ndarray:
     """Per-pair start transform (theta, tx, ty): theta ~ U[-pi, pi), t ~ U[-0.5, 0.5]^2."""
     g = rng(config, salt)
