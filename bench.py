@@ -444,7 +444,7 @@ def pce_pair_fn(ctx, with_cpu=True):
     return res
 
 
-def other_pair_fns(ctx, with_cpu=True):
+def other_pair_fns(ctx, with_cpu=True, autotune=True):
     """Gaussian overlap (2048 uneven clouds), the two per-point-sigma scores and the
     20-step registration, one entry each."""
     import numpy as np
@@ -457,6 +457,10 @@ def other_pair_fns(ctx, with_cpu=True):
     P = 2048 * 2047 // 2
     out = torch.empty(P, device="cuda")
     ctx.set(ovl_variant=0, ovl_block=0)
+    tune = None
+    if autotune:  # untimed setup: clouds per block x inner-loop variant
+        ctx.prepare(cl, "gauss_overlap")
+        tune = ctx.autotune()
     dt, kern = _time_fn(ctx, cl, "gauss_overlap", out, 5, 1)
     cnt = np.diff(off).astype(np.float64)
     terms = (cnt.sum() ** 2 - (cnt ** 2).sum()) / 2
@@ -466,6 +470,9 @@ def other_pair_fns(ctx, with_cpu=True):
                             "kernel_ms": kern * 1e3, "terms_per_s": terms / kern,
                             "roofline": {"bound": "alu", "achieved": terms / kern, "peak": peak_terms,
                                          "unit": "terms/s", "frac": terms / kern / peak_terms}}
+    if tune is not None:
+        res["gauss_overlap"]["autotune"] = dict(tune, candidates="block {4, 8, 16} x variant 1..4")
+    ctx.set(ovl_variant=0, ovl_block=0)  # the other scores run with their defaults
     if with_cpu:
         import oracle
         g = np.random.default_rng(5)
@@ -609,7 +616,7 @@ def other_pair_fns(ctx, with_cpu=True):
     return res
 
 
-def sparse_pair_fn(ctx, with_cpu=True):
+def sparse_pair_fn(ctx, with_cpu=True, autotune=True):
     """Sparse cosine over 8192 composition-vector-like items (about 1.56e9 entries)."""
     import numpy as np
     import torch
@@ -621,6 +628,7 @@ def sparse_pair_fn(ctx, with_cpu=True):
     P = n * (n - 1) // 2
     out = torch.empty(P, device="cuda")
     ctx.prepare(S, "sparse_cosine")
+    tune = ctx.autotune() if autotune else None  # untimed setup: lanes x chunk width
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx.compare(out=out)
@@ -647,6 +655,8 @@ def sparse_pair_fn(ctx, with_cpu=True):
                         "frac": ref_bytes / kern / 1e9 / PEAK_HBM, "algorithmic_bytes_per_launch": ref_bytes,
                         "model": "(n / 2T) * 8 * sum(nnz), T = 16 rows per band",
                         "streaming_model_bytes": byts, "streaming_model_frac": byts / kern / 1e9 / PEAK_HBM}}
+    if tune is not None:
+        res["autotune"] = dict(tune, candidates="lanes {4, 8} x micro-chunk width {automatic, twice that}")
     if with_cpu:
         import oracle
         m = 24  # all pairs among the first 24 items
@@ -674,6 +684,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip the FP32 and two-term split comparison runs")
+    ap.add_argument("--no-autotune", action="store_true", help="skip the autotuner in the untimed setup")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM counter scaling)")
     ap.add_argument("--only", choices=["clouds", "sparse", "cv", "pce", "ooc", "small"],
@@ -706,7 +717,8 @@ def main():
         ctx = Context(0)
         ctx.set(timing=1)
         cpu = not args.no_cpu_baseline
-        run = {"clouds": lambda: other_pair_fns(ctx, cpu), "sparse": lambda: sparse_pair_fn(ctx, cpu),
+        tune = not args.no_autotune
+        run = {"clouds": lambda: other_pair_fns(ctx, cpu, tune), "sparse": lambda: sparse_pair_fn(ctx, cpu, tune),
                "cv": lambda: cv_pipeline(ctx, cpu), "pce": lambda: pce_pair_fn(ctx, cpu),
                "small": lambda: ncc_small(ctx, cpu)}[args.only]
         print(json.dumps({"only": args.only, "record": run()}))
@@ -723,6 +735,13 @@ def main():
         sys.stdout.flush()
         return
 
+    # untimed setup: the autotuner picks the Gram tile shape for this set (cache in a
+    # temporary file, so a second tuning call would reuse it)
+    import tempfile
+    tune_cache = os.path.join(tempfile.mkdtemp(prefix="rocket_tune_"), "tune.json")
+    ctx.set_tune_cache(tune_cache)
+    ctx.prepare(X, "ncc_bf16x6")
+    tune = ctx.autotune() if not args.no_autotune else None
     dt, kern = _time_fn(ctx, X, "ncc_bf16x6", out, args.steps, args.warmup)
     st = ctx.stats()
     value = P * args.steps / dt
@@ -733,7 +752,9 @@ def main():
     T = st["tile"]
     blocks = st["tiles"] * (T // 32) ** 2 - (28 * ((n + T - 1) // T) if T == 256 else 0)
     issued = 6 * 2.0 * 32 * 32 * ((d + 15) // 16 * 16) * blocks
-    traffic = _traffic_from_profile()
+    waves = ctx.get("ncc_waves") or 8
+    # the committed counter file was taken with the default shape (256-item tiles, 8 waves, 2048 K chunks)
+    traffic = _traffic_from_profile() if (T, waves, st["kchunk"]) == (256, 8, 2048) else None
     rec = {
         "metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
@@ -744,7 +765,7 @@ def main():
                    "kchunk": st["kchunk"], "work_items": st["work_items"], "grid": st["grid"]},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_BF16, "traffic": traffic,
-                     "kernel": "k_ncc_gram<256, 256, bf16x6, 8 waves>", "kernel_ms": kern * 1e3,
+                     "kernel": "k_ncc_gram<%d, %d, bf16x6, %d waves>" % (T, T, waves), "kernel_ms": kern * 1e3,
                      "algorithmic_flop_per_launch": flop, "issued_mfma_flop_per_launch": issued,
                      "issued_frac": issued / kern / 1e12 / PEAK_BF16},
     }
@@ -757,6 +778,8 @@ def main():
     # leave the BF16x6 result in `out` for the parity sample
     ctx.allpairs(X, "ncc_bf16x6", out=out)
     torch.cuda.synchronize()
+    if tune is not None:
+        rec["autotune"] = dict(tune, candidates="tile {256, 128} x waves {8, 4} x K chunk {2048, 1024}")
     if traffic is not None:
         # HBM bytes moved by one Gram launch over the bytes of the f32 data set
         rec["roofline"]["R_HBM"] = traffic / (4.0 * n * d)
@@ -767,8 +790,8 @@ def main():
         rec["ncc_out_of_core"] = out_of_core(ctx, X, out)
         del X
         torch.cuda.empty_cache()
-        rec["pair_fns"] = other_pair_fns(ctx, not args.no_cpu_baseline)
-        rec["pair_fns"]["sparse_cosine"] = sparse_pair_fn(ctx, not args.no_cpu_baseline)
+        rec["pair_fns"] = other_pair_fns(ctx, not args.no_cpu_baseline, not args.no_autotune)
+        rec["pair_fns"]["sparse_cosine"] = sparse_pair_fn(ctx, not args.no_cpu_baseline, not args.no_autotune)
         rec["cv_build"] = cv_pipeline(ctx, not args.no_cpu_baseline)
         rec["pair_fns"]["pce"] = pce_pair_fn(ctx, not args.no_cpu_baseline)
     print(json.dumps(rec))

@@ -302,7 +302,7 @@ typedef enum {
                                      * under it, or without a cap into half of the free device memory, by
                                      * running the leaf tiles in batches of one Gram launch + epilogue each
                                      * (same output bit for bit); E_OOM if one tile's partials do not fit */
-    ROCKET_OPT_AUTOTUNE = 12,       /* 1: rocket_prepare of ragged sets runs the tile-shape autotuner */
+    ROCKET_OPT_AUTOTUNE = 12,       /* 1: every rocket_prepare ends with rocket_autotune */
     ROCKET_OPT_TIMING = 13,         /* 1: bracket each compare's main persistent kernel with HIP events on the
                                        launch stream; rocket_get_stats reports its duration (for
                                        rocket_allpairs_host: the whole call's device work) */
@@ -334,6 +334,8 @@ typedef struct {
     int64_t cache_slots;     /* rocket_allpairs_host: device cache slots used (0 otherwise) */
     int64_t cache_loads;     /* rocket_allpairs_host: block loads from host memory; the reload factor is
                                 cache_loads / ceil(n / tile) (1 when every block is loaded once) */
+    int64_t tune_us;         /* the last autotune's wall time in microseconds (0 if none ran) */
+    int64_t tune_cached;     /* 1 when the last autotune applied a shape from the cache file */
 } rocket_stats;
 
 rocket_status rocket_get_stats(const rocket_ctx *ctx, rocket_stats *out /* host */);
@@ -342,11 +344,29 @@ rocket_status rocket_get_stats(const rocket_ctx *ctx, rocket_stats *out /* host 
  * [cap]; *count receives the number of work items.  Synchronises the device. */
 rocket_status rocket_get_ledger(rocket_ctx *ctx, int32_t *out /* host */, int64_t cap, int64_t *count /* host */);
 
-/* Autotuner (cloud pair functions): time every candidate (block size, inner-loop
- * variant) on the whole prepared set and keep the fastest in the context
- * (synchronises; allocates one scratch output).  The chosen values are readable
- * through rocket_get_option.  A no-op for the dense and sparse functions. */
+/* Autotuner of the tile shapes for the prepared set (the batching of uneven items into one
+ * persistent launch, and the dense Gram tiles): every candidate is prepared and one whole
+ * compare is timed with HIP events; the fastest is kept in the context's options (readable
+ * with rocket_get_option) and the set is prepared with it.  Candidates:
+ *   NCC:     tile {256, 128} (n >= 1536) or {128, 64}, waves {8, 4}, K chunk {default,
+ *            default/2} (never longer than the default: FP32 accumulation in the matrix
+ *            cores loses accuracy with chunk length);
+ *   sparse:  lanes per column {4, 8} x micro-chunk width {automatic, twice that};
+ *   clouds:  clouds per block {4, 8, 16} x inner-loop variant 1..4.
+ * NCC tile / waves and the cloud shapes change only the schedule (same output bit for bit);
+ * the K chunk and the sparse shapes change the FP32 summation order (results stay within
+ * the pair function's accuracy).  With a cache file (rocket_set_tune_cache) the choice is
+ * stored under (pair function, GPU architecture, log2 n in half steps, p50 / p90 item size
+ * or log2 d) and reused by later calls with the same key without timing.  Synchronises;
+ * allocates one scratch output when it times.  rocket_get_stats reports tune_us and
+ * tune_cached.  A no-op for PCE.  ROCKET_OPT_AUTOTUNE=1 runs it at the end of every
+ * rocket_prepare. */
 rocket_status rocket_autotune(rocket_ctx *ctx, void *stream);
+
+/* The autotuner's cache file (host path; NULL or "" disables the cache).  The file is
+ * read at every rocket_autotune and rewritten (write to path.tmp, then rename) when a new
+ * key is tuned. */
+rocket_status rocket_set_tune_cache(rocket_ctx *ctx, const char *path /* host */);
 
 /* Host-only planner, no device needed: the divide-and-conquer leaves for n items
  * with tiles of T items (Section IV-B: recursive quadrant split of the upper

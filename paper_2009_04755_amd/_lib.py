@@ -29,7 +29,8 @@ SYMBOLS = ["rocket_create", "rocket_destroy", "rocket_status_str", "rocket_last_
            "rocket_compare", "rocket_allpairs_ex", "rocket_allpairs", "rocket_allpairs_host", "rocket_cv_build",
            "rocket_overlap_cost_grad",
            "rocket_set_option", "rocket_get_option", "rocket_get_stats", "rocket_get_ledger", "rocket_autotune",
-           "rocket_plan_tiles", "rocket_pair_index", "rocket_allpairs_noalloc", "rocket_cost_grad"]
+           "rocket_plan_tiles", "rocket_pair_index", "rocket_allpairs_noalloc", "rocket_cost_grad",
+           "rocket_set_tune_cache"]
 NOALLOC_SCRATCH_BYTES = 64 << 20  # ROCKET_NOALLOC_SCRATCH_BYTES
 
 
@@ -43,7 +44,7 @@ class Items(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in
                 ("n", "pairs", "tiles", "work_items", "grid", "tile", "kchunk", "workspace_bytes", "variant",
-                 "kernel_ns", "cache_slots", "cache_loads")]
+                 "kernel_ns", "cache_slots", "cache_loads", "tune_us", "tune_cached")]
 
 
 class RocketError(RuntimeError):
@@ -103,6 +104,8 @@ def load():
     L.rocket_get_ledger.restype = I32
     L.rocket_autotune.argtypes = [P, P]
     L.rocket_autotune.restype = I32
+    L.rocket_set_tune_cache.argtypes = [P, ctypes.c_char_p]
+    L.rocket_set_tune_cache.restype = I32
     L.rocket_plan_tiles.argtypes = [I64, I64, P, P, I64]
     L.rocket_plan_tiles.restype = I64
     L.rocket_pair_index.argtypes = [I64, I64, I64]

@@ -236,8 +236,21 @@ class Context:
         return SparseSet(cv_off, keys[:total], vals[:total])
 
     def autotune(self):
+        """Tune the tile shape of the prepared set (cached when a cache file is set); returns
+        the options it chose and the tuning time."""
         _lib.check(_lib.load().rocket_autotune(self.handle, _stream()), self.handle)
-        return {k: self.get(k) for k in ("ovl_block", "ovl_variant")}
+        names = {"ncc": ("ncc_tile", "ncc_waves", "ncc_kchunk"), "sparse_cosine": ("sp_lanes", "sp_chunk")}
+        fn = getattr(self, "_fn", "")
+        keys = names["ncc"] if fn.startswith("ncc") else names.get(fn, ("ovl_block", "ovl_variant"))
+        st = self.stats()
+        out = {k: self.get(k) for k in keys}
+        out.update(tune_ms=st["tune_us"] / 1e3, cached=bool(st["tune_cached"]))
+        return out
+
+    def set_tune_cache(self, path: str | None):
+        """Autotuner cache file (JSON); None disables it."""
+        _lib.check(_lib.load().rocket_set_tune_cache(self.handle, path.encode() if path else None), self.handle)
+        return self
 
     def cost_grad(self, clouds: Clouds, centroids, params, fn: str = "gauss_overlap", with_grad: bool = True,
                   reuse: bool = False):

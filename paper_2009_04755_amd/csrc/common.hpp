@@ -156,6 +156,7 @@ struct rocket_ctx {
     // carved from [arena, arena + arena_cap) in call order instead of being allocated.
     char *arena = nullptr;
     size_t arena_cap = 0, arena_used = 0;
+    std::string tune_cache;  // autotuner cache file (empty: no cache)
 };
 
 namespace rk {
@@ -191,6 +192,9 @@ rocket_status ovl_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, in
 rocket_status ovl_compare(rocket_ctx *ctx, float *out, const float *centroids, const float *params, float *grad,
                           hipStream_t s);
 rocket_status ovl_autotune(rocket_ctx *ctx, hipStream_t s);
+rocket_status ovl_replan_public(rocket_ctx *ctx, hipStream_t s);  // rebuild the cloud queue for the current options
+// Autotuner for the prepared set (tune.cpp): cached or timed choice of the tile shape.
+rocket_status autotune(rocket_ctx *ctx, hipStream_t s);
 rocket_status sp_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, hipStream_t s);
 rocket_status sp_compare(rocket_ctx *ctx, float *out, uint32_t *counts, hipStream_t s);
 rocket_status pce_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, hipStream_t s);

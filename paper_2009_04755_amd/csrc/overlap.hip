@@ -786,7 +786,6 @@ rocket_status ovl_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, in
         return fail(ctx, ROCKET_E_INVALID, "a point covariance is not positive definite within [1e-36, 1e36]");
     if (flag) return fail(ctx, ROCKET_E_INVALID, "point_sigma outside [1e-18, 1e18]");
     RK_TRY(ovl_replan(ctx, s));
-    if (ctx->opt[ROCKET_OPT_AUTOTUNE] && n >= 64) RK_TRY(ovl_autotune(ctx, s));
     ctx->stats.tiles = o.tiles;
     ctx->stats.work_items = o.tiles;
     ctx->stats.tile = o.block;
@@ -833,6 +832,16 @@ static rocket_status ovl_launch(rocket_ctx *ctx, hipStream_t s, float *out, cons
     launch_ovl(o.mode, g, variant, grid, lds, s, a);
     RK_HIP(hipGetLastError());
     RK_TRY(timing_end(ctx, s));
+    return ROCKET_OK;
+}
+
+rocket_status ovl_replan_public(rocket_ctx *ctx, hipStream_t s)
+{
+    RK_TRY(ovl_replan(ctx, s));
+    ctx->stats.tiles = ctx->ovl.tiles;
+    ctx->stats.work_items = ctx->ovl.tiles;
+    ctx->stats.tile = ctx->ovl.block;
+    ctx->stats.variant = ovl_variant(ctx);
     return ROCKET_OK;
 }
 

@@ -262,6 +262,7 @@ rocket_status rocket_prepare(rocket_ctx *ctx, const rocket_items *items, int64_t
     if (st == ROCKET_OK) ctx->prepared_fn = (int)fn;
     ctx->stats.n = n;
     ctx->stats.pairs = n * (n - 1) / 2;
+    if (st == ROCKET_OK && ctx->opt[ROCKET_OPT_AUTOTUNE]) st = rk::autotune(ctx, s);
     ctx->stats.workspace_bytes = rk::ws_total(ctx);
     return st;
 }
@@ -463,11 +464,9 @@ rocket_status rocket_get_ledger(rocket_ctx *ctx, int32_t *out, int64_t cap, int6
 rocket_status rocket_autotune(rocket_ctx *ctx, void *stream)
 {
     RK_TRY(enter(ctx));
-    if (ctx->prepared_fn == ROCKET_GAUSS_OVERLAP || ctx->prepared_fn == ROCKET_GMM_L2 ||
-        ctx->prepared_fn == ROCKET_GMM_BHATTACHARYA)
-        return rk::ovl_autotune(ctx, (hipStream_t)stream);
-    if (!ctx->prepared_fn) return rk::fail(ctx, ROCKET_E_STATE, "autotune needs a prepared set");
-    return ROCKET_OK;  // dense and sparse paths have fixed shapes
+    rocket_status st = rk::autotune(ctx, (hipStream_t)stream);
+    ctx->stats.workspace_bytes = rk::ws_total(ctx);
+    return st;
 }
 
 }  // extern "C"
