@@ -119,14 +119,19 @@ typedef enum {
     ROCKET_GMM_L2 = 6,
     ROCKET_GMM_BHATTACHARYA = 7,
     /* Peak-to-correlation energy over all cyclic shifts (the PCE variant of the forensics
-     * comparison, Section V-A).  Items are L x L images, L = 32, 64 or 128, flattened
-     * row-major (dense, dim = L*L, ld >= dim).  With a, b the two items minus their means,
-     *   C(s) = sum_x a(x + s) b(x)  (indices mod L),  s* = argmax C (smallest shift index
-     *   r*L + c on ties),  PCE = C(s*)^2 (L^2 - |N|) / sum_{s outside N} C(s)^2,
-     * N the (2h+1) x (2h+1) cyclic neighbourhood of s*, h = ROCKET_OPT_PCE_RADIUS (5 if 0).
-     * rocket_prepare transforms every item once (FP64 mean, f32 2-D FFT in LDS);
-     * rocket_compare runs one f32 2-D FFT per pair.  out_counts, when given, receives the
-     * peak shift index r*L + c of s* (a(x) ~ b(x - s*)).  A constant item gives NaN. */
+     * comparison, Section V-A).  Items are H x W images flattened row-major (dense,
+     * dim = H*W, ld >= dim), W = ROCKET_OPT_PCE_WIDTH (square if 0).  With a, b the two
+     * items minus their means,
+     *   C(s) = sum_x a(x + s) b(x)  (row index mod H, column index mod W),  s* = argmax C
+     *   (smallest shift index r*W + c on ties),  PCE = C(s*)^2 (H W - |N|) / sum_{s outside N} C(s)^2,
+     * N the (2h+1) x (2h+1) cyclic neighbourhood of s*, h = ROCKET_OPT_PCE_RADIUS (5 if 0),
+     * h < min(H, W)/2.  Square items with L = 32, 64 or 128 run one f32 2-D FFT per pair
+     * inside LDS; otherwise H and W must be powers of two in [16, 2048] (else
+     * ROCKET_E_UNSUPPORTED) and the pair transforms are staged in HBM: two pairs per
+     * complex 2-D FFT, a row pass, a column pass and a peak/energy pass over batches of
+     * pair-pairs (ROCKET_OPT_PCE_BATCH).  rocket_prepare transforms every item once
+     * (FP64 mean and norm, f32 2-D FFT).  out_counts, when given, receives the peak shift
+     * index r*W + c of s* (a(x) ~ b(x - s*)).  A constant item gives NaN. */
     ROCKET_PCE = 8
 } rocket_pair_fn;
 
@@ -309,8 +314,11 @@ typedef enum {
     ROCKET_OPT_CACHE_SLOTS = 14,    /* rocket_allpairs_host: device cache slots, one block of `tile` items each
                                        (0: one per block, i.e. everything stays resident); at least 2 */
     ROCKET_OPT_PCE_RADIUS = 15,     /* ROCKET_PCE: half-width h of the excluded peak neighbourhood (0: 5); h < L/2 */
-    ROCKET_OPT_NCC_WAVES = 16       /* NCC Gram workgroup: 4 or 8 waves (0: 8 for tiles of 128 and 256; tiles of
+    ROCKET_OPT_NCC_WAVES = 16,      /* NCC Gram workgroup: 4 or 8 waves (0: 8 for tiles of 128 and 256; tiles of
                                        64 always use 4) */
+    ROCKET_OPT_PCE_WIDTH = 17,      /* ROCKET_PCE: image width W (items are dim / W rows of W values); 0: square */
+    ROCKET_OPT_PCE_BATCH = 18       /* ROCKET_PCE, staged path: pair-pairs per batch of staged transforms (0: as
+                                       many as fit in 128 MiB of staging; the cap and the arena bound it too) */
 } rocket_option;
 
 rocket_status rocket_set_option(rocket_ctx *ctx, rocket_option opt, int64_t value);
@@ -328,7 +336,7 @@ typedef struct {
     int64_t workspace_bytes; /* device bytes currently held by the context */
     int64_t variant;         /* kernel variant in use: NCC pair function, overlap inner-loop variant, sparse
                                 lanes per column item (a work item covers 1024 / variant column items),
-                                PCE side L */
+                                PCE side L (one LDS tile per pair) or H * 10000 + W (staged path) */
     int64_t kernel_ns;       /* duration of the last main kernel (ROCKET_OPT_TIMING=1), else -1;
                                 reading it waits for that kernel to finish */
     int64_t cache_slots;     /* rocket_allpairs_host: device cache slots used (0 otherwise) */

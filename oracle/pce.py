@@ -4,9 +4,10 @@ The forensics application compares camera noise patterns; its PCE variant (Secti
 names the comparison metric, the stage table names PCE) correlates two patterns over all
 cyclic 2-D shifts and scores the sharpness of the highest peak:
 
-  C(s)  = sum_x a(x + s) b(x)              (a, b: items minus their means; indices mod L)
+  C(s)  = sum_x a(x + s) b(x)              (a, b: H x W items minus their means; row
+                                            index mod H, column index mod W)
   s*    = argmax_s C(s)                     (first in row-major order on ties)
-  PCE   = C(s*)^2 (L^2 - |N|) / sum_{s not in N} C(s)^2,
+  PCE   = C(s*)^2 (H W - |N|) / sum_{s not in N} C(s)^2,
 
 N the (2h+1) x (2h+1) cyclic neighbourhood of s* (h = 5 by default).  C is evaluated as
 the inverse FFT of A conj(B) (numpy FFT, FP64).
@@ -42,11 +43,13 @@ def pce(a: np.ndarray, b: np.ndarray, h: int = 5, peak=None):
     return pce_of_surface(correlation(a, b), h, peak)
 
 
-def pce_pairs(X: np.ndarray, L: int, pi, pj, h: int = 5):
-    """(pce float64 [np], peak int64 [np]) for the listed pairs of items X[k] (L*L values)."""
+def pce_pairs(X: np.ndarray, L, pi, pj, h: int = 5):
+    """(pce float64 [np], peak int64 [np]) for the listed pairs of items X[k]: L x L values
+    (L an int) or H x W values (L a pair (H, W)), row-major."""
+    H, W = (L, L) if np.isscalar(L) else (int(L[0]), int(L[1]))
     X = np.asarray(X, dtype=np.float32)
     out = np.empty(len(pi))
     pk = np.empty(len(pi), dtype=np.int64)
     for t, (i, j) in enumerate(zip(pi, pj)):
-        out[t], pk[t] = pce(X[i].reshape(L, L), X[j].reshape(L, L), h)
+        out[t], pk[t] = pce(X[i].reshape(H, W), X[j].reshape(H, W), h)
     return out, pk

@@ -22,7 +22,7 @@ FN_BY_NAME = {"ncc_fp32": NCC_FP32, "ncc_bf16x3": NCC_BF16X3, "ncc_bf16x6": NCC_
 
 OPT = {"ncc_tile": 1, "ncc_kchunk": 2, "grid": 3, "queue_order": 4, "seed": 5, "ledger": 6, "ovl_block": 7,
        "ovl_variant": 8, "sp_lanes": 9, "sp_chunk": 10, "workspace_cap": 11, "autotune": 12, "timing": 13,
-       "cache_slots": 14, "pce_radius": 15, "ncc_waves": 16}
+       "cache_slots": 14, "pce_radius": 15, "ncc_waves": 16, "pce_width": 17, "pce_batch": 18}
 
 # every symbol include/rocket.h declares
 SYMBOLS = ["rocket_create", "rocket_destroy", "rocket_status_str", "rocket_last_error", "rocket_prepare",

@@ -33,6 +33,7 @@ enum Slot {
     WS_SP_BOUNDS,        // chunk boundaries (units of 2^ulog keys)
     WS_SP_FINE,          // 64-key counts of micro-chunks that overflow a band's chunk
     WS_PCE_SPEC,         // PCE item spectra (complex f32, natural order)
+    WS_PCE_STAGE,        // PCE staged transforms of one batch of pair-pairs (large images)
     WS_CV_K,             // dense K-string counts of a group of species (kept zeroed between calls)
     WS_CV_AUX,           // (K-1)- and (K-2)-string counts, chunk occupancy, totals
     WS_COUNT
@@ -112,6 +113,9 @@ struct PceState {
     int L = 0;
     QueueArgs qa{};
     bool valid = false;
+    bool big = false;  // H x W items through the staged multi-pass path
+    int H = 0, W = 0;
+    std::vector<int4> h_pp;  // pair-pairs (i, j, k, l) in tile order (staged path)
 };
 
 // Composition-vector builder: whether the dense K-string count array is all zeros.
@@ -199,6 +203,9 @@ rocket_status sp_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, hip
 rocket_status sp_compare(rocket_ctx *ctx, float *out, uint32_t *counts, hipStream_t s);
 rocket_status pce_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, hipStream_t s);
 rocket_status pce_compare(rocket_ctx *ctx, float *out, uint32_t *peak, hipStream_t s);
+bool pce_big_shape(int64_t H, int64_t W);
+rocket_status pce_big_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, int H, int W, hipStream_t s);
+rocket_status pce_big_compare(rocket_ctx *ctx, float *out, uint32_t *peak, int h, hipStream_t s);
 rocket_status cv_build(rocket_ctx *ctx, const uint8_t *res, const int64_t *offsets, int64_t n, int K,
                        int64_t *cv_off, int64_t *keys, float *vals, int64_t capacity, hipStream_t s);
 

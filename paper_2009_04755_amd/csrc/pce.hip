@@ -427,12 +427,32 @@ rocket_status pce_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, hi
     PceState &p = ctx->pce;
     p.valid = false;
     if (n > 0 && !it->dense) return fail(ctx, ROCKET_E_INVALID, "dense is NULL");
-    const int L = side_of(it->dim);
-    if (!L) return fail(ctx, ROCKET_E_UNSUPPORTED, "PCE items must be L x L with L = 32, 64 or 128");
     if (it->ld < it->dim) return fail(ctx, ROCKET_E_INVALID, "ld < dim");
     if (n >= (1 << 30)) return fail(ctx, ROCKET_E_INVALID, "n too large");
+    const int64_t wopt = ctx->opt[ROCKET_OPT_PCE_WIDTH];
+    const int L = wopt ? (wopt * wopt == it->dim ? side_of(it->dim) : 0) : side_of(it->dim);
     p.n = n;
     p.L = L;
+    p.big = false;
+    if (!L) {
+        // H x W with W = ROCKET_OPT_PCE_WIDTH (square if 0): the staged multi-pass path
+        int64_t W = wopt;
+        if (!W) {
+            W = (int64_t)std::llround(std::sqrt((double)it->dim));
+            if (W * W != it->dim) W = 0;
+        }
+        const int64_t H = W > 0 && it->dim % W == 0 ? it->dim / W : 0;
+        if (!H || !pce_big_shape(H, W))
+            return fail(ctx, ROCKET_E_UNSUPPORTED,
+                        "PCE items must be L x L with L = 32, 64 or 128, or H x W (W = ROCKET_OPT_PCE_WIDTH, square "
+                        "if 0) with H and W powers of two in [16, 2048]");
+        p.big = true;
+        p.H = (int)H;
+        p.W = (int)W;
+        RK_TRY(pce_big_prepare(ctx, it, n, p.H, p.W, s));
+        p.valid = true;
+        return ROCKET_OK;
+    }
     void *spec = nullptr;
     const size_t spec_bytes = (size_t)std::max<int64_t>(n, 1) * L * (L / 2 + 1) * sizeof(float2);
     RK_TRY(ws_get(ctx, WS_PCE_SPEC, spec_bytes + sizeof(int) * (size_t)std::max<int64_t>(n, 1), &spec));
@@ -478,11 +498,13 @@ rocket_status pce_compare(rocket_ctx *ctx, float *out, uint32_t *peak, hipStream
 {
     PceState &p = ctx->pce;
     if (!p.valid) return fail(ctx, ROCKET_E_STATE, "PCE set not prepared");
+    const int h = ctx->opt[ROCKET_OPT_PCE_RADIUS] ? (int)ctx->opt[ROCKET_OPT_PCE_RADIUS] : 5;
+    if (h >= (p.big ? std::min(p.H, p.W) : p.L) / 2)
+        return fail(ctx, ROCKET_E_INVALID, "PCE neighbourhood radius must be < min(H, W)/2");
     if (p.n < 2 || p.tiles == 0) return ROCKET_OK;
+    if (p.big) return pce_big_compare(ctx, out, peak, h, s);
     if (ctx->queue_owner != QOWN_PCE) return fail(ctx, ROCKET_E_STATE, "queue was replanned by another prepare");
     const int L = p.L;
-    const int h = ctx->opt[ROCKET_OPT_PCE_RADIUS] ? (int)ctx->opt[ROCKET_OPT_PCE_RADIUS] : 5;
-    if (h >= L / 2) return fail(ctx, ROCKET_E_INVALID, "PCE neighbourhood radius must be < L/2");
     const size_t lds = L == 32 ? pce_lds<32>() : L == 64 ? pce_lds<64>() : pce_lds<128>();
     const void *kp = L == 32 ? pce_kernel<32>() : L == 64 ? pce_kernel<64>() : pce_kernel<128>();
     RK_HIP(hipFuncSetAttribute(kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));

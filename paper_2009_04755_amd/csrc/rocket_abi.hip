@@ -406,7 +406,7 @@ rocket_status rocket_cost_grad(rocket_ctx *ctx, const rocket_items *items, int64
 rocket_status rocket_set_option(rocket_ctx *ctx, rocket_option opt, int64_t value)
 {
     if (!ctx) return rk::fail(nullptr, ROCKET_E_INVALID, "ctx is NULL");
-    if (opt < ROCKET_OPT_NCC_TILE || opt > ROCKET_OPT_NCC_WAVES) return rk::fail(ctx, ROCKET_E_UNSUPPORTED, "option");
+    if (opt < ROCKET_OPT_NCC_TILE || opt > ROCKET_OPT_PCE_BATCH) return rk::fail(ctx, ROCKET_E_UNSUPPORTED, "option");
     if (value < 0) return rk::fail(ctx, ROCKET_E_INVALID, "negative option value");
     if (opt == ROCKET_OPT_NCC_TILE && value != 0 && value != 64 && value != 128 && value != 256)
         return rk::fail(ctx, ROCKET_E_INVALID, "NCC tile must be 0, 64, 128 or 256");
@@ -428,7 +428,7 @@ rocket_status rocket_set_option(rocket_ctx *ctx, rocket_option opt, int64_t valu
 rocket_status rocket_get_option(const rocket_ctx *ctx, rocket_option opt, int64_t *value)
 {
     if (!ctx || !value) return rk::fail(nullptr, ROCKET_E_INVALID, "NULL argument");
-    if (opt < ROCKET_OPT_NCC_TILE || opt > ROCKET_OPT_NCC_WAVES) return ROCKET_E_UNSUPPORTED;
+    if (opt < ROCKET_OPT_NCC_TILE || opt > ROCKET_OPT_PCE_BATCH) return ROCKET_E_UNSUPPORTED;
     *value = ctx->opt[opt];
     return ROCKET_OK;
 }

@@ -321,19 +321,22 @@ def proteomes(n: int, n_families: int = 4000, len_min: int = 100, len_max: int =
     return np.concatenate(parts) if parts else np.zeros(0, np.uint8), np.array(off, dtype=np.int64)
 
 
-def noise_images(n: int, L: int, nsrc: int = 8, amp: float = 0.05, p_shift: float = 0.25, config: int = 6,
+def noise_images(n: int, L, nsrc: int = 8, amp: float = 0.05, p_shift: float = 0.25, config: int = 6,
                  salt: int = 0):
-    """Camera-noise-like L x L images (flattened, f32 [n][L*L]): item = amp * source[c] + N(0, 1)
-    with c uniform over ``nsrc`` N(0, 1) sources; with probability ``p_shift`` the source is
-    cyclically shifted by a uniform (dy, dx) (a crop taken at another offset).
+    """Camera-noise-like images of L x L (L an int) or H x W (L a pair) values, flattened
+    row-major (f32 [n][H*W]): item = amp * source[c] + N(0, 1) with c uniform over ``nsrc``
+    N(0, 1) sources; with probability ``p_shift`` the source is cyclically shifted by a
+    uniform (dy, dx) (a crop taken at another offset).
     Returns (images, source index, shift (dy, dx) per item)."""
+    H, W = (L, L) if np.isscalar(L) else (int(L[0]), int(L[1]))
     g = rng(config, salt)
-    src = g.standard_normal((nsrc, L, L))
+    src = g.standard_normal((nsrc, H, W))
     c = g.integers(0, nsrc, n)
     shifted = g.random(n) < p_shift
-    sh = np.where(shifted[:, None], g.integers(0, L, (n, 2)), 0)
-    X = np.empty((n, L * L), dtype=np.float32)
+    sh = np.where(shifted[:, None], np.stack([g.integers(0, H, n), g.integers(0, W, n)], axis=1), 0) \
+        if H != W else np.where(shifted[:, None], g.integers(0, H, (n, 2)), 0)
+    X = np.empty((n, H * W), dtype=np.float32)
     for i in range(n):
         s = np.roll(src[c[i]], (int(sh[i, 0]), int(sh[i, 1])), axis=(0, 1))
-        X[i] = (amp * s + g.standard_normal((L, L))).reshape(-1)
+        X[i] = (amp * s + g.standard_normal((H, W))).reshape(-1)
     return X, c, sh

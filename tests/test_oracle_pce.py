@@ -59,3 +59,46 @@ def test_neighbourhood_wraps_around():
     C[8, 8] = 1.0     # outside
     v, p = pce.pce_of_surface(C, h=1)
     assert p == 0 and abs(v - 100.0 * (256 - 9) / 1.0) < 1e-9
+
+
+def test_rectangular_correlation_matches_explicit_sum():
+    # H != W catches a transposed axis or a modulus taken over the wrong side
+    g = np.random.default_rng(3)
+    a = g.standard_normal((4, 6))
+    b = g.standard_normal((4, 6))
+    A, B = a - a.mean(), b - b.mean()
+    C = np.zeros((4, 6))
+    for sr in range(4):
+        for sc in range(6):
+            C[sr, sc] = sum(A[(r + sr) % 4, (c + sc) % 6] * B[r, c] for r in range(4) for c in range(6))
+    np.testing.assert_allclose(pce.correlation(a, b), C, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("H,W", [(256, 512), (1024, 1024)])
+def test_large_correlation_matches_explicit_sums_at_sampled_shifts(H, W):
+    g = np.random.default_rng(H + W)
+    a = g.standard_normal((H, W))
+    b = 0.3 * np.roll(a, (17, W - 5), axis=(0, 1)) + g.standard_normal((H, W))
+    C = pce.correlation(a, b)
+    A, B = a - a.mean(), b - b.mean()
+    shifts = [(0, 0), (H - 17, 5), (H - 1, W - 1), (1, 0), (0, 1)] + \
+        [tuple(s) for s in np.stack([g.integers(0, H, 15), g.integers(0, W, 15)], axis=1)]
+    scale = np.sqrt(np.sum(A * A) * np.sum(B * B))
+    for sr, sc in shifts:
+        want = np.sum(np.roll(A, (-sr, -sc), axis=(0, 1)) * B)  # sum_x a(x + s) b(x)
+        assert abs(C[sr, sc] - want) <= 1e-12 * scale, (sr, sc)
+    # b holds a copy of a shifted by (17, -5): a(x) ~ b(x - s*) at s* = (-17, 5)
+    assert int(np.argmax(C)) == (H - 17) * W + 5
+
+
+@pytest.mark.parametrize("H,W,k,h,axis", [(16, 32, 3, 2, 1), (32, 16, 3, 2, 1), (64, 16, 5, 3, 0)])
+def test_rectangular_cosine_wave_closed_form(H, W, k, h, axis):
+    # a = b = cos(2 pi k t / n) along one axis of n values: C(s) = (H W / 2) cos(2 pi k s_axis / n),
+    # PCE = (H W - (2h+1)^2) / (H W / 2 - (2h+1) S),  S = sum_{|t|<=h} cos^2(2 pi k t / n)
+    n = (H, W)[axis]
+    wave = np.cos(2 * np.pi * k * np.arange(n) / n)
+    a = np.tile(wave, (H, 1)) if axis == 1 else np.tile(wave[:, None], (1, W))
+    v, p = pce.pce(a, a, h)
+    S = sum(np.cos(2 * np.pi * k * t / n) ** 2 for t in range(-h, h + 1))
+    want = (H * W - (2 * h + 1) ** 2) / (H * W / 2 - (2 * h + 1) * S)
+    assert p == 0 and abs(v - want) <= 1e-9 * want
