@@ -318,7 +318,7 @@ typedef enum {
                                        64 always use 4) */
     ROCKET_OPT_PCE_WIDTH = 17,      /* ROCKET_PCE: image width W (items are dim / W rows of W values); 0: square */
     ROCKET_OPT_PCE_BATCH = 18       /* ROCKET_PCE, staged path: pair-pairs per batch of staged transforms (0: as
-                                       many as fit in 128 MiB of staging; the cap and the arena bound it too) */
+                                       many as fit in 512 MiB of staging; the cap and the arena bound it too) */
 } rocket_option;
 
 rocket_status rocket_set_option(rocket_ctx *ctx, rocket_option opt, int64_t value);

@@ -106,18 +106,19 @@ def test_batches_change_only_the_schedule(ctx):
     for b in (1, 7):
         got, gpk = _run(ctx, X, 256, pce_batch=b)
         assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)) and np.array_equal(gpk, rpk)
-    # a capped workspace bounds the batch the same way: room for three staged transforms of
-    # 128 x 256 complex f32 plus 4 block statistics of 32 bytes (allocations are rounded to
-    # 2 MiB); one byte less than one transform fails with E_OOM
+    # a capped workspace bounds the batch the same way: room for k staged transforms of
+    # 128 x 256 complex f32 and their block statistics (a few hundred bytes each, counted
+    # here as 4 KiB; allocations are rounded to 2 MiB) gives batches of k; room for less
+    # than one transform fails with E_OOM
     from paper_2009_04755_amd import Context
     from paper_2009_04755_amd._lib import RocketError, E_OOM
     Xd = torch.from_numpy(X).cuda()
-    per = 128 * 256 * 8 + 4 * 32
+    per = 128 * 256 * 8 + 4096
     for k, ok in ((3, True), (1, True), (0, False)):
         c2 = Context(0).set(pce_width=256)
         c2.prepare(Xd, "pce")
         base = c2.stats()["workspace_bytes"]
-        c2.set(workspace_cap=base + (2 << 20) + k * per + (0 if ok else per - 1))
+        c2.set(workspace_cap=base + (2 << 20) + (k * per if ok else 128 * 256 * 8 - 1))
         if ok:
             got, gpk = c2.compare(counts=True)
             assert np.array_equal(got.cpu().numpy().view(np.uint32), ref.view(np.uint32))
@@ -161,8 +162,8 @@ def test_errors(ctx):
 
 
 def test_workload_sampled(ctx):
-    # the benchmark's staged workload: 256 noise images of 1024 x 1024 (32,640 pairs, batches
-    # of 16 two-pair transforms), sampled pairs against the oracle
+    # the benchmark's staged workload and launch configuration: 256 noise images of 1024 x 1024
+    # (32,640 pairs, default batches of 64 two-pair transforms), sampled pairs against the oracle
     announce("pce staged n=256 1024x1024 sampled")
     n = 256
     X, c, sh = synth.noise_images(n, 1024, nsrc=16, amp=0.3, config=6, salt=1)
