@@ -516,6 +516,18 @@ def pce_big_pair_fn(ctx, with_cpu=True):
     return res
 
 
+def valu_probe():
+    """Measured issue rates behind the VALU rooflines: FP32 FMA, v_exp_f32 and v_rcp_f32 in
+    independent chains (rocket_probe_valu), against the lane-slot peak used as denominator."""
+    from paper_2009_04755_amd import probe_valu
+    r = probe_valu(0)
+    r.update({"lane_slot_peak": VALU_LANE_OPS, "fma_frac_of_peak": r["fma_per_s"] / VALU_LANE_OPS,
+              "exp2_frac_of_quarter_peak": r["exp2_per_s"] / (VALU_LANE_OPS / 4),
+              "rcp_frac_of_quarter_peak": r["rcp_per_s"] / (VALU_LANE_OPS / 4),
+              "exp2_cost_in_fma": r["fma_per_s"] / r["exp2_per_s"], "rcp_cost_in_fma": r["fma_per_s"] / r["rcp_per_s"]})
+    return r
+
+
 def other_pair_fns(ctx, with_cpu=True, autotune=True):
     """Gaussian overlap (2048 uneven clouds), the two per-point-sigma scores and the
     20-step registration, one entry each."""
@@ -759,7 +771,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="skip the autotuner in the untimed setup")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM counter scaling)")
-    ap.add_argument("--only", choices=["clouds", "sparse", "cv", "pce", "pce_big", "ooc", "small"],
+    ap.add_argument("--only", choices=["clouds", "sparse", "cv", "pce", "pce_big", "ooc", "small", "valu"],
                     help="run only this secondary workload (for profiling it) and print its record; "
                          "clouds = overlap, GMM L2 / Bhattacharya and the registration gradient; "
                          "small = the 256 x 4096 NCC workload")
@@ -792,7 +804,7 @@ def main():
         tune = not args.no_autotune
         run = {"clouds": lambda: other_pair_fns(ctx, cpu, tune), "sparse": lambda: sparse_pair_fn(ctx, cpu, tune),
                "cv": lambda: cv_pipeline(ctx, cpu), "pce": lambda: pce_pair_fn(ctx, cpu),
-               "pce_big": lambda: pce_big_pair_fn(ctx, cpu),
+               "pce_big": lambda: pce_big_pair_fn(ctx, cpu), "valu": valu_probe,
                "small": lambda: ncc_small(ctx, cpu)}[args.only]
         print(json.dumps({"only": args.only, "record": run()}))
         sys.stdout.flush()
@@ -863,6 +875,7 @@ def main():
         rec["ncc_out_of_core"] = out_of_core(ctx, X, out)
         del X
         torch.cuda.empty_cache()
+        rec["valu_probe"] = valu_probe()
         rec["pair_fns"] = other_pair_fns(ctx, not args.no_cpu_baseline, not args.no_autotune)
         rec["pair_fns"]["sparse_cosine"] = sparse_pair_fn(ctx, not args.no_cpu_baseline, not args.no_autotune)
         rec["cv_build"] = cv_pipeline(ctx, not args.no_cpu_baseline)

@@ -376,6 +376,14 @@ rocket_status rocket_autotune(rocket_ctx *ctx, void *stream);
  * key is tuned. */
 rocket_status rocket_set_tune_cache(rocket_ctx *ctx, const char *path /* host */);
 
+/* Measurement aid for the VALU-bound rooflines (not part of the pair computation): issue
+ * rates on `device`, in instructions per second over all lanes, of dependent chains of
+ * FP32 FMA (v_fma_f32), v_exp_f32 and v_rcp_f32, eight independent chains per lane and
+ * eight waves per SIMD of every CU, each timed with HIP events over one launch (~10 ms in
+ * all).  Outputs are host doubles.  Allocates and frees a small sink buffer; synchronises. */
+rocket_status rocket_probe_valu(int device, double *fma_per_s /* host */, double *exp2_per_s /* host */,
+                                double *rcp_per_s /* host */);
+
 /* Host-only planner, no device needed: the divide-and-conquer leaves for n items
  * with tiles of T items (Section IV-B: recursive quadrant split of the upper
  * triangle, empty quadrants skipped), in visiting order (top-left, top-right,

@@ -9,4 +9,4 @@ package is a thin ctypes binding (``api``) plus seeded input generators
 (``synth``).
 """
 from .api import (Clouds, Context, OverlapCost, SparseSet, allpairs, allpairs_noalloc, default_context,  # noqa: F401
-                  num_pairs, pair_index, plan_tiles, register)
+                  num_pairs, pair_index, plan_tiles, probe_valu, register)

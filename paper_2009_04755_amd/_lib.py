@@ -30,7 +30,7 @@ SYMBOLS = ["rocket_create", "rocket_destroy", "rocket_status_str", "rocket_last_
            "rocket_overlap_cost_grad",
            "rocket_set_option", "rocket_get_option", "rocket_get_stats", "rocket_get_ledger", "rocket_autotune",
            "rocket_plan_tiles", "rocket_pair_index", "rocket_allpairs_noalloc", "rocket_cost_grad",
-           "rocket_set_tune_cache"]
+           "rocket_set_tune_cache", "rocket_probe_valu"]
 NOALLOC_SCRATCH_BYTES = 64 << 20  # ROCKET_NOALLOC_SCRATCH_BYTES
 
 
@@ -94,6 +94,9 @@ def load():
     L.rocket_overlap_cost_grad.restype = I32
     L.rocket_cost_grad.argtypes = [P, IT, I64, I32, P, P, P, P, P]
     L.rocket_cost_grad.restype = I32
+    L.rocket_probe_valu.argtypes = [I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double)]
+    L.rocket_probe_valu.restype = I32
     L.rocket_set_option.argtypes = [P, I32, I64]
     L.rocket_set_option.restype = I32
     L.rocket_get_option.argtypes = [P, I32, ctypes.POINTER(I64)]

@@ -353,6 +353,14 @@ def allpairs_noalloc(x, fn: str, out, counts=None):
     return out
 
 
+def probe_valu(device: int = 0) -> dict:
+    """Issue rates (instructions/s over all lanes) of FP32 FMA, v_exp_f32 and v_rcp_f32 on
+    ``device`` (rocket_probe_valu): the measured denominators of the VALU rooflines."""
+    a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _lib.check(_lib.load().rocket_probe_valu(int(device), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), None)
+    return {"fma_per_s": a.value, "exp2_per_s": b.value, "rcp_per_s": c.value}
+
+
 def plan_tiles(n: int, T: int):
     """Host-only divide-and-conquer leaves (bi, bj) for n items and tile T."""
     import numpy as np
