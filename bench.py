@@ -134,6 +134,23 @@ def _host_info():
     return {"affinity_cpus": len(os.sched_getaffinity(0)), "cpu_model": model}
 
 
+def _trace_summary(tr, grid):
+    """Load balance of one traced persistent launch: span from the first start to the last
+    end, the fraction of grid x span that workgroups spent in work items, per-XCD busy
+    fractions (workgroup b on XCD b mod 8), and the tail after the first workgroup ran dry."""
+    import numpy as np
+    ran = tr[tr["workgroup"] >= 0]
+    span = float(ran["end_ns"].max() - ran["start_ns"].min())
+    busy = float(np.sum(ran["end_ns"] - ran["start_ns"]))
+    last = np.array([ran["end_ns"][ran["workgroup"] == w].max() for w in np.unique(ran["workgroup"])])
+    xcd = ran["workgroup"] % 8
+    per_xcd = [float(np.sum((ran["end_ns"] - ran["start_ns"])[xcd == x])) / (span * grid / 8) for x in range(8)]
+    return {"items": int(tr.size), "items_run": int(ran.size), "workgroups": int(grid), "span_ms": span * 1e-6,
+            "busy_frac": busy / (span * grid), "busy_frac_per_xcd": per_xcd,
+            "tail_ms": float(last.max() - last.min()) * 1e-6,
+            "item_ms_p50_p99": [float(np.percentile(ran["end_ns"] - ran["start_ns"], q)) * 1e-6 for q in (50, 99)]}
+
+
 def _ensure_built():
     from paper_2009_04755_amd import _lib
     if not os.path.exists(_lib.LIB_PATH):
@@ -860,9 +877,13 @@ def main():
                    "frac_of_own_peak": flop / kern2 / 1e12 / peak}
     if "ncc_fp32" in rec:
         rec["bf16x6_speedup_vs_fp32"] = value / rec["ncc_fp32"]["pairs_per_s"]
-    # leave the BF16x6 result in `out` for the parity sample
+    # leave the BF16x6 result in `out` for the parity sample, from one untimed step with the
+    # per-tile trace on (the queue's load balance)
+    ctx.set(trace=1)
     ctx.allpairs(X, "ncc_bf16x6", out=out)
     torch.cuda.synchronize()
+    rec["queue_trace"] = _trace_summary(ctx.trace(), ctx.stats()["grid"])
+    ctx.set(trace=0)
     if tune is not None:
         rec["autotune"] = dict(tune, candidates="tile {256, 128} x waves {8, 4} x K chunk {2048, 1024}")
     if traffic is not None:

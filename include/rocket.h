@@ -317,8 +317,10 @@ typedef enum {
     ROCKET_OPT_NCC_WAVES = 16,      /* NCC Gram workgroup: 4 or 8 waves (0: 8 for tiles of 128 and 256; tiles of
                                        64 always use 4) */
     ROCKET_OPT_PCE_WIDTH = 17,      /* ROCKET_PCE: image width W (items are dim / W rows of W values); 0: square */
-    ROCKET_OPT_PCE_BATCH = 18       /* ROCKET_PCE, staged path: pair-pairs per batch of staged transforms (0: as
+    ROCKET_OPT_PCE_BATCH = 18,      /* ROCKET_PCE, staged path: pair-pairs per batch of staged transforms (0: as
                                        many as fit in 512 MiB of staging; the cap and the arena bound it too) */
+    ROCKET_OPT_TRACE = 19           /* 1: the persistent kernels time-stamp every work item (rocket_get_trace); set
+                                       before rocket_prepare, like ROCKET_OPT_LEDGER */
 } rocket_option;
 
 rocket_status rocket_set_option(rocket_ctx *ctx, rocket_option opt, int64_t value);
@@ -347,6 +349,24 @@ typedef struct {
 } rocket_stats;
 
 rocket_status rocket_get_stats(const rocket_ctx *ctx, rocket_stats *out /* host */);
+
+/* Per-tile trace of the last compare that ran a persistent queue (Section IV-C's profiling
+ * of when each job ran where), with ROCKET_OPT_TRACE set to 1 before its rocket_prepare.
+ * One record per work item in queue order: its tile (block row, block column, NCC split-K
+ * chunk or 0), the persistent workgroup that ran it (hardware places workgroup b on XCD
+ * b mod 8) and its start and end on the device's constant-rate wall clock, in ns after the
+ * earliest start.  A work item ends when its workgroup next pops the queue.  Items that did
+ * not run have workgroup -1.  *count receives the number of work items; at most cap
+ * records are written to out (host; NULL with cap 0 queries the count).  Synchronises the
+ * device.  ROCKET_E_STATE without a trace (option unset, or a path without a queue: the
+ * staged PCE path, the host-resident NCC path). */
+typedef struct {
+    int32_t tile_i, tile_j; /* block row and block column of the work item's tile */
+    int32_t chunk;          /* NCC split-K chunk (0 for the other pair functions) */
+    int32_t workgroup;      /* persistent workgroup that ran it, -1 if none */
+    int64_t start_ns, end_ns;
+} rocket_trace_rec;
+rocket_status rocket_get_trace(rocket_ctx *ctx, rocket_trace_rec *out /* host */, int64_t cap, int64_t *count /* host */);
 
 /* Copy the pop counts of the last compare (ROCKET_OPT_LEDGER=1) into host array out
  * [cap]; *count receives the number of work items.  Synchronises the device. */

@@ -22,7 +22,8 @@ FN_BY_NAME = {"ncc_fp32": NCC_FP32, "ncc_bf16x3": NCC_BF16X3, "ncc_bf16x6": NCC_
 
 OPT = {"ncc_tile": 1, "ncc_kchunk": 2, "grid": 3, "queue_order": 4, "seed": 5, "ledger": 6, "ovl_block": 7,
        "ovl_variant": 8, "sp_lanes": 9, "sp_chunk": 10, "workspace_cap": 11, "autotune": 12, "timing": 13,
-       "cache_slots": 14, "pce_radius": 15, "ncc_waves": 16, "pce_width": 17, "pce_batch": 18}
+       "cache_slots": 14, "pce_radius": 15, "ncc_waves": 16, "pce_width": 17, "pce_batch": 18,
+       "trace": 19}
 
 # every symbol include/rocket.h declares
 SYMBOLS = ["rocket_create", "rocket_destroy", "rocket_status_str", "rocket_last_error", "rocket_prepare",
@@ -30,8 +31,13 @@ SYMBOLS = ["rocket_create", "rocket_destroy", "rocket_status_str", "rocket_last_
            "rocket_overlap_cost_grad",
            "rocket_set_option", "rocket_get_option", "rocket_get_stats", "rocket_get_ledger", "rocket_autotune",
            "rocket_plan_tiles", "rocket_pair_index", "rocket_allpairs_noalloc", "rocket_cost_grad",
-           "rocket_set_tune_cache", "rocket_probe_valu"]
+           "rocket_set_tune_cache", "rocket_probe_valu", "rocket_get_trace"]
 NOALLOC_SCRATCH_BYTES = 64 << 20  # ROCKET_NOALLOC_SCRATCH_BYTES
+
+
+class TraceRec(ctypes.Structure):
+    _fields_ = [("tile_i", ctypes.c_int32), ("tile_j", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("workgroup", ctypes.c_int32), ("start_ns", ctypes.c_int64), ("end_ns", ctypes.c_int64)]
 
 
 class Items(ctypes.Structure):
@@ -94,6 +100,8 @@ def load():
     L.rocket_overlap_cost_grad.restype = I32
     L.rocket_cost_grad.argtypes = [P, IT, I64, I32, P, P, P, P, P]
     L.rocket_cost_grad.restype = I32
+    L.rocket_get_trace.argtypes = [P, P, I64, ctypes.POINTER(I64)]
+    L.rocket_get_trace.restype = I32
     L.rocket_probe_valu.argtypes = [I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_double)]
     L.rocket_probe_valu.restype = I32

@@ -171,6 +171,21 @@ class Context:
                                        ctypes.byref(cnt)), self.handle)
         return out
 
+    def trace(self):
+        """Per-tile trace of the last compare (option ``trace`` set before prepare): a numpy
+        structured array with tile_i, tile_j, chunk, workgroup, start_ns, end_ns per work item."""
+        import numpy as np
+        L = _lib.load()
+        cnt = ctypes.c_int64()
+        _lib.check(L.rocket_get_trace(self.handle, None, 0, ctypes.byref(cnt)), self.handle)
+        dt = np.dtype([("tile_i", np.int32), ("tile_j", np.int32), ("chunk", np.int32), ("workgroup", np.int32),
+                       ("start_ns", np.int64), ("end_ns", np.int64)])
+        assert dt.itemsize == ctypes.sizeof(_lib.TraceRec)
+        out = np.zeros(cnt.value, dtype=dt)
+        _lib.check(L.rocket_get_trace(self.handle, out.ctypes.data_as(ctypes.c_void_p), cnt.value, ctypes.byref(cnt)),
+                   self.handle)
+        return out
+
     # -- items ----------------------------------------------------------------------------
     def _dev(self, t, name: str, dtype, contiguous: bool = True):
         return _check_dev(t, name, dtype, self.device, contiguous)

@@ -17,6 +17,7 @@ enum Slot {
     WS_QUEUE_HEADS,      // per-segment pop counters
     WS_QUEUE_SEGS,       // segment boundaries
     WS_LEDGER,           // per-item pop counts (debug)
+    WS_TRACE,            // per-item start, end and workgroup (ROCKET_OPT_TRACE)
     WS_FLAGS,            // device error flags
     WS_NCC_STATS,        // mean (f64), inverse norm (f32)
     WS_NCC_PLANES,       // split / centred operand planes
@@ -51,6 +52,8 @@ struct QueueArgs {
     const int *seg;     // nseg + 1 segment boundaries into items
     int *ledger;        // optional per-item pop counter
     int nseg;
+    // optional per-item trace: start and end on the device wall clock, and the workgroup
+    unsigned long long *trace = nullptr;
 };
 constexpr int HEAD_STRIDE = 32;  // 128 bytes between segment counters
 constexpr int MAX_SEG = 8;       // one segment per XCD
@@ -150,6 +153,7 @@ struct rocket_ctx {
     rk::PceState pce;
     rocket_stats stats = {};
     int64_t ledger_items = 0;
+    bool trace_valid = false;  // the trace slot holds the last compare's per-item records
     hipEvent_t ev_begin = nullptr, ev_end = nullptr;  // main-kernel timing (ROCKET_OPT_TIMING)
     bool ev_pending = false;
     std::string last_error;
@@ -164,6 +168,13 @@ struct rocket_ctx {
 };
 
 namespace rk {
+
+// Queue instrumentation in effect (ledger bit 0, trace bit 1): part of the key under which
+// an uploaded queue is reused.
+inline int64_t queue_flags(const rocket_ctx *ctx)
+{
+    return (ctx->opt[ROCKET_OPT_LEDGER] != 0 ? 1 : 0) | (ctx->opt[ROCKET_OPT_TRACE] != 0 ? 2 : 0);
+}
 
 rocket_status fail(rocket_ctx *ctx, rocket_status st, const std::string &msg);
 rocket_status hip_fail(rocket_ctx *ctx, hipError_t e, const char *what, const char *file, int line);

@@ -306,8 +306,9 @@ __global__ __launch_bounds__(64 * NWV, 1) void k_ncc_gram(const char *__restrict
     const int h = lane >> 5;
     const int lrow = lane / SEGS, pseg = lane % SEGS;
 
+    int prev = -1;
     for (;;) {
-        const int it = __builtin_amdgcn_readfirstlane(queue_pop_wg(q, &s_item));
+        const int it = __builtin_amdgcn_readfirstlane(queue_pop_wg(q, &s_item, prev));
         if (it < 0) break;
         const int4 w = q.items[it];
         // slot = tile * HALVES + half; all work-item fields are wave-uniform
@@ -671,7 +672,7 @@ static rocket_status ncc_upload_plan(rocket_ctx *ctx, hipStream_t s)
 {
     NccState &pc = ctx->ncc;
     const int64_t order = ctx->opt[ROCKET_OPT_QUEUE_ORDER], seed = ctx->opt[ROCKET_OPT_SEED],
-                  ledger = ctx->opt[ROCKET_OPT_LEDGER];
+                  ledger = queue_flags(ctx);
     plan_chunked(pc.h_tiles, pc.nchunks, MAX_SEG, ctx->h_items, ctx->h_seg, 1);
     if (order == 1) shuffle_items(ctx->h_items, ctx->h_seg, (uint64_t)seed);
     if (order == 2) single_segment(ctx->h_seg, (int64_t)ctx->h_items.size());
@@ -760,7 +761,7 @@ rocket_status ncc_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, in
     if (st.items > INT32_MAX / 2) return fail(ctx, ROCKET_E_INVALID, "too many work items");
 
     const int64_t order = ctx->opt[ROCKET_OPT_QUEUE_ORDER], seed = ctx->opt[ROCKET_OPT_SEED],
-                  ledger = ctx->opt[ROCKET_OPT_LEDGER];
+                  ledger = queue_flags(ctx);
     if (st.tiles > 0 &&
         (pc.pc_nchunks != st.nchunks || pc.pc_order != order || pc.pc_seed != seed || pc.pc_ledger != ledger))
         RK_TRY(ncc_upload_plan(ctx, s));
@@ -908,9 +909,11 @@ rocket_status ncc_compare(rocket_ctx *ctx, float *out, hipStream_t s)
         qb.items = (const int4 *)items + item0[b];
         qb.seg = (const int *)segs + b * (MAX_SEG + 1);
         qb.ledger = ledger ? ledger + item0[b] : nullptr;
+        qb.trace = qa.trace ? qa.trace + 3 * item0[b] : nullptr;
         if (b > 0) {
             QueueArgs qh = qb;
-            qh.ledger = nullptr;  // heads only: the ledger was cleared once for all batches
+            qh.ledger = nullptr;  // heads only: the ledger and trace were cleared once for all batches
+            qh.trace = nullptr;
             RK_TRY(reset_queue(ctx, s, qh));
         }
         const int grid = auto_grid(ctx, gram_kernel(bm, st.scheme, st.waves), 64 * st.waves, 0, nit);

@@ -128,8 +128,9 @@ __global__ __launch_bounds__(OVL_THREADS, 1) void k_overlap(const float2 *__rest
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int slot = lane % S, phase = lane / S;
 
+    int prev = -1;
     for (;;) {
-        const int it = queue_pop_wg(q, &s_item);
+        const int it = queue_pop_wg(q, &s_item, prev);
         if (it < 0) break;
         const int4 w = q.items[it];
         const int bI = w.x, bJ = w.y;
@@ -343,8 +344,9 @@ __global__ __launch_bounds__(OVL_THREADS, 1) void k_gmm_full(const float2 *__res
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int slot = lane % S, phase = lane / S;
 
+    int prev = -1;
     for (;;) {
-        const int it = queue_pop_wg(q, &s_item);
+        const int it = queue_pop_wg(q, &s_item, prev);
         if (it < 0) break;
         const int4 w = q.items[it];
         const int bI = w.x, bJ = w.y;
@@ -706,7 +708,7 @@ static rocket_status ovl_replan(rocket_ctx *ctx, hipStream_t s)
     o.pc_block = ovl_block(ctx);
     o.pc_order = ctx->opt[ROCKET_OPT_QUEUE_ORDER];
     o.pc_seed = ctx->opt[ROCKET_OPT_SEED];
-    o.pc_ledger = ctx->opt[ROCKET_OPT_LEDGER];
+    o.pc_ledger = queue_flags(ctx);
     return ROCKET_OK;
 }
 
@@ -852,7 +854,7 @@ rocket_status ovl_compare(rocket_ctx *ctx, float *out, const float *cen, const f
     if (!o.valid) return fail(ctx, ROCKET_E_STATE, "overlap set not prepared");
     if (o.n < 2 || o.tiles == 0) return ROCKET_OK;
     if (ctx->queue_owner != QOWN_OVL || o.pc_block != ovl_block(ctx) || o.pc_order != ctx->opt[ROCKET_OPT_QUEUE_ORDER] ||
-        o.pc_seed != ctx->opt[ROCKET_OPT_SEED] || o.pc_ledger != ctx->opt[ROCKET_OPT_LEDGER])
+        o.pc_seed != ctx->opt[ROCKET_OPT_SEED] || o.pc_ledger != queue_flags(ctx))
         RK_TRY(ovl_replan(ctx, s));
     return ovl_launch(ctx, s, out, cen, params, grad, ovl_variant(ctx));
 }

@@ -218,8 +218,9 @@ __global__ __launch_bounds__(PCE_CMP_THREADS, 1) void k_pce(const float2 *__rest
     fill_twiddles<L>(tw);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nb_side = 2 * h + 1 < L ? 2 * h + 1 : L;
+    int prev = -1;
     for (;;) {
-        const int it = queue_pop_wg(q, &s_item);
+        const int it = queue_pop_wg(q, &s_item, prev);
         if (it < 0) break;
         const int4 w = q.items[it];
         const int i0 = w.x * PCE_T, i1 = min(n, i0 + PCE_T), j0 = w.y * PCE_T, j1 = min(n, j0 + PCE_T);

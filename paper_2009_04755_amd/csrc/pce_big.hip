@@ -522,6 +522,7 @@ rocket_status pce_big_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n
     PceState &p = ctx->pce;
     const int WH = W / 2 + 1;
     const PbLayout l = layout(n, H, W);
+    ctx->trace_valid = false;  // batched launches, no persistent queue to trace
     void *buf = nullptr;
     RK_TRY(ws_get(ctx, WS_PCE_SPEC, l.spec + l.stats + l.live + l.tw, &buf));
     float2 *F = (float2 *)buf;

@@ -34,10 +34,22 @@ __device__ __forceinline__ int queue_pop(const QueueArgs &q)
 }
 
 // Pop by thread 0, broadcast to the workgroup through LDS.  The caller's loop body
-// must contain at least one __syncthreads() between consecutive calls.
-__device__ __forceinline__ int queue_pop_wg(const QueueArgs &q, int *slot)
+// must contain at least one __syncthreads() between consecutive calls.  `prev` is thread
+// 0's previous item (-1 before the first call): with a trace, the wall clock before the
+// pop ends the previous item and the clock after it starts the new one, and the new item
+// records its workgroup (the per-tile timeline of Section IV-C's profiling).
+__device__ __forceinline__ int queue_pop_wg(const QueueArgs &q, int *slot, int &prev)
 {
-    if (threadIdx.x == 0) *slot = queue_pop(q);
+    if (threadIdx.x == 0) {
+        if (q.trace && prev >= 0) q.trace[3 * (int64_t)prev + 1] = wall_clock64();
+        const int it = queue_pop(q);
+        if (q.trace && it >= 0) {
+            q.trace[3 * (int64_t)it] = wall_clock64();
+            q.trace[3 * (int64_t)it + 2] = blockIdx.x;
+        }
+        prev = it;
+        *slot = it;
+    }
     __syncthreads();
     return *slot;
 }

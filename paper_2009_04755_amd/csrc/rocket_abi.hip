@@ -114,6 +114,14 @@ rocket_status upload_queue(rocket_ctx *ctx, hipStream_t s, QueueArgs *qa)
         qa->ledger = (int *)led;
     }
     ctx->ledger_items = nitems;
+    qa->trace = nullptr;
+    ctx->trace_valid = false;
+    if (ctx->opt[ROCKET_OPT_TRACE]) {
+        void *tr = nullptr;
+        RK_TRY(ws_get(ctx, WS_TRACE, 3 * sizeof(unsigned long long) * (size_t)std::max<int64_t>(nitems, 1), &tr));
+        qa->trace = (unsigned long long *)tr;
+        ctx->trace_valid = true;
+    }
     return ROCKET_OK;
 }
 
@@ -125,6 +133,12 @@ rocket_status reset_queue(rocket_ctx *ctx, hipStream_t s, const QueueArgs &qa)
         const int64_t n = std::max<int64_t>(ctx->ledger_items, 1);
         hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)), dim3(256), 0, s,
                            qa.ledger, n, 0);
+        RK_HIP(hipGetLastError());
+    }
+    if (qa.trace) {  // items never run keep zeros
+        const int64_t n = 6 * std::max<int64_t>(ctx->ledger_items, 1);
+        hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)), dim3(256), 0, s,
+                           (int *)qa.trace, n, 0);
         RK_HIP(hipGetLastError());
     }
     return ROCKET_OK;
@@ -324,6 +338,7 @@ rocket_status rocket_allpairs_host(rocket_ctx *ctx, const float *host_items, int
     if (fn != ROCKET_NCC_FP32 && fn != ROCKET_NCC_BF16X3 && fn != ROCKET_NCC_BF16X6)
         return rk::fail(ctx, ROCKET_E_UNSUPPORTED, "host-resident items: NCC pair functions only");
     ctx->prepared_fn = 0;  // the plane workspace is reused as the device cache
+    ctx->trace_valid = false;
     ctx->ovl.grad_ready = false;
     rocket_status st = rk::ncc_allpairs_host(ctx, host_items, n, dim, ld, (int)fn, out, (hipStream_t)stream);
     ctx->stats.n = n;
@@ -406,7 +421,7 @@ rocket_status rocket_cost_grad(rocket_ctx *ctx, const rocket_items *items, int64
 rocket_status rocket_set_option(rocket_ctx *ctx, rocket_option opt, int64_t value)
 {
     if (!ctx) return rk::fail(nullptr, ROCKET_E_INVALID, "ctx is NULL");
-    if (opt < ROCKET_OPT_NCC_TILE || opt > ROCKET_OPT_PCE_BATCH) return rk::fail(ctx, ROCKET_E_UNSUPPORTED, "option");
+    if (opt < ROCKET_OPT_NCC_TILE || opt > ROCKET_OPT_TRACE) return rk::fail(ctx, ROCKET_E_UNSUPPORTED, "option");
     if (value < 0) return rk::fail(ctx, ROCKET_E_INVALID, "negative option value");
     if (opt == ROCKET_OPT_NCC_TILE && value != 0 && value != 64 && value != 128 && value != 256)
         return rk::fail(ctx, ROCKET_E_INVALID, "NCC tile must be 0, 64, 128 or 256");
@@ -428,7 +443,7 @@ rocket_status rocket_set_option(rocket_ctx *ctx, rocket_option opt, int64_t valu
 rocket_status rocket_get_option(const rocket_ctx *ctx, rocket_option opt, int64_t *value)
 {
     if (!ctx || !value) return rk::fail(nullptr, ROCKET_E_INVALID, "NULL argument");
-    if (opt < ROCKET_OPT_NCC_TILE || opt > ROCKET_OPT_PCE_BATCH) return ROCKET_E_UNSUPPORTED;
+    if (opt < ROCKET_OPT_NCC_TILE || opt > ROCKET_OPT_TRACE) return ROCKET_E_UNSUPPORTED;
     *value = ctx->opt[opt];
     return ROCKET_OK;
 }
@@ -444,6 +459,43 @@ rocket_status rocket_get_stats(const rocket_ctx *ctx, rocket_stats *out)
             out->kernel_ns = (int64_t)((double)ms * 1e6);
         else
             (void)hipGetLastError();
+    }
+    return ROCKET_OK;
+}
+
+rocket_status rocket_get_trace(rocket_ctx *ctx, rocket_trace_rec *out, int64_t cap, int64_t *count)
+{
+    if (!ctx || !count) return rk::fail(ctx, ROCKET_E_INVALID, "NULL argument");
+    if (!ctx->opt[ROCKET_OPT_TRACE] || !ctx->trace_valid || !ctx->ws[rk::WS_TRACE].ptr ||
+        !ctx->ws[rk::WS_QUEUE_ITEMS].ptr)
+        return rk::fail(ctx, ROCKET_E_STATE, "no per-tile trace: set ROCKET_OPT_TRACE before a prepare whose compare "
+                                             "runs a persistent queue");
+    *count = ctx->ledger_items;
+    if (!out || cap <= 0) return ROCKET_OK;
+    const int64_t m = std::min(cap, ctx->ledger_items);
+    if (m == 0) return ROCKET_OK;
+    std::vector<unsigned long long> tr((size_t)(3 * m));
+    std::vector<int4> items((size_t)m);
+    RK_HIP(hipSetDevice(ctx->device));
+    RK_HIP(hipDeviceSynchronize());
+    RK_HIP(hipMemcpy(tr.data(), ctx->ws[rk::WS_TRACE].ptr, sizeof(unsigned long long) * tr.size(), hipMemcpyDeviceToHost));
+    RK_HIP(hipMemcpy(items.data(), ctx->ws[rk::WS_QUEUE_ITEMS].ptr, sizeof(int4) * items.size(), hipMemcpyDeviceToHost));
+    int khz = 0;
+    RK_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device));
+    if (khz <= 0) return rk::fail(ctx, ROCKET_E_HIP, "device wall clock rate unknown");
+    unsigned long long t0 = ~0ull;
+    for (int64_t k = 0; k < m; ++k)
+        if (tr[3 * k] != 0) t0 = std::min(t0, tr[3 * k]);
+    const double ns_per_tick = 1e6 / (double)khz;
+    for (int64_t k = 0; k < m; ++k) {
+        rocket_trace_rec &r = out[k];
+        r.tile_i = items[k].x;
+        r.tile_j = items[k].y;
+        r.chunk = items[k].z;
+        const bool ran = tr[3 * k] != 0;
+        r.workgroup = ran ? (int32_t)tr[3 * k + 2] : -1;
+        r.start_ns = ran ? (int64_t)((double)(tr[3 * k] - t0) * ns_per_tick) : -1;
+        r.end_ns = ran && tr[3 * k + 1] >= tr[3 * k] ? (int64_t)((double)(tr[3 * k + 1] - t0) * ns_per_tick) : -1;
     }
     return ROCKET_OK;
 }

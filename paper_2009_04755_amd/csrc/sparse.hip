@@ -216,8 +216,9 @@ __global__ __launch_bounds__(SP_THREADS, 1) void k_sparse(const uint32_t *__rest
         const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
         return (int64_t)(((uint64_t)hi << 32) | lo);
     };
+    int prev = -1;
     for (;;) {
-        const int it = __builtin_amdgcn_readfirstlane(queue_pop_wg(q, &s_item));
+        const int it = __builtin_amdgcn_readfirstlane(queue_pop_wg(q, &s_item, prev));
         if (it < 0) break;
         const int4 w = q.items[it];
         const int band = __builtin_amdgcn_readfirstlane(w.x), cblk = __builtin_amdgcn_readfirstlane(w.y);
