@@ -243,3 +243,21 @@ def test_full_scale_sampled():
     err = _check(gv, gc, so, sk, sv, np.array([remap[int(v)] for v in pi]), np.array([remap[int(v)] for v in pj]))
     announce("max rel err %.2e, mean count %.0f" % (err, gc.mean()))
     ctx.close()
+
+
+def test_without_counts_same_cosines():
+    # the counts are optional: without them the kernel skips the presence sums only, so the
+    # cosines are identical bit for bit
+    import torch
+    from paper_2009_04755_amd import Context, SparseSet
+    device_or_skip()
+    announce("sparse cosine with and without counts, n=300")
+    off, keys, vals = synth.sparse_vectors(300, key_space=20 ** 6, nnz_mean=3000, nnz_min=300, nnz_max=20000,
+                                           config=4, salt=41)
+    S = SparseSet(torch.from_numpy(off).cuda(), torch.from_numpy(keys).cuda(), torch.from_numpy(vals).cuda())
+    for lanes in (4, 8):
+        c = Context(0).set(sp_lanes=lanes)
+        with_counts, cnt = c.allpairs(S, "sparse_cosine", counts=True)
+        without = c.allpairs(S, "sparse_cosine")
+        assert torch.equal(with_counts, without), lanes
+        c.close()
