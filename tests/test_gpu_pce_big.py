@@ -79,6 +79,21 @@ def test_all_pairs_1024(ctx):
             assert gpk[idx] == ((sh[i, 0] - sh[j, 0]) % 1024) * 1024 + (sh[i, 1] - sh[j, 1]) % 1024
 
 
+@pytest.mark.parametrize("L", [16, 2048])
+def test_smallest_and_largest_square(ctx, L):
+    # the size limits of the staged path: 16 x 16 (one radix-16 pass per axis) and 2048 x 2048
+    n = 3 if L == 2048 else 12
+    announce("pce staged all pairs n=%d %dx%d" % (n, L, L))
+    # one source, strong enough that the true shift beats the noise maxima at 256 shifts
+    X, c, sh = synth.noise_images(n, L, nsrc=1, amp=2.0 if L == 16 else 0.5, p_shift=0.7, config=6, salt=L + 7)
+    got, gpk = _run(ctx, X, 0)
+    pairs = [(i, j) for i in range(n) for j in range(i + 1, n)]
+    announce("max rel err %.2e" % _check(got, gpk, X, L, L, pairs))
+    for i, j in pairs:  # one source: the peak is the relative shift of the two crops
+        idx = i * n - i * (i + 1) // 2 + (j - i - 1)
+        assert gpk[idx] == ((sh[i, 0] - sh[j, 0]) % L) * L + (sh[i, 1] - sh[j, 1]) % L
+
+
 def test_shifted_copies_and_constant_item(ctx):
     announce("pce staged shifted copies 256x1024")
     H, W = 256, 1024
