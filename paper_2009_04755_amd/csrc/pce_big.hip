@@ -19,6 +19,8 @@
 //   final        per pair-pair and channel: the overall peak and energy, the 2h+1 columns
 //                around the peak transformed again (by the same code, so to the same values)
 //                for the energy of the (2h+1)^2 cells around it, and the PCE.
+// The staged transform of a pair-pair is stored as W/CB blocks of H x CB values (CB columns
+// per column-pass workgroup), so that each column-pass workgroup reads one contiguous piece.
 // Every FFT kernel works on one tile of 8K complex values in LDS with 512 threads: radix-16
 // Stockham passes in registers (natural order in and out; pass twiddles computed in FP64 and
 // rounded once), one padding slot per 16 values against bank conflicts.
@@ -30,9 +32,9 @@
 namespace rk {
 namespace {
 
-constexpr int PB_THREADS = 256;     // statistics and final kernels
-constexpr int PB_NT = 512;          // FFT kernels: one tile of PB_TILE complex values per workgroup,
-constexpr int PB_EPT = 16;          // 16 per thread per pass (two workgroups share a CU's LDS)
+constexpr int PB_THREADS = 256;     // per-item statistics kernel
+constexpr int PB_NT = 512;          // FFT kernels (all others): one tile of PB_TILE complex values
+constexpr int PB_EPT = 16;          // per workgroup, 16 per thread per pass (two workgroups per CU)
 constexpr int PB_TILE = PB_NT * PB_EPT;
 constexpr int PB_T = 8;             // items per block of the pair tiles
 constexpr int64_t PB_STAGE_BYTES = (int64_t)512 << 20;  // default staging of one batch of transforms
