@@ -41,6 +41,7 @@ PEAK_HBM = 8000.0       # GB/s
 # VALU issue peak: the published FP32 vector peak (157.3 TFLOP/s = 256 CU x 128 FMA lanes x
 # 2.4 GHz x 2 flop) as lane-instruction slots/s; a transcendental (exp2, rcp) takes 4 slots
 VALU_LANE_OPS = 157.3e12 / 2
+PEAK_FP32_VALU = 157.3  # TFLOP/s, the same peak as FMA flops
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "ncc_gram_bf16x6_4096x1048576_counters.txt")
 
 
@@ -477,18 +478,29 @@ def pce_pair_fn(ctx, with_cpu=True):
     return res
 
 
-def pce_big_pair_fn(ctx, with_cpu=True):
-    """PCE over all shifts for 256 noise images of 1024 x 1024 (32,640 pairs): the staged
-    multi-pass path, in its default batches of 64 two-pair transforms."""
+def _fft_len(N):
+    """FFT length of an N-point axis of the staged PCE: N for a power of two, else the
+    Bluestein length (the power of two >= 2N - 1), and the number of FFTs per DFT."""
+    if N & (N - 1) == 0:
+        return N, 1
+    M = 1
+    while M < 2 * N - 1:
+        M *= 2
+    return M, 2
+
+
+def pce_big_pair_fn(ctx, with_cpu=True, n=256, H=1024, W=1024, nsrc=16, sample=128):
+    """PCE over all shifts for n noise images of H x W (default: 256 of 1024 x 1024, 32,640
+    pairs): the staged multi-pass path, in its default batches of two-pair transforms."""
     import numpy as np
     import torch
     from paper_2009_04755_amd import synth
 
-    n, H, W = 256, 1024, 1024
-    X, _, _ = synth.noise_images(n, H, nsrc=16, amp=0.3, config=6, salt=1)
+    X, _, _ = synth.noise_images(n, (H, W), nsrc=nsrc, amp=0.3, config=6, salt=1 if H == W == 1024 else H + W)
     Xd = torch.from_numpy(X).cuda()
     P = n * (n - 1) // 2
     out = torch.empty(P, device="cuda")
+    ctx.set(pce_width=W)
     dt, kern = _time_fn(ctx, Xd, "pce", out, 3, 1)
     st = ctx.stats()
     npp = (P + 1) // 2
@@ -496,20 +508,31 @@ def pce_big_pair_fn(ctx, with_cpu=True):
     # staged H x W complex transform written by the row pass and read by the column pass
     spec = H * (W // 2 + 1) * 8
     per_pp = 4 * spec + 2 * H * W * 8
-    res = {"workload": "256 noise images 1024 x 1024 (16 sources, amp 0.3, 25 % shifted crops), h = 5",
+    # nominal FFT flops per two-pair transform (5 M log2 M per M-point FFT): H row DFTs and
+    # W column DFTs, each one FFT, or two of the Bluestein length
+    (MW, kw), (MH, kh) = _fft_len(W), _fft_len(H)
+    flops_pp = 5 * (H * kw * MW * np.log2(MW) + W * kh * MH * np.log2(MH))
+    pct = "%d %%" % round(100 * 0.25) if H == W == 1024 else "25 %"
+    res = {"workload": "%d noise images %d x %d (%d sources, amp 0.3, %s shifted crops), h = 5" % (n, H, W, nsrc, pct),
            "pairs_per_s": 3 * P / dt, "kernel_ms": kern * 1e3, "batch_pair_pairs": st["grid"],
            "roofline": {"bound": "hbm", "achieved": npp * per_pp / kern / 1e9, "peak": PEAK_HBM, "unit": "GB/s",
                         "frac": npp * per_pp / kern / 1e9 / PEAK_HBM, "bytes_per_pair_pair": per_pp,
                         "model": "4 half spectra read + staged H x W complex transform written and read once, "
-                                 "per two-pair transform (row pass, column pass and final kernels together)"}}
+                                 "per two-pair transform (row pass, column pass and final kernels together)"},
+           "fft_flop_rate": {"achieved": npp * flops_pp / kern / 1e12, "unit": "TFLOP/s", "peak": PEAK_FP32_VALU,
+                             "frac": npp * flops_pp / kern / 1e12 / PEAK_FP32_VALU, "flops_per_pair_pair": flops_pp,
+                             "model": "5 M log2 M per M-point FFT; an axis that is not a power of two costs two "
+                                      "FFTs of the Bluestein length M >= 2N - 1"}}
+    if H != W or H & (H - 1):
+        res["fft_lengths"] = {"rows": int(MW), "columns": int(MH)}
     if with_cpu:
-        # 128 random pairs, oracle (numpy FFT, FP64) on one process per host CPU; PCE compared
-        # at the GPU's peak where that peak is a valid one
+        # random pairs, oracle (numpy FFT, FP64) on one process per host CPU; PCE compared at
+        # the GPU's peak where that peak is a valid one
         g = np.random.default_rng(9)
-        pi = g.integers(0, n, 160)
-        pj = g.integers(0, n, 160)
+        pi = g.integers(0, n, sample + sample // 4)
+        pj = g.integers(0, n, sample + sample // 4)
         keep = pi != pj
-        pi, pj = np.minimum(pi, pj)[keep][:128], np.maximum(pi, pj)[keep][:128]
+        pi, pj = np.minimum(pi, pj)[keep][:sample], np.maximum(pi, pj)[keep][:sample]
         idx = pi * n - pi * (pi + 1) // 2 + (pj - pi - 1)
         got, pk = ctx.allpairs(Xd, "pce", counts=True)
         got, pk = got.cpu().numpy()[idx], pk.cpu().numpy()[idx].astype(np.int64)
@@ -517,7 +540,9 @@ def pce_big_pair_fn(ctx, with_cpu=True):
         loc = {r: k for k, r in enumerate(rows)}
         li = [loc[a] for a in pi.tolist()]
         lj = [loc[b] for b in pj.tolist()]
-        jobs = [list(zip(li[a:a + 8], lj[a:a + 8], pk[a:a + 8].tolist())) for a in range(0, len(li), 8)]
+        per_job = max(1, min(8, len(li) // _pool_size()))
+        jobs = [list(zip(li[a:a + per_job], lj[a:a + per_job], pk[a:a + per_job].tolist()))
+                for a in range(0, len(li), per_job)]
         r, dto = _run_pool(_pce_big_job, jobs, {"X": X[rows], "H": H, "W": W})
         r = [t for part in r for t in part]
         at_g = np.array([t[2] for t in r])
@@ -526,8 +551,10 @@ def pce_big_pair_fn(ctx, with_cpu=True):
                          "gpu_peak_valid_frac": float(np.mean(valid)),
                          "pce_at_gpu_peak": _errors(got[valid], at_g[valid])}
         res["cpu_baseline"] = dict({"value": len(li) / dto, "unit": "pairs/s", "cores": _pool_size(),
-                                    "kind": "oracle", "sample": "128 random pairs of the 256 images (numpy FFT, "
-                                                                "FP64, one process per CPU)"}, **_host_info())
+                                    "kind": "oracle", "sample": "%d random pairs of the %d images (numpy FFT, "
+                                                                "FP64, one process per CPU)" % (len(li), n)},
+                                   **_host_info())
+    ctx.set(pce_width=0)
     del Xd
     torch.cuda.empty_cache()
     return res
@@ -788,7 +815,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="skip the autotuner in the untimed setup")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM counter scaling)")
-    ap.add_argument("--only", choices=["clouds", "sparse", "cv", "pce", "pce_big", "ooc", "small", "valu"],
+    ap.add_argument("--only", choices=["clouds", "sparse", "cv", "pce", "pce_big", "pce_camera", "ooc", "small",
+                                             "valu"],
                     help="run only this secondary workload (for profiling it) and print its record; "
                          "clouds = overlap, GMM L2 / Bhattacharya and the registration gradient; "
                          "small = the 256 x 4096 NCC workload")
@@ -822,6 +850,7 @@ def main():
         run = {"clouds": lambda: other_pair_fns(ctx, cpu, tune), "sparse": lambda: sparse_pair_fn(ctx, cpu, tune),
                "cv": lambda: cv_pipeline(ctx, cpu), "pce": lambda: pce_pair_fn(ctx, cpu),
                "pce_big": lambda: pce_big_pair_fn(ctx, cpu), "valu": valu_probe,
+               "pce_camera": lambda: pce_big_pair_fn(ctx, cpu, n=32, H=3648, W=2736, nsrc=4, sample=16),
                "small": lambda: ncc_small(ctx, cpu)}[args.only]
         print(json.dumps({"only": args.only, "record": run()}))
         sys.stdout.flush()
@@ -902,6 +931,9 @@ def main():
         rec["cv_build"] = cv_pipeline(ctx, not args.no_cpu_baseline)
         rec["pair_fns"]["pce"] = pce_pair_fn(ctx, not args.no_cpu_baseline)
         rec["pair_fns"]["pce_1024"] = pce_big_pair_fn(ctx, not args.no_cpu_baseline)
+        # a camera sensor's pixel grid: both sides by Bluestein (8192-point FFTs)
+        rec["pair_fns"]["pce_3648x2736"] = pce_big_pair_fn(ctx, not args.no_cpu_baseline, n=32, H=3648, W=2736,
+                                                           nsrc=4, sample=16)
     print(json.dumps(rec))
     sys.stdout.flush()
 

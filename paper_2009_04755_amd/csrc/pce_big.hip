@@ -1,10 +1,11 @@
 // PCE over all cyclic shifts for images larger than one LDS tile (Section V-A's PCE variant
 // of the pattern comparison at the size of the forensics patterns): H x W items, H and W
-// powers of two in [16, 2048].  The quantities are those of the in-LDS path:
+// even and in [16, 4096] (a side that is not a power of two by Bluestein's chirp
+// convolution).  The quantities are those of the in-LDS path:
 //   C(s) = sum_x a(x + s) b(x),  s* = argmax C,  PCE = C(s*)^2 (HW - |N|) / sum_{s not in N} C(s)^2.
 //
-// Prepare (per item): FP64 mean and norm, then the 2-D FFT of the centred unit-norm image as
-// row FFTs (length W, only columns 0 .. W/2 kept: the input is real) followed by column FFTs
+// Prepare (per item): FP64 mean and norm, then the 2-D DFT of the centred unit-norm image as
+// row DFTs (length W, only columns 0 .. W/2 kept: the input is real) followed by column DFTs
 // (length H) in place; spectra are H x (W/2 + 1) complex f32, row-major.
 //
 // Compare: pairs are visited tile by tile (T x T items, divide-and-conquer leaves), two at a
@@ -19,11 +20,14 @@
 //   final        per pair-pair and channel: the overall peak and energy, the 2h+1 columns
 //                around the peak transformed again (by the same code, so to the same values)
 //                for the energy of the (2h+1)^2 cells around it, and the PCE.
-// The staged transform of a pair-pair is stored as W/CB blocks of H x CB values (CB columns
-// per column-pass workgroup), so that each column-pass workgroup reads one contiguous piece.
-// Every FFT kernel works on one tile of 8K complex values in LDS with 512 threads: radix-16
-// Stockham passes in registers (natural order in and out; pass twiddles computed in FP64 and
-// rounded once), one padding slot per 16 values against bank conflicts.
+// The staged transform of a pair-pair is stored as ceil(W/CB) blocks of H x CB values (CB
+// columns per column-pass workgroup), so that each column-pass workgroup reads one contiguous
+// piece.  Every FFT kernel works on one tile of 8K complex values in LDS with 512 threads
+// (1024 for a row pair of 8K-point transforms): radix-16 Stockham passes in registers
+// (natural order in and out; pass twiddles computed in FP64 and rounded once), one padding
+// slot per 16 values against bank conflicts.  An axis of N values, N not a power of two, is
+// an M-point FFT, its product with the chirp filter's spectrum and an inverse M-point FFT in
+// the same tile (M the power of two >= 2N - 1), N <= 4096 so that M <= 8192.
 #include <algorithm>
 #include <cmath>
 
@@ -133,7 +137,7 @@ struct PbLds {
 // (k = j mod Ns, from tw[(r - 1) Ns + k]), transforms them and hands value s to dst at
 // (j - k) R + k + s Ns.  Every load of the workgroup finishes before its first store, so src
 // and dst may be the same memory; a pass that stores to LDS ends with a barrier.
-template <int R, int LR, bool VF, bool DST_LDS, class Src, class Dst>
+template <int R, int LR, bool VF, bool DST_LDS, int NT, class Src, class Dst>
 __device__ __forceinline__ void pb_pass(int logN, int M, int logNs, const float2 *tw, const Src &src,
                                         const Dst &dst)
 {
@@ -143,7 +147,7 @@ __device__ __forceinline__ void pb_pass(int logN, int M, int logNs, const float2
     float2 a[UPT][R];
 #pragma unroll
     for (int i = 0; i < UPT; ++i) {
-        const int u = threadIdx.x + i * PB_NT;
+        const int u = threadIdx.x + i * NT;
         if (u < units) {
             int v, j;
             pb_unit<VF>(u, M, logQ, v, j);
@@ -160,7 +164,7 @@ __device__ __forceinline__ void pb_pass(int logN, int M, int logNs, const float2
     pb_barrier();
 #pragma unroll
     for (int i = 0; i < UPT; ++i) {
-        const int u = threadIdx.x + i * PB_NT;
+        const int u = threadIdx.x + i * NT;
         if (u < units) {
             int v, j;
             pb_unit<VF>(u, M, logQ, v, j);
@@ -176,19 +180,19 @@ __device__ __forceinline__ void pb_pass(int logN, int M, int logNs, const float2
 // The passes after the first of a forward DFT of M vectors of N = 2^logN values (N >= 32):
 // radix-16 passes through lds, then the last pass (radix 2, 4, 8 or 16) from lds to dst.
 // tw points at the second pass's twiddles.
-template <bool VF, class Dst>
+template <bool VF, int NT, class Dst>
 __device__ __forceinline__ void pb_fft_rest(int logN, int M, const float2 *tw, const PbLds &lds, const Dst &dst)
 {
     int logNs = 4;
     for (; logN - logNs > 4; logNs += 4) {
-        pb_pass<16, 4, VF, true>(logN, M, logNs, tw, lds, lds);
+        pb_pass<16, 4, VF, true, NT>(logN, M, logNs, tw, lds, lds);
         tw += 15 << logNs;
     }
     switch (logN - logNs) {
-    case 1: pb_pass<2, 1, VF, false>(logN, M, logNs, tw, lds, dst); break;
-    case 2: pb_pass<4, 2, VF, false>(logN, M, logNs, tw, lds, dst); break;
-    case 3: pb_pass<8, 3, VF, false>(logN, M, logNs, tw, lds, dst); break;
-    default: pb_pass<16, 4, VF, false>(logN, M, logNs, tw, lds, dst); break;
+    case 1: pb_pass<2, 1, VF, false, NT>(logN, M, logNs, tw, lds, dst); break;
+    case 2: pb_pass<4, 2, VF, false, NT>(logN, M, logNs, tw, lds, dst); break;
+    case 3: pb_pass<8, 3, VF, false, NT>(logN, M, logNs, tw, lds, dst); break;
+    default: pb_pass<16, 4, VF, false, NT>(logN, M, logNs, tw, lds, dst); break;
     }
 }
 
@@ -196,16 +200,56 @@ __device__ __forceinline__ void pb_fft_rest(int logN, int M, const float2 *tw, c
 // -4 or -8 pass for the rest.  The first pass reads src(v, e), the last hands every result to
 // dst(v, e, value) (natural order); the passes between go through lds (M padded vectors of
 // stride ld).  tw holds the passes' twiddles one after another, (R - 1) Ns values each.
-// VF1 / VF: unit order of the first pass / of the others (VF: consecutive vectors).
-template <bool VF1, bool VF, class Src, class Dst>
+// VF1 / VF: unit order of the first pass / of the others (VF: consecutive vectors); NT
+// threads, at most NT * PB_EPT values.
+template <bool VF1, bool VF, int NT, class Src, class Dst>
 __device__ void pb_fft(int logN, int M, const float2 *tw, const PbLds &lds, const Src &src, const Dst &dst)
 {
     if (logN == 4) {
-        pb_pass<16, 4, VF1, false>(logN, M, 0, tw, src, dst);
+        pb_pass<16, 4, VF1, false, NT>(logN, M, 0, tw, src, dst);
         return;
     }
-    pb_pass<16, 4, VF1, true>(logN, M, 0, tw, src, lds);
-    pb_fft_rest<VF>(logN, M, tw + 15, lds, dst);
+    pb_pass<16, 4, VF1, true, NT>(logN, M, 0, tw, src, lds);
+    pb_fft_rest<VF, NT>(logN, M, tw + 15, lds, dst);
+}
+
+// One axis of the 2-D transform: an N-point DFT.  When N is a power of two it is one FFT
+// (M = N).  Otherwise Bluestein's chirp convolution: with w_n = exp(-i pi n^2 / N),
+// X_k = w_k sum_n (x_n w_n) conj(w_(k-n)), a convolution that one circular convolution of
+// length M >= 2N - 1 (a power of two) holds: X = w . IFFT_M(FFT_M(x w) . B) on k < N, with
+// B = FFT_M(b), b_m = conj(w_|m|) for |m| < N (indices mod M) and 0 between.
+struct PbDim {
+    int N, M, logM;
+    const float2 *tw;     // twiddles of the M-point FFT
+    const float2 *chirp;  // w_n, n < N (Bluestein only)
+    const float2 *filt;   // B (Bluestein only)
+};
+
+// The N-point DFT of nv vectors: src(v, e) for e < N, results to dst(v, e, X_e) for e < N.
+// BLUE (a compile-time choice, so that the power-of-two kernels keep their registers): by
+// Bluestein, the vectors occupying M values each in lds; the inverse FFT is the forward FFT
+// of the conjugate, conjugated and scaled by 1/M (exact: M is a power of two).
+template <bool BLUE, bool VF1, bool VF, int NT, class Src, class Dst>
+__device__ void pb_dft(const PbDim &d, int nv, const PbLds &lds, const Src &src, const Dst &dst)
+{
+    if constexpr (!BLUE) {
+        pb_fft<VF1, VF, NT>(d.logM, nv, d.tw, lds, src, dst);
+        return;
+    }
+    const float2 *w = d.chirp, *B = d.filt;
+    const int N = d.N;
+    auto src1 = [&](int v, int e) { return e < N ? pb_mul(src(v, e), w[e]) : make_float2(0.f, 0.f); };
+    auto dst1 = [&](int v, int e, float2 val) {
+        const float2 z = pb_mul(val, B[e]);
+        lds(v, e, make_float2(z.x, -z.y));
+    };
+    pb_fft<VF1, VF, NT>(d.logM, nv, d.tw, lds, src1, dst1);
+    pb_barrier();
+    const float inv = 1.f / (float)d.M;
+    auto dst2 = [&](int v, int e, float2 val) {
+        if (e < N) dst(v, e, pb_mul(make_float2(val.x * inv, -val.y * inv), w[e]));
+    };
+    pb_fft<VF, VF, NT>(d.logM, nv, d.tw, lds, lds, dst2);
 }
 
 // The passes' twiddles W_(R Ns)^(r k) for an N-point transform, FP64 rounded once.
@@ -226,43 +270,123 @@ __global__ void k_pb_twiddles(float2 *tw, int logN)
     }
 }
 
-// Per item: FP64 mean and inverse norm of the centred values; live = non-zero variance.
-__global__ __launch_bounds__(PB_THREADS) void k_pb_stats(const float *__restrict__ X, int64_t ld, int64_t d,
-                                                         double2 *__restrict__ st, int *__restrict__ live)
+// Bluestein tables of an N-point DFT computed with M-point FFTs, FP64 rounded once: the chirp
+// w_n = exp(-i pi n^2 / N) (angles reduced exactly: n^2 mod 2N) and the filter spectrum
+// B_k = sum_m b_m exp(-2 pi i m k / M) over the 2N - 1 non-zero b_m, one k per thread.
+__global__ void k_pb_chirp(int N, int M, float2 *__restrict__ chirp, float2 *__restrict__ filt)
 {
-    const float *x = X + (int64_t)blockIdx.x * ld;
-    __shared__ double red[PB_THREADS / 64];
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < d; i += PB_THREADS) s += (double)x[i];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-    __syncthreads();
-    const double mean = ((red[0] + red[1]) + (red[2] + red[3])) / (double)d;
-    __syncthreads();
-    double q = 0.0;
-    for (int64_t i = threadIdx.x; i < d; i += PB_THREADS) {
-        const double c = (double)x[i] - mean;
-        q = fma(c, c, q);
+    const int stride = gridDim.x * blockDim.x;
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < N; n += stride) {
+        double sn, cs;
+        sincospi(-(double)(((int64_t)n * n) % (2 * N)) / N, &sn, &cs);
+        chirp[n] = make_float2((float)cs, (float)sn);
     }
-    for (int o = 32; o > 0; o >>= 1) q += __shfl_xor(q, o);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = q;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const double ss = (red[0] + red[1]) + (red[2] + red[3]);
-        st[blockIdx.x] = make_double2(mean, ss > 0.0 ? 1.0 / sqrt(ss) : 0.0);  // a constant item: zero spectrum
-        live[blockIdx.x] = ss > 0.0;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < M; k += stride) {
+        double re = 0.0, im = 0.0;
+        for (int m = 0; m < N; ++m) {  // b_m = exp(i pi m^2 / N) at m and at M - m
+            const double a = (double)(((int64_t)m * m) % (2 * N)) / N, t = 2.0 * (double)(((int64_t)m * k) % M) / M;
+            double sn, cs;
+            sincospi(a - t, &sn, &cs);
+            re += cs;
+            im += sn;
+            if (m > 0) {
+                sincospi(a + t, &sn, &cs);
+                re += cs;
+                im += sn;
+            }
+        }
+        filt[k] = make_float2((float)re, (float)im);
     }
 }
 
-// Prepare, rows: grid (H / RB, items), RB = min(H, PB_TILE / W) rows per workgroup.  The rows,
-// centred and scaled (FP64, rounded once), transformed along the row; columns 0 .. W/2 go to F.
-__global__ __launch_bounds__(PB_NT) void k_pb_prep_rows(const float *__restrict__ X, int64_t ld, int H, int W, int logW,
-                                                        int RB, int64_t i0, const double2 *__restrict__ st,
-                                                        const float2 *__restrict__ twW, float2 *__restrict__ F)
+// Per-item statistics, FP64, in three launches so that a large item is read by many
+// workgroups: grid (items, nb) with chunk b of an item holding values [d b / nb, d (b+1) / nb).
+// Every sum has a fixed order (per thread four interleaved accumulators, a fixed tree over the
+// workgroup, the chunks in order), so the result does not depend on the schedule.
+__device__ __forceinline__ double pb_chunk_sum(const float *__restrict__ x, int64_t lo, int64_t hi, double mean,
+                                               bool centred)
+{
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int64_t i = lo + threadIdx.x;
+    for (; i + 3 * PB_THREADS < hi; i += 4 * PB_THREADS) {
+        const double a = x[i], b = x[i + PB_THREADS], c = x[i + 2 * PB_THREADS], e = x[i + 3 * PB_THREADS];
+        if (centred) {
+            s0 = fma(a - mean, a - mean, s0);
+            s1 = fma(b - mean, b - mean, s1);
+            s2 = fma(c - mean, c - mean, s2);
+            s3 = fma(e - mean, e - mean, s3);
+        } else {
+            s0 += a;
+            s1 += b;
+            s2 += c;
+            s3 += e;
+        }
+    }
+    for (; i < hi; i += PB_THREADS) {
+        const double a = x[i];
+        s0 = centred ? fma(a - mean, a - mean, s0) : s0 + a;
+    }
+    double r = (s0 + s1) + (s2 + s3);
+    for (int o = 32; o > 0; o >>= 1) r += __shfl_xor(r, o);
+    __shared__ double red[PB_THREADS / 64];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = r;
+    __syncthreads();
+    return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// The item's mean from its nb chunk sums (the same arithmetic wherever it is needed).
+__device__ __forceinline__ double pb_mean(const double *__restrict__ part, int nb, int64_t d)
+{
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[b];
+    return s / (double)d;
+}
+
+// Pass 1: chunk sums of the values to part[item][b].
+__global__ __launch_bounds__(PB_THREADS) void k_pb_sum(const float *__restrict__ X, int64_t ld, int64_t d,
+                                                       double *__restrict__ part)
+{
+    const int nb = gridDim.y, b = blockIdx.y;
+    const double r = pb_chunk_sum(X + (int64_t)blockIdx.x * ld, d * b / nb, d * (b + 1) / nb, 0.0, false);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * nb + b] = r;
+}
+
+// Pass 2: chunk sums of the squared centred values to part2[item][b].
+__global__ __launch_bounds__(PB_THREADS) void k_pb_sumsq(const float *__restrict__ X, int64_t ld, int64_t d,
+                                                         const double *__restrict__ part, double *__restrict__ part2)
+{
+    const int nb = gridDim.y, b = blockIdx.y;
+    __shared__ double mean;
+    if (threadIdx.x == 0) mean = pb_mean(part + (int64_t)blockIdx.x * nb, nb, d);
+    __syncthreads();
+    const double r = pb_chunk_sum(X + (int64_t)blockIdx.x * ld, d * b / nb, d * (b + 1) / nb, mean, true);
+    if (threadIdx.x == 0) part2[(int64_t)blockIdx.x * nb + b] = r;
+}
+
+// Pass 3, one thread per item: (mean, 1 / norm of the centred values) and live = non-zero
+// variance (a constant item gets a zero spectrum).
+__global__ void k_pb_stats(const double *__restrict__ part, const double *__restrict__ part2, int nb, int64_t n,
+                           int64_t d, double2 *__restrict__ st, int *__restrict__ live)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double ss = 0.0;
+    for (int b = 0; b < nb; ++b) ss += part2[i * nb + b];
+    st[i] = make_double2(pb_mean(part + i * nb, nb, d), ss > 0.0 ? 1.0 / sqrt(ss) : 0.0);
+    live[i] = ss > 0.0;
+}
+
+// Prepare, rows: grid (ceil(H / RB), items), RB rows per workgroup (the last may hold fewer).
+// The rows, centred and scaled (FP64, rounded once), transformed along the row; columns
+// 0 .. W/2 go to F.
+template <bool BLUE>
+__global__ __launch_bounds__(PB_NT) void k_pb_prep_rows(const float *__restrict__ X, int64_t ld, int H, int W, int RB,
+                                                        int64_t i0, const double2 *__restrict__ st, PbDim dW,
+                                                        float2 *__restrict__ F)
 {
     extern __shared__ float2 pb_sm[];
     const int64_t i = i0 + blockIdx.y;
-    const int r0 = blockIdx.x * RB, WH = W / 2 + 1;
+    const int r0 = blockIdx.x * RB, nr = min(RB, H - r0), WH = W / 2 + 1;
     const double2 ms = st[i];
     const float *x = X + i * ld + (int64_t)r0 * W;
     float2 *f = F + i * (int64_t)H * WH + (int64_t)r0 * WH;
@@ -270,53 +394,65 @@ __global__ __launch_bounds__(PB_NT) void k_pb_prep_rows(const float *__restrict_
     auto dst = [&](int v, int e, float2 val) {
         if (e <= W / 2) f[v * WH + e] = val;
     };
-    pb_fft<false, false>(logW, RB, twW, PbLds{pb_sm, pb_ld(W)}, src, dst);
+    pb_dft<BLUE, false, false, PB_NT>(dW, nr, PbLds{pb_sm, pb_ld(dW.M)}, src, dst);
 }
 
-// Column FFTs in place over F (H x WH, row-major): grid (ceil(WH / CB), items), CB = PB_TILE / H
-// columns per workgroup (fewer in the last).
-__global__ __launch_bounds__(PB_NT) void k_pb_prep_cols(float2 *__restrict__ F, int H, int logH, int WH, int CB,
-                                                        int64_t i0, const float2 *__restrict__ twH)
+// Column transforms in place over F (H x WH, row-major): grid (ceil(WH / CB), items), CB columns
+// per workgroup (fewer in the last).
+template <bool BLUE>
+__global__ __launch_bounds__(PB_NT) void k_pb_prep_cols(float2 *__restrict__ F, int H, int WH, int CB, int64_t i0,
+                                                        PbDim dH)
 {
     extern __shared__ float2 pb_sm[];
     float2 *f = F + (i0 + blockIdx.y) * (int64_t)H * WH + blockIdx.x * CB;
     const int nc = min(CB, WH - (int)blockIdx.x * CB);
     auto src = [&](int v, int e) { return f[(int64_t)e * WH + v]; };
     auto dst = [&](int v, int e, float2 val) { f[(int64_t)e * WH + v] = val; };
-    pb_fft<true, true>(logH, nc, twH, PbLds{pb_sm, pb_ld(H)}, src, dst);
+    pb_dft<BLUE, true, true, PB_NT>(dH, nc, PbLds{pb_sm, pb_ld(dH.M)}, src, dst);
 }
 
 // Rows of the pair-pair spectrum P = conj(F_a) F_b + i conj(F_c) F_d come in mirror pairs:
 // row pair q = 0 holds rows 0 and H/2 (each its own mirror), q > 0 rows q and H - q.
 __device__ __forceinline__ int pb_row(int q, int slot, int H) { return q == 0 ? (slot ? H / 2 : 0) : (slot ? H - q : q); }
 
-// Row pass: grid (H / (2 KP), pair-pairs of the batch), KP = min(H/2, PB_TILE / (2 W)) row pairs
-// per workgroup.  Q holds each pair-pair's transform as W / CB blocks of H x CB values.  pp[q] = (a, b, c, d): the pairs (a, b) and (c, d) (c < 0: no second pair).
-// Column c <= W/2 of a row comes from the half spectra at that row; column W - c (0 < c < W/2)
-// is conj(Z1) + i conj(Z2) taken at the mirror row, column c.  Rows are transformed and
-// written to Q.
-__global__ __launch_bounds__(PB_NT) void k_pb_rowpass(const float2 *__restrict__ F, const int4 *__restrict__ pp, int H,
-                                                      int W, int logW, int KP, int logCB,
-                                                      const float2 *__restrict__ twW, float2 *__restrict__ Q)
+// Row pass: grid (ceil(H / (2 KP)), pair-pairs of the batch), KP mirror row pairs per workgroup
+// (the last may hold fewer).  pp[q] = (a, b, c, d): the pairs (a, b) and (c, d) (c < 0: no
+// second pair).  Column c <= W/2 of a row comes from the half spectra at that row; column
+// W - c (0 < c < W/2) is conj(Z1) + i conj(Z2) taken at the mirror row, column c.  Rows are
+// transformed and written to Q, which holds each pair-pair's transform as ceil(W / CB)
+// blocks of H x CB values (CB = 2^logCB).  lhw = log2(W / 2), or -1 if W / 2 is not a power of two.
+template <int NT, bool BLUE>
+__global__ __launch_bounds__(NT) void k_pb_rowpass(const float2 *__restrict__ F, const int4 *__restrict__ pp, int H,
+                                                   int W, int lhw, int KP, int logCB, PbDim dW, float2 *__restrict__ Q)
 {
     extern __shared__ float2 pb_sm[];
     const int4 p = pp[blockIdx.y];
-    const int q0 = blockIdx.x * KP, lw = pb_ld(W), WH = W / 2 + 1, hw = W / 2;
+    const int q0 = blockIdx.x * KP, nq = min(KP, H / 2 - q0), lw = pb_ld(dW.M), WH = W / 2 + 1, hw = W / 2;
     const int64_t NH = (int64_t)H * WH;
     const bool two = p.z >= 0;
     const float2 *fa = F + p.x * NH, *fb = F + p.y * NH;
     const float2 *fc = F + (two ? p.z : p.x) * NH, *fd = F + (two ? p.w : p.y) * NH;
     const bool same_a = p.z == p.x;  // consecutive pairs of a tile row share their first item
-    // columns 0 .. W/2 - 1 of every row and their mirrors (at most PB_TILE / 2 elements: all
+    // columns 0 .. W/2 - 1 of every row and their mirrors (at most NT * PB_EPT / 2 elements: all
     // loads of a thread are issued before the first LDS store), then column W/2
     constexpr int G = PB_EPT / 2;
-    const int nmain = 2 * KP * hw;
+    const int nmain = 2 * nq * hw;
+    auto split = [&](int t, int &v, int &c) {
+        if (lhw >= 0) {
+            v = t >> lhw;
+            c = t & (hw - 1);
+        } else {
+            v = t / hw;
+            c = t - v * hw;
+        }
+    };
     float2 va[G], vb[G], vc[G], vd[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        const int t = threadIdx.x + g * PB_NT;
+        const int t = threadIdx.x + g * NT;
         if (t < nmain) {
-            const int v = t >> (logW - 1), c = t & (hw - 1);
+            int v, c;
+            split(t, v, c);
             const int64_t e = (int64_t)pb_row(q0 + (v >> 1), v & 1, H) * WH + c;
             va[g] = fa[e];
             vb[g] = fb[e];
@@ -326,9 +462,11 @@ __global__ __launch_bounds__(PB_NT) void k_pb_rowpass(const float2 *__restrict__
     }
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        const int t = threadIdx.x + g * PB_NT;
+        const int t = threadIdx.x + g * NT;
         if (t < nmain) {
-            const int v = t >> (logW - 1), c = t & (hw - 1), q = q0 + (v >> 1);
+            int v, c;
+            split(t, v, c);
+            const int q = q0 + (v >> 1);
             const float2 z1 = pb_cjmul(va[g], vb[g]);
             const float2 z2 = two ? pb_cjmul(vc[g], vd[g]) : make_float2(0.f, 0.f);
             pb_sm[v * lw + pb_pad(c)] = make_float2(z1.x - z2.y, z1.y + z2.x);
@@ -338,7 +476,7 @@ __global__ __launch_bounds__(PB_NT) void k_pb_rowpass(const float2 *__restrict__
             }
         }
     }
-    if (threadIdx.x < 2 * KP) {  // column W/2 is its own mirror
+    if (threadIdx.x < 2 * nq) {  // column W/2 is its own mirror
         const int v = threadIdx.x;
         const int64_t e = (int64_t)pb_row(q0 + (v >> 1), v & 1, H) * WH + hw;
         const float2 z1 = pb_cjmul(fa[e], fb[e]);
@@ -346,13 +484,13 @@ __global__ __launch_bounds__(PB_NT) void k_pb_rowpass(const float2 *__restrict__
         pb_sm[v * lw + pb_pad(hw)] = make_float2(z1.x - z2.y, z1.y + z2.x);
     }
     __syncthreads();
-    float2 *q = Q + (int64_t)blockIdx.y * H * W;
+    float2 *q = Q + (int64_t)blockIdx.y * H * (((W + (1 << logCB) - 1) >> logCB) << logCB);
     const PbLds lds{pb_sm, lw};
     const int cbm = (1 << logCB) - 1;
     auto dst = [&](int v, int e, float2 val) {
         q[((int64_t)(e >> logCB) * H + pb_row(q0 + (v >> 1), v & 1, H)) * (cbm + 1) + (e & cbm)] = val;
     };
-    pb_fft<false, false>(logW, 2 * KP, twW, lds, lds, dst);
+    pb_dft<BLUE, false, false, NT>(dW, 2 * nq, lds, lds, dst);
 }
 
 struct PbStat {
@@ -395,8 +533,9 @@ __device__ __forceinline__ PbStat pb_reduce(PbStat r)
 // Energy of the (2h+1)^2 cells around the peak (r0, c0) of channel ch: the 2h+1 columns
 // around c0 of the row-pass output q are transformed again, CF at a time, by the same code
 // as in the column pass (so to the same values).  Valid in thread 0.
-__device__ double pb_inside(const float2 *__restrict__ q, int H, int logH, int W, int logCB, int h, int CF, int r0,
-                            int c0, int ch, const float2 *__restrict__ twH, const PbLds &lds)
+template <bool BLUE>
+__device__ double pb_inside(const float2 *__restrict__ q, int H, int W, int logCB, int h, int CF, int r0, int c0,
+                            int ch, const PbDim &dH, const PbLds &lds)
 {
     const int cbm = (1 << logCB) - 1;
     const int side = 2 * h + 1;
@@ -404,16 +543,16 @@ __device__ double pb_inside(const float2 *__restrict__ q, int H, int logH, int W
     for (int k0 = 0; k0 < side; k0 += CF) {
         const int m = min(CF, side - k0), cs = c0 - h + k0 + W;
         auto src = [&](int v, int e) {
-            const int c = (cs + v) & (W - 1);
+            const int c = (cs + v) % W;
             return q[((int64_t)(c >> logCB) * H + e) * (cbm + 1) + (c & cbm)];
         };
         auto dst = [&](int v, int e, float2 val) {
-            if (((e - r0 + h + H) & (H - 1)) < side) {
+            if ((e - r0 + h + H) % H < side) {
                 const double x = ch ? val.y : val.x;
                 inside = fma(x, x, inside);
             }
         };
-        pb_fft<true, false>(logH, m, twH, lds, src, dst);
+        pb_dft<BLUE, true, false, PB_NT>(dH, m, lds, src, dst);
     }
     for (int o = 32; o > 0; o >>= 1) inside += __shfl_xor(inside, o);
     __shared__ double red[PB_NT / 64];
@@ -425,33 +564,36 @@ __device__ double pb_inside(const float2 *__restrict__ q, int H, int logH, int W
     return inside;
 }
 
-// Column pass: grid (W / CB, pair-pairs), CB = min(W, PB_TILE / H) columns per workgroup.
-// Transforms the columns of the row-pass output (left as it is) and writes the workgroup's
-// peak (largest value, smallest shift index on ties) and FP64 energy per channel to S.
-__global__ __launch_bounds__(PB_NT) void k_pb_colpass(const float2 *__restrict__ Q, int H, int logH, int W, int CB,
-                                                      const float2 *__restrict__ twH, PbStat *__restrict__ S)
+// Column pass: grid (ceil(W / CBS), pair-pairs): the workgroup's CBS columns (fewer in the
+// last) are transformed from the row-pass output (left as it is), and the workgroup's peak
+// (largest value, smallest shift index on ties) and FP64 energy per channel go to S.  CBS
+// divides the block width CB, or one workgroup covers all W columns.
+template <bool BLUE>
+__global__ __launch_bounds__(PB_NT) void k_pb_colpass(const float2 *__restrict__ Q, int H, int W, int logCB, int CBS,
+                                                      PbDim dH, PbStat *__restrict__ S)
 {
     extern __shared__ float2 pb_sm[];
-    const float2 *q = Q + (int64_t)blockIdx.y * H * W;
-    const int c0 = blockIdx.x * CB;
+    const int CB = 1 << logCB, Wp = ((W + CB - 1) >> logCB) << logCB;
+    const int c0 = blockIdx.x * CBS, nc = min(CBS, W - c0);
+    const float2 *qb = Q + (int64_t)blockIdx.y * H * Wp + (int64_t)(c0 >> logCB) * H * CB + (c0 & (CB - 1));
     PbStat st{-INFINITY, -INFINITY, 0x7fffffff, 0x7fffffff, 0.0, 0.0};
-    const float2 *qb = q + (int64_t)blockIdx.x * H * CB;  // the block's columns: H x CB values in a row
     auto src = [&](int v, int e) { return qb[e * CB + v]; };
     auto dst = [&](int v, int e, float2 val) {
         const int idx = e * W + c0 + v;
         pb_merge(st, val.x, val.y, idx, idx, (double)val.x * val.x, (double)val.y * val.y);
     };
-    pb_fft<true, false>(logH, CB, twH, PbLds{pb_sm, pb_ld(H)}, src, dst);
+    pb_dft<BLUE, true, false, PB_NT>(dH, nc, PbLds{pb_sm, pb_ld(dH.M)}, src, dst);
     st = pb_reduce<PB_NT>(st);
     if (threadIdx.x == 0) S[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = st;
 }
 
 // Final: grid (2 channels, pair-pairs).  The blocks' peaks and energies give the channel's
 // peak s* and total energy; with the energy of the (2h+1)^2 cells around s*, the PCE.
+template <bool BLUE>
 __global__ __launch_bounds__(PB_NT) void k_pb_final(const float2 *__restrict__ Q, const PbStat *__restrict__ S, int nblk,
                                                     const int4 *__restrict__ pp, const int *__restrict__ live, int H,
-                                                    int logH, int W, int logCB, int h, int CF, const float2 *__restrict__ twH,
-                                                    int64_t n, float *__restrict__ out, uint32_t *__restrict__ peak_out)
+                                                    int W, int logCB, int h, int CF, PbDim dH, int64_t n,
+                                                    float *__restrict__ out, uint32_t *__restrict__ peak_out)
 {
     extern __shared__ float2 pb_sm[];
     const int ch = blockIdx.x;
@@ -466,8 +608,9 @@ __global__ __launch_bounds__(PB_NT) void k_pb_final(const float2 *__restrict__ Q
     pb_barrier();
     const int pk = ch ? tot.i1 : tot.i0;
     const bool found = pk != 0x7fffffff;  // false only for NaN surfaces
-    const double inside = pb_inside(Q + (int64_t)blockIdx.y * H * W, H, logH, W, logCB, h, CF, found ? pk / W : 0,
-                                    found ? pk % W : 0, ch, twH, PbLds{pb_sm, pb_ld(H)});
+    const int CB = 1 << logCB, Wp = ((W + CB - 1) >> logCB) << logCB;
+    const double inside = pb_inside<BLUE>(Q + (int64_t)blockIdx.y * H * Wp, H, W, logCB, h, CF, found ? pk / W : 0,
+                                    found ? pk % W : 0, ch, dH, PbLds{pb_sm, pb_ld(dH.M)});
     if (threadIdx.x == 0) {
         const double pv = ch ? tot.v1 : tot.v0, rest = (ch ? tot.e1 : tot.e0) - inside;
         const double num = pv * pv * (double)((int64_t)H * W - (int64_t)(2 * h + 1) * (2 * h + 1));
@@ -489,20 +632,46 @@ int log2_exact(int64_t v)
 // LDS bytes of a workgroup holding M padded vectors of N complex values
 size_t tile_lds(int M, int N) { return (size_t)M * pb_ld(N) * sizeof(float2); }
 
+// FFT length of an N-point axis: N itself for powers of two, else the Bluestein length
+int fft_len(int N)
+{
+    if (log2_exact(N) >= 0) return N;
+    int M = 1;
+    while (M < 2 * N - 1) M *= 2;
+    return M;
+}
+
 struct PbLayout {
-    size_t spec, stats, live, tw;
+    size_t spec, stats, live, tab, part;
+    int MH, MW, nb;
 };
 
-// spectra | per item (mean, 1/norm) | live flags | twiddles of the H- and W-point transforms
+// spectra | per item (mean, 1/norm) | live flags | per axis (H, then W): FFT twiddles (M),
+// Bluestein chirp (N) and filter spectrum (M) | the statistics' chunk sums (two per chunk)
 PbLayout layout(int64_t n, int H, int W)
 {
     const int64_t m = std::max<int64_t>(n, 1);
     PbLayout l;
+    l.MH = fft_len(H);
+    l.MW = fft_len(W);
+    // chunks of at least 16K values per item, at most 64, and at least 2048 workgroups where
+    // the item count allows it
+    const int64_t d = (int64_t)H * W;
+    l.nb = (int)std::max<int64_t>(1, std::min<int64_t>({64, d / 16384, (2048 + m - 1) / m}));
+    l.part = (size_t)m * l.nb * 2 * sizeof(double);
     l.spec = (size_t)m * H * (W / 2 + 1) * sizeof(float2);
     l.stats = (size_t)m * sizeof(double2);
     l.live = ((size_t)m * sizeof(int) + 255) & ~(size_t)255;
-    l.tw = (size_t)(H + W) * sizeof(float2);
+    l.tab = (size_t)(2 * l.MH + H + 2 * l.MW + W) * sizeof(float2);
     return l;
+}
+
+// the axis descriptors over the tables at tab (see layout)
+void axes(const PbLayout &l, int H, int W, float2 *tab, PbDim &dH, PbDim &dW)
+{
+    dH = PbDim{H, l.MH, log2_exact(l.MH), tab, tab + l.MH, tab + l.MH + H};
+    float2 *t = tab + 2 * l.MH + H;
+    dW = PbDim{W, l.MW, log2_exact(l.MW), t, t + l.MW, t + l.MW + W};
 }
 
 rocket_status set_lds(rocket_ctx *ctx, const void *k, size_t bytes)
@@ -515,8 +684,8 @@ rocket_status set_lds(rocket_ctx *ctx, const void *k, size_t bytes)
 
 bool pce_big_shape(int64_t H, int64_t W)
 {
-    const int lh = log2_exact(H), lw = log2_exact(W);
-    return lh >= 4 && lh <= 11 && lw >= 4 && lw <= 11;
+    // even sides in [16, 4096] (FFT lengths up to 8192: one LDS tile), at most 2^24 values
+    return H >= 16 && W >= 16 && H <= 4096 && W <= 4096 && H % 2 == 0 && W % 2 == 0 && H * W <= ((int64_t)1 << 24);
 }
 
 rocket_status pce_big_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, int H, int W, hipStream_t s)
@@ -526,29 +695,42 @@ rocket_status pce_big_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n
     const PbLayout l = layout(n, H, W);
     ctx->trace_valid = false;  // batched launches, no persistent queue to trace
     void *buf = nullptr;
-    RK_TRY(ws_get(ctx, WS_PCE_SPEC, l.spec + l.stats + l.live + l.tw, &buf));
+    RK_TRY(ws_get(ctx, WS_PCE_SPEC, l.spec + l.stats + l.live + l.tab + l.part, &buf));
     float2 *F = (float2 *)buf;
     double2 *st = (double2 *)((char *)buf + l.spec);
     int *live = (int *)((char *)st + l.stats);
-    float2 *twH = (float2 *)((char *)live + l.live), *twW = twH + H;
-    const int logH = log2_exact(H), logW = log2_exact(W);
-    hipLaunchKernelGGL(k_pb_twiddles, dim3(8), dim3(256), 0, s, twH, logH);
-    hipLaunchKernelGGL(k_pb_twiddles, dim3(8), dim3(256), 0, s, twW, logW);
-    RK_HIP(hipGetLastError());
-    if (n > 0) {
-        hipLaunchKernelGGL(k_pb_stats, dim3((unsigned)n), dim3(PB_THREADS), 0, s, it->dense, it->ld, it->dim, st, live);
+    PbDim dH, dW;
+    axes(l, H, W, (float2 *)((char *)live + l.live), dH, dW);
+    for (const PbDim *d : {&dH, &dW}) {
+        hipLaunchKernelGGL(k_pb_twiddles, dim3(8), dim3(256), 0, s, (float2 *)d->tw, d->logM);
+        if (d->M != d->N)
+            hipLaunchKernelGGL(k_pb_chirp, dim3((unsigned)((d->M + 255) / 256)), dim3(256), 0, s, d->N, d->M,
+                               (float2 *)d->chirp, (float2 *)d->filt);
         RK_HIP(hipGetLastError());
-        const int RB = std::min(H, PB_TILE / W);         // rows per workgroup
-        const int CB = PB_TILE / H;  // columns per workgroup (WH is not a power of two)
-        const size_t rl = tile_lds(RB, W), cl = tile_lds(CB, H);
-        RK_TRY(set_lds(ctx, (const void *)&k_pb_prep_rows, rl));
-        RK_TRY(set_lds(ctx, (const void *)&k_pb_prep_cols, cl));
+    }
+    if (n > 0) {
+        double *part = (double *)((char *)live + l.live + l.tab), *part2 = part + n * l.nb;
+        hipLaunchKernelGGL(k_pb_sum, dim3((unsigned)n, (unsigned)l.nb), dim3(PB_THREADS), 0, s, it->dense, it->ld,
+                           it->dim, part);
+        hipLaunchKernelGGL(k_pb_sumsq, dim3((unsigned)n, (unsigned)l.nb), dim3(PB_THREADS), 0, s, it->dense, it->ld,
+                           it->dim, (const double *)part, part2);
+        hipLaunchKernelGGL(k_pb_stats, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (const double *)part,
+                           (const double *)part2, l.nb, n, it->dim, st, live);
+        RK_HIP(hipGetLastError());
+        const int RB = std::min(H, PB_TILE / l.MW);  // rows per workgroup
+        const int CB = PB_TILE / l.MH;               // columns per workgroup
+        const size_t rl = tile_lds(RB, l.MW), cl = tile_lds(CB, l.MH);
+        // Bluestein instantiations per axis (a side that is not a power of two)
+        const auto kr = l.MW != W ? &k_pb_prep_rows<true> : &k_pb_prep_rows<false>;
+        const auto kc = l.MH != H ? &k_pb_prep_cols<true> : &k_pb_prep_cols<false>;
+        RK_TRY(set_lds(ctx, (const void *)kr, rl));
+        RK_TRY(set_lds(ctx, (const void *)kc, cl));
         for (int64_t i0 = 0; i0 < n; i0 += 65535) {
             const unsigned ni = (unsigned)std::min<int64_t>(65535, n - i0);
-            hipLaunchKernelGGL(k_pb_prep_rows, dim3((unsigned)(H / RB), ni), dim3(PB_NT), rl, s, it->dense, it->ld, H, W,
-                               logW, RB, i0, st, twW, F);
-            hipLaunchKernelGGL(k_pb_prep_cols, dim3((unsigned)((WH + CB - 1) / CB), ni), dim3(PB_NT), cl, s, F, H, logH,
-                               WH, CB, i0, twH);
+            hipLaunchKernelGGL(kr, dim3((unsigned)((H + RB - 1) / RB), ni), dim3(PB_NT), rl, s, it->dense,
+                               it->ld, H, W, RB, i0, st, dW, F);
+            hipLaunchKernelGGL(kc, dim3((unsigned)((WH + CB - 1) / CB), ni), dim3(PB_NT), cl, s, F, H, WH,
+                               CB, i0, dH);
             RK_HIP(hipGetLastError());
         }
     }
@@ -599,17 +781,27 @@ rocket_status pce_big_compare(rocket_ctx *ctx, float *out, uint32_t *peak, int h
     const PbLayout l = layout(n, H, W);
     const float2 *F = (const float2 *)ctx->ws[WS_PCE_SPEC].ptr;
     const int *live = (const int *)((const char *)F + l.spec + l.stats);
-    const float2 *twH = (const float2 *)((const char *)live + l.live), *twW = twH + H;
-    // columns per column-pass workgroup; the staged transform is stored column block by column
-    // block ([W / CB][H][CB]), so that each column-pass workgroup reads one contiguous piece
-    const int CB = std::min(W, PB_TILE / H), logCB = log2_exact(CB);
-    const int KP = std::min(H / 2, PB_TILE / (2 * W));                 // row pairs per row-pass workgroup
-    const int nblk = W / CB;
-    // batch of pair-pairs: one staged H x W complex transform and nblk block statistics each
-    const int64_t per = (int64_t)H * W * (int64_t)sizeof(float2) + nblk * (int64_t)sizeof(PbStat);
+    PbDim dH, dW;
+    axes(l, H, W, (float2 *)((const char *)live + l.live), dH, dW);
+    // column-pass workgroups: CBS columns each (one LDS tile).  The staged transform is stored
+    // column block by column block ([ceil(W / CB)][H][CB], CB a power of two >= CBS, at least 8
+    // where W allows, so that the row pass stores runs of 64 bytes or more), so that the
+    // workgroups of one block read one contiguous piece
+    const int CBS = std::min(W, PB_TILE / l.MH);
+    int CB = 1;
+    while (CB < std::min(W, std::max(CBS, 8))) CB *= 2;
+    const int logCB = log2_exact(CB), Wp = (W + CB - 1) / CB * CB;
+    const int nblk = (W + CBS - 1) / CBS;  // column-pass workgroups (and statistics) per transform
+    // row-pass workgroups: KP mirror row pairs, 2 KP vectors of MW values (1024 threads when a
+    // row pair of the longest transforms needs 16K values)
+    const bool wide = 2 * l.MW > PB_TILE;
+    const int KP = std::max(1, std::min(H / 2, (wide ? 2 : 1) * PB_TILE / (2 * l.MW)));
+    const int lhw = log2_exact(W / 2);
+    // batch of pair-pairs: one staged H x Wp complex transform and nblk block statistics each
+    const int64_t per = (int64_t)H * Wp * (int64_t)sizeof(float2) + nblk * (int64_t)sizeof(PbStat);
     // default: as many transforms as 512 MiB holds (64 of 1024 x 1024), plus their statistics
     int64_t budget = (ctx->opt[ROCKET_OPT_PCE_BATCH] > 0 ? ctx->opt[ROCKET_OPT_PCE_BATCH]
-                                                          : std::max<int64_t>(1, PB_STAGE_BYTES / ((int64_t)H * W * 8))) *
+                                                          : std::max<int64_t>(1, PB_STAGE_BYTES / ((int64_t)H * Wp * 8))) *
                      per;
     const int64_t held = (int64_t)ctx->ws[WS_PCE_STAGE].bytes;
     if (ctx->arena)  // a slot that grows takes a new piece of the arena
@@ -621,25 +813,33 @@ rocket_status pce_big_compare(rocket_ctx *ctx, float *out, uint32_t *peak, int h
     void *stage = nullptr;
     RK_TRY(ws_get(ctx, WS_PCE_STAGE, (size_t)(B * per), &stage));
     float2 *Q = (float2 *)stage;
-    PbStat *S = (PbStat *)((char *)stage + B * (int64_t)H * W * sizeof(float2));
+    PbStat *S = (PbStat *)((char *)stage + B * (int64_t)H * Wp * sizeof(float2));
     const int4 *pp = (const int4 *)ctx->ws[WS_QUEUE_ITEMS].ptr;
-    const int logH = log2_exact(H), logW = log2_exact(W);
-    const size_t rl = tile_lds(2 * KP, W), cl = tile_lds(CB, H);
-    RK_TRY(set_lds(ctx, (const void *)&k_pb_rowpass, rl));
-    RK_TRY(set_lds(ctx, (const void *)&k_pb_colpass, cl));
-    const int CF = std::min(2 * h + 1, PB_TILE / H);  // neighbourhood columns transformed at a time
-    const size_t fl = tile_lds(CF, H);
-    RK_TRY(set_lds(ctx, (const void *)&k_pb_final, fl));
+    const size_t rl = tile_lds(2 * KP, l.MW), cl = tile_lds(CBS, l.MH);
+    // Bluestein instantiations per axis; the wide row pass exists only for those (MW = 8192)
+    const bool bw = l.MW != W, bh = l.MH != H;
+    const auto kr = bw ? &k_pb_rowpass<PB_NT, true> : &k_pb_rowpass<PB_NT, false>;
+    const auto kw = &k_pb_rowpass<2 * PB_NT, true>;
+    const auto kc = bh ? &k_pb_colpass<true> : &k_pb_colpass<false>;
+    const auto kf = bh ? &k_pb_final<true> : &k_pb_final<false>;
+    RK_TRY(set_lds(ctx, wide ? (const void *)kw : (const void *)kr, rl));
+    RK_TRY(set_lds(ctx, (const void *)kc, cl));
+    const int CF = std::min(2 * h + 1, PB_TILE / l.MH);  // neighbourhood columns transformed at a time
+    const size_t fl = tile_lds(CF, l.MH);
+    RK_TRY(set_lds(ctx, (const void *)kf, fl));
     ctx->stats.grid = B;
     RK_TRY(timing_begin(ctx, s));
+    const unsigned rgrid = (unsigned)((H / 2 + KP - 1) / KP);
     for (int64_t q0 = 0; q0 < npp; q0 += B) {
         const unsigned nb = (unsigned)std::min<int64_t>(B, npp - q0);
-        hipLaunchKernelGGL(k_pb_rowpass, dim3((unsigned)(H / (2 * KP)), nb), dim3(PB_NT), rl, s, F, pp + q0, H, W, logW, KP,
-                           logCB, twW, Q);
-        hipLaunchKernelGGL(k_pb_colpass, dim3((unsigned)nblk, nb), dim3(PB_NT), cl, s, (const float2 *)Q, H, logH, W, CB,
-                           twH, S);
-        hipLaunchKernelGGL(k_pb_final, dim3(2, nb), dim3(PB_NT), fl, s, (const float2 *)Q, (const PbStat *)S, nblk, pp + q0,
-                           live, H, logH, W, logCB, h, CF, twH, n, out, peak);
+        if (wide)
+            hipLaunchKernelGGL(kw, dim3(rgrid, nb), dim3(2 * PB_NT), rl, s, F, pp + q0, H, W, lhw, KP, logCB, dW, Q);
+        else
+            hipLaunchKernelGGL(kr, dim3(rgrid, nb), dim3(PB_NT), rl, s, F, pp + q0, H, W, lhw, KP, logCB, dW, Q);
+        hipLaunchKernelGGL(kc, dim3((unsigned)nblk, nb), dim3(PB_NT), cl, s, (const float2 *)Q, H, W, logCB, CBS,
+                           dH, S);
+        hipLaunchKernelGGL(kf, dim3(2, nb), dim3(PB_NT), fl, s, (const float2 *)Q, (const PbStat *)S, nblk, pp + q0,
+                           live, H, W, logCB, h, CF, dH, n, out, peak);
         RK_HIP(hipGetLastError());
     }
     RK_TRY(timing_end(ctx, s));

@@ -1,5 +1,6 @@
 """GPU PCE of images larger than one LDS tile (forensics PCE variant, Section V-A) against
-the FP64 oracle: H x W items with H and W powers of two, pair transforms staged in HBM.
+the FP64 oracle: H x W items with H and W even (a side that is not a power of two by
+Bluestein's chirp convolution), pair transforms staged in HBM.
 
 Pass metric as for the in-LDS sizes: |g - r| <= 1e-5 * r, with r the oracle's PCE at the
 GPU's peak shift; that peak must be the oracle's argmax, or (where the two largest
@@ -94,6 +95,51 @@ def test_smallest_and_largest_square(ctx, L):
         assert gpk[idx] == ((sh[i, 0] - sh[j, 0]) % L) * L + (sh[i, 1] - sh[j, 1]) % L
 
 
+def _check_shifts(gpk, c, sh, H, W):
+    n = len(c)
+    for i in range(n):
+        for j in range(i + 1, n):
+            if c[i] == c[j]:  # same source: the peak is the relative shift of the two crops
+                idx = i * n - i * (i + 1) // 2 + (j - i - 1)
+                assert gpk[idx] == ((sh[i, 0] - sh[j, 0]) % H) * W + (sh[i, 1] - sh[j, 1]) % W, (i, j)
+
+
+@pytest.mark.parametrize("H,W", [(48, 80), (96, 40), (100, 64), (64, 100), (18, 30), (1000, 16)])
+def test_all_pairs_not_powers_of_two(ctx, H, W):
+    # one side or both not a power of two: Bluestein along those axes (FFT lengths 64 .. 2048)
+    n = 11
+    announce("pce staged bluestein all pairs n=%d %dx%d" % (n, H, W))
+    X, c, sh = synth.noise_images(n, (H, W), nsrc=3, amp=1.0, p_shift=0.7, config=6, salt=H + 5 * W)
+    got, gpk = _run(ctx, X, W)
+    pairs = [(i, j) for i in range(n) for j in range(i + 1, n)]
+    announce("max rel err %.2e" % _check(got, gpk, X, H, W, pairs))
+    _check_shifts(gpk, c, sh, H, W)
+
+
+@pytest.mark.parametrize("H,W", [(2050, 16), (16, 4094), (4096, 16)])
+def test_longest_axes(ctx, H, W):
+    # 8192-point transforms: Bluestein columns one per group in the column pass (2050), Bluestein
+    # rows through the 1024-thread row pass (4094), and the longest power-of-two side (4096)
+    n = 6
+    announce("pce staged all pairs n=%d %dx%d" % (n, H, W))
+    X, c, sh = synth.noise_images(n, (H, W), nsrc=2, amp=1.0, p_shift=0.7, config=6, salt=H + 9 * W)
+    got, gpk = _run(ctx, X, W)
+    pairs = [(i, j) for i in range(n) for j in range(i + 1, n)]
+    announce("max rel err %.2e" % _check(got, gpk, X, H, W, pairs))
+    _check_shifts(gpk, c, sh, H, W)
+
+
+def test_camera_sensor_size(ctx):
+    # 3648 x 2736, a camera sensor's pixel grid: both axes by Bluestein with 8192-point FFTs
+    H, W, n = 3648, 2736, 3
+    announce("pce staged bluestein n=%d %dx%d" % (n, H, W))
+    X, c, sh = synth.noise_images(n, (H, W), nsrc=1, amp=0.3, p_shift=1.0, config=6, salt=3648)
+    got, gpk = _run(ctx, X, W)
+    pairs = [(0, 1), (0, 2), (1, 2)]
+    announce("max rel err %.2e" % _check(got, gpk, X, H, W, pairs))
+    _check_shifts(gpk, c, sh, H, W)
+
+
 def test_shifted_copies_and_constant_item(ctx):
     announce("pce staged shifted copies 256x1024")
     H, W = 256, 1024
@@ -158,8 +204,9 @@ def test_errors(ctx):
     import torch
     from paper_2009_04755_amd._lib import RocketError, E_INVALID, E_UNSUPPORTED
     announce("pce staged errors")
-    bad = [(48 * 48, 0), (100 * 64, 100), (1000, 64), (4096 * 16, 4096), (8 * 64, 64)]
-    for dim, w in bad:  # not powers of two, width not dividing, a side above 2048 or below 16
+    bad = [(45 * 45, 0), (64 * 99, 99), (99 * 64, 64), (1000, 64), (4098 * 16, 16),
+           (16 * 4098, 4098), (8 * 64, 64)]
+    for dim, w in bad:  # odd sides, width not dividing, a side above 4096 or below 16
         ctx.set(pce_width=w)
         try:
             with pytest.raises(RocketError) as e:

@@ -74,7 +74,7 @@ def test_rectangular_correlation_matches_explicit_sum():
     np.testing.assert_allclose(pce.correlation(a, b), C, rtol=0, atol=1e-12)
 
 
-@pytest.mark.parametrize("H,W", [(256, 512), (1024, 1024)])
+@pytest.mark.parametrize("H,W", [(256, 512), (1024, 1024), (96, 40)])
 def test_large_correlation_matches_explicit_sums_at_sampled_shifts(H, W):
     g = np.random.default_rng(H + W)
     a = g.standard_normal((H, W))
@@ -91,7 +91,8 @@ def test_large_correlation_matches_explicit_sums_at_sampled_shifts(H, W):
     assert int(np.argmax(C)) == (H - 17) * W + 5
 
 
-@pytest.mark.parametrize("H,W,k,h,axis", [(16, 32, 3, 2, 1), (32, 16, 3, 2, 1), (64, 16, 5, 3, 0)])
+@pytest.mark.parametrize("H,W,k,h,axis", [(16, 32, 3, 2, 1), (32, 16, 3, 2, 1), (64, 16, 5, 3, 0), (48, 80, 7, 3, 1),
+                                           (36, 20, 4, 2, 0)])
 def test_rectangular_cosine_wave_closed_form(H, W, k, h, axis):
     # a = b = cos(2 pi k t / n) along one axis of n values: C(s) = (H W / 2) cos(2 pi k s_axis / n),
     # PCE = (H W - (2h+1)^2) / (H W / 2 - (2h+1) S),  S = sum_{|t|<=h} cos^2(2 pi k t / n)
