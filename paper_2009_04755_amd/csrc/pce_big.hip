@@ -10,20 +10,22 @@
 //
 // Compare: pairs are visited tile by tile (T x T items, divide-and-conquer leaves), two at a
 // time: P = conj(F_a) F_b + i conj(F_c) F_d is the spectrum of H W (C_1 + i C_2), both C real.
-// A batch of such pair-pairs runs as three kernels with the transform staged in HBM:
+// A batch of such pair-pairs runs as four kernels with the transform staged in HBM:
 //   row pass     per pair-pair and group of mirror row pairs {q, H - q}: build those rows of P
 //                over all W columns from the four half spectra (Hermitian mirror for columns
 //                > W/2) and transform them along the row;
-//   column pass  per pair-pair and block of columns: transform along the columns and keep
-//                only the block's peak (largest value, smallest shift index r W + c on ties)
+//   column pass  per pair-pair and group of columns: transform along the columns and keep
+//                only the group's peak (largest value, smallest shift index r W + c on ties)
 //                and its FP64 energy per channel (H W C is not written back);
-//   final        per pair-pair and channel: the overall peak and energy, the 2h+1 columns
-//                around the peak transformed again (by the same code, so to the same values)
-//                for the energy of the (2h+1)^2 cells around it, and the PCE.
-// The staged transform of a pair-pair is stored as ceil(W/CB) blocks of H x CB values (CB
-// columns per column-pass workgroup), so that each column-pass workgroup reads one contiguous
-// piece.  Every FFT kernel works on one tile of 8K complex values in LDS with 512 threads
-// (1024 for a row pair of 8K-point transforms): radix-16 Stockham passes in registers
+//   peak         per pair-pair, channel and group of the 2h+1 columns around the peak: the
+//                overall peak and energy, and those columns transformed again (by the same
+//                code, so to the same values) for their energy inside the (2h+1)^2 cells
+//                around the peak;
+//   pce          per pair-pair and channel: the neighbourhood energy summed, and the PCE.
+// The staged transform of a pair-pair is stored as ceil(W/CB) blocks of H x CB values, so
+// that the column-pass workgroups of a block read one contiguous piece.  Every FFT kernel
+// works on one tile of 8K complex values in LDS with 512 threads (1024 for a row pair of
+// 8K-point transforms): radix-16 Stockham passes in registers
 // (natural order in and out; pass twiddles computed in FP64 and rounded once), one padding
 // slot per 16 values against bank conflicts.  An axis of N values, N not a power of two, is
 // an M-point FFT, its product with the chirp filter's spectrum and an inverse M-point FFT in
@@ -108,6 +110,23 @@ __device__ __forceinline__ int pb_pad(int e) { return e + (e >> 4); }
 // Vector stride of M vectors of N values in LDS (odd, so that neighbouring vectors start
 // in different banks).
 __host__ __device__ __forceinline__ int pb_ld(int N) { return N + N / 16 + 1; }
+
+// Workgroup coordinates in an XCD-aware order.  Workgroups go to the 8 XCDs (each with its
+// own L2) round-robin by linear id, so neighbours in the grid run on different XCDs; when
+// neighbouring workgroups read parts of the same cache lines (columns narrower than a line)
+// every XCD would fetch each line.  Renumbered, XCD k takes the k-th eighth of the grid in
+// order (the remainder of a grid not divisible by 8 keeps its place).
+__device__ __forceinline__ void pb_xcd_order(bool on, int &x, int &y)
+{
+    x = blockIdx.x;
+    y = blockIdx.y;
+    if (!on) return;
+    const int64_t total = (int64_t)gridDim.x * gridDim.y, lin = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    if (lin >= total / 8 * 8) return;
+    const int64_t l = (lin & 7) * (total / 8) + (lin >> 3);
+    y = (int)(l / gridDim.x);
+    x = (int)(l - (int64_t)y * gridDim.x);
+}
 
 // Unit u of a pass over M vectors, N/R = 2^logQ units per vector: vector v and index j.  Row
 // kernels put consecutive units on consecutive j of one vector; column kernels (VF) put them
@@ -272,31 +291,35 @@ __global__ void k_pb_twiddles(float2 *tw, int logN)
 
 // Bluestein tables of an N-point DFT computed with M-point FFTs, FP64 rounded once: the chirp
 // w_n = exp(-i pi n^2 / N) (angles reduced exactly: n^2 mod 2N) and the filter spectrum
-// B_k = sum_m b_m exp(-2 pi i m k / M) over the 2N - 1 non-zero b_m, one k per thread.
-__global__ void k_pb_chirp(int N, int M, float2 *__restrict__ chirp, float2 *__restrict__ filt)
+// B_k = sum_m b_m exp(-2 pi i m k / M) over the 2N - 1 non-zero b_m.  Grid (M): one wave per
+// k, lane l summing m = l, l + 64, ..., then a fixed shuffle tree; workgroup 0 also writes w.
+__global__ __launch_bounds__(64) void k_pb_chirp(int N, int M, float2 *__restrict__ chirp, float2 *__restrict__ filt)
 {
-    const int stride = gridDim.x * blockDim.x;
-    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < N; n += stride) {
-        double sn, cs;
-        sincospi(-(double)(((int64_t)n * n) % (2 * N)) / N, &sn, &cs);
-        chirp[n] = make_float2((float)cs, (float)sn);
-    }
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < M; k += stride) {
-        double re = 0.0, im = 0.0;
-        for (int m = 0; m < N; ++m) {  // b_m = exp(i pi m^2 / N) at m and at M - m
-            const double a = (double)(((int64_t)m * m) % (2 * N)) / N, t = 2.0 * (double)(((int64_t)m * k) % M) / M;
+    const int k = blockIdx.x;
+    if (k == 0)
+        for (int n = threadIdx.x; n < N; n += 64) {
             double sn, cs;
-            sincospi(a - t, &sn, &cs);
+            sincospi(-(double)(((int64_t)n * n) % (2 * N)) / N, &sn, &cs);
+            chirp[n] = make_float2((float)cs, (float)sn);
+        }
+    double re = 0.0, im = 0.0;
+    for (int m = threadIdx.x; m < N; m += 64) {  // b_m = exp(i pi m^2 / N) at m and at M - m
+        const double a = (double)(((int64_t)m * m) % (2 * N)) / N, t = 2.0 * (double)(((int64_t)m * k) % M) / M;
+        double sn, cs;
+        sincospi(a - t, &sn, &cs);
+        re += cs;
+        im += sn;
+        if (m > 0) {
+            sincospi(a + t, &sn, &cs);
             re += cs;
             im += sn;
-            if (m > 0) {
-                sincospi(a + t, &sn, &cs);
-                re += cs;
-                im += sn;
-            }
         }
-        filt[k] = make_float2((float)re, (float)im);
     }
+    for (int o = 32; o > 0; o >>= 1) {
+        re += __shfl_xor(re, o);
+        im += __shfl_xor(im, o);
+    }
+    if (threadIdx.x == 0) filt[k] = make_float2((float)re, (float)im);
 }
 
 // Per-item statistics, FP64, in three launches so that a large item is read by many
@@ -404,8 +427,10 @@ __global__ __launch_bounds__(PB_NT) void k_pb_prep_cols(float2 *__restrict__ F, 
                                                         PbDim dH)
 {
     extern __shared__ float2 pb_sm[];
-    float2 *f = F + (i0 + blockIdx.y) * (int64_t)H * WH + blockIdx.x * CB;
-    const int nc = min(CB, WH - (int)blockIdx.x * CB);
+    int bx, by;
+    pb_xcd_order(CB < 8, bx, by);  // fewer than 8 columns: rows of 64 bytes shared by workgroups
+    float2 *f = F + (i0 + by) * (int64_t)H * WH + bx * CB;
+    const int nc = min(CB, WH - bx * CB);
     auto src = [&](int v, int e) { return f[(int64_t)e * WH + v]; };
     auto dst = [&](int v, int e, float2 val) { f[(int64_t)e * WH + v] = val; };
     pb_dft<BLUE, true, true, PB_NT>(dH, nc, PbLds{pb_sm, pb_ld(dH.M)}, src, dst);
@@ -493,6 +518,52 @@ __global__ __launch_bounds__(NT) void k_pb_rowpass(const float2 *__restrict__ F,
     pb_dft<BLUE, false, false, NT>(dW, 2 * nq, lds, lds, dst);
 }
 
+// Row pass for rows of 8K-point transforms: grid (H, pair-pairs), one row per workgroup of
+// PB_NT threads and one LDS vector (two workgroups per CU).  Row r takes columns 0 .. W/2 from
+// the half spectra at row r and columns W - c from its mirror row (as in k_pb_rowpass); the
+// two workgroups of a mirror pair are neighbours in the XCD-aware order, so the second
+// reads the shared spectra rows from the same L2.
+template <bool BLUE>
+__global__ __launch_bounds__(PB_NT) void k_pb_rowpass_one(const float2 *__restrict__ F, const int4 *__restrict__ pp,
+                                                          int H, int W, int logCB, PbDim dW, float2 *__restrict__ Q)
+{
+    extern __shared__ float2 pb_sm[];
+    int bx, by;
+    pb_xcd_order(true, bx, by);
+    const int4 p = pp[by];
+    const int q0 = bx >> 1, slot = bx & 1, WH = W / 2 + 1, hw = W / 2;
+    const int r = pb_row(q0, slot, H), rm = pb_row(q0, q0 ? slot ^ 1 : slot, H);  // rows 0, H/2: own mirrors
+    const int64_t NH = (int64_t)H * WH;
+    const bool two = p.z >= 0;
+    const float2 *fa = F + p.x * NH, *fb = F + p.y * NH;
+    const float2 *fc = F + (two ? p.z : p.x) * NH, *fd = F + (two ? p.w : p.y) * NH;
+    // column c of row r is z1 + i z2 at (r, c); column W - c is conj(z1) + i conj(z2) at (rm, c)
+    constexpr int G = 4096 / 2 / PB_NT;  // columns 0 .. W/2 - 1 per thread (W <= 4096)
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int c = threadIdx.x + g * PB_NT;
+        if (c < hw) {
+            const int64_t e = (int64_t)r * WH + c, em = (int64_t)rm * WH + c;
+            const float2 u1 = pb_cjmul(fa[e], fb[e]), m1 = pb_cjmul(fa[em], fb[em]);
+            const float2 u2 = two ? pb_cjmul(fc[e], fd[e]) : make_float2(0.f, 0.f);
+            const float2 m2 = two ? pb_cjmul(fc[em], fd[em]) : make_float2(0.f, 0.f);
+            pb_sm[pb_pad(c)] = make_float2(u1.x - u2.y, u1.y + u2.x);
+            if (c > 0) pb_sm[pb_pad(W - c)] = make_float2(m1.x + m2.y, m2.x - m1.y);
+        }
+    }
+    if (threadIdx.x == 0) {  // column W/2 is its own mirror
+        const int64_t e = (int64_t)r * WH + hw;
+        const float2 z1 = pb_cjmul(fa[e], fb[e]);
+        const float2 z2 = two ? pb_cjmul(fc[e], fd[e]) : make_float2(0.f, 0.f);
+        pb_sm[pb_pad(hw)] = make_float2(z1.x - z2.y, z1.y + z2.x);
+    }
+    pb_barrier();
+    const int CB = 1 << logCB, cbm = CB - 1;
+    float2 *qo = Q + (int64_t)by * H * ((W + CB - 1) / CB * CB);
+    auto dst = [&](int v, int e, float2 x) { qo[((int64_t)(e >> logCB) * H + r) * CB + (e & cbm)] = x; };
+    pb_dft<BLUE, false, false, PB_NT>(dW, 1, PbLds{pb_sm, pb_ld(dW.M)}, PbLds{pb_sm, pb_ld(dW.M)}, dst);
+}
+
 struct PbStat {
     float v0, v1;  // largest value per channel
     int i0, i1;    // its shift index r W + c (the smallest on ties)
@@ -530,30 +601,29 @@ __device__ __forceinline__ PbStat pb_reduce(PbStat r)
     return r;
 }
 
-// Energy of the (2h+1)^2 cells around the peak (r0, c0) of channel ch: the 2h+1 columns
-// around c0 of the row-pass output q are transformed again, CF at a time, by the same code
-// as in the column pass (so to the same values).  Valid in thread 0.
+// Energy of the cells of the (2h+1)^2 neighbourhood of the peak (r0, c0) of channel ch in
+// columns k0 .. k0 + m - 1 of it (at most one LDS tile): those columns of the row-pass output
+// q are transformed again by the same code as in the column pass (so to the same values).
+// Valid in thread 0.
 template <bool BLUE>
-__device__ double pb_inside(const float2 *__restrict__ q, int H, int W, int logCB, int h, int CF, int r0, int c0,
-                            int ch, const PbDim &dH, const PbLds &lds)
+__device__ double pb_inside(const float2 *__restrict__ q, int H, int W, int logCB, int h, int k0, int m, int r0,
+                            int c0, int ch, const PbDim &dH, const PbLds &lds)
 {
     const int cbm = (1 << logCB) - 1;
     const int side = 2 * h + 1;
     double inside = 0.0;
-    for (int k0 = 0; k0 < side; k0 += CF) {
-        const int m = min(CF, side - k0), cs = c0 - h + k0 + W;
-        auto src = [&](int v, int e) {
-            const int c = (cs + v) % W;
-            return q[((int64_t)(c >> logCB) * H + e) * (cbm + 1) + (c & cbm)];
-        };
-        auto dst = [&](int v, int e, float2 val) {
-            if ((e - r0 + h + H) % H < side) {
-                const double x = ch ? val.y : val.x;
-                inside = fma(x, x, inside);
-            }
-        };
-        pb_dft<BLUE, true, false, PB_NT>(dH, m, lds, src, dst);
-    }
+    const int cs = c0 - h + k0 + W;
+    auto src = [&](int v, int e) {
+        const int c = (cs + v) % W;
+        return q[((int64_t)(c >> logCB) * H + e) * (cbm + 1) + (c & cbm)];
+    };
+    auto dst = [&](int v, int e, float2 val) {
+        if ((e - r0 + h + H) % H < side) {
+            const double x = ch ? val.y : val.x;
+            inside = fma(x, x, inside);
+        }
+    };
+    pb_dft<BLUE, true, false, PB_NT>(dH, m, lds, src, dst);
     for (int o = 32; o > 0; o >>= 1) inside += __shfl_xor(inside, o);
     __shared__ double red[PB_NT / 64];
     pb_barrier();
@@ -574,8 +644,10 @@ __global__ __launch_bounds__(PB_NT) void k_pb_colpass(const float2 *__restrict__
 {
     extern __shared__ float2 pb_sm[];
     const int CB = 1 << logCB, Wp = ((W + CB - 1) >> logCB) << logCB;
-    const int c0 = blockIdx.x * CBS, nc = min(CBS, W - c0);
-    const float2 *qb = Q + (int64_t)blockIdx.y * H * Wp + (int64_t)(c0 >> logCB) * H * CB + (c0 & (CB - 1));
+    int bx, by;
+    pb_xcd_order(CBS < CB, bx, by);  // the workgroups of one block share its cache lines
+    const int c0 = bx * CBS, nc = min(CBS, W - c0);
+    const float2 *qb = Q + (int64_t)by * H * Wp + (int64_t)(c0 >> logCB) * H * CB + (c0 & (CB - 1));
     PbStat st{-INFINITY, -INFINITY, 0x7fffffff, 0x7fffffff, 0.0, 0.0};
     auto src = [&](int v, int e) { return qb[e * CB + v]; };
     auto dst = [&](int v, int e, float2 val) {
@@ -584,42 +656,63 @@ __global__ __launch_bounds__(PB_NT) void k_pb_colpass(const float2 *__restrict__
     };
     pb_dft<BLUE, true, false, PB_NT>(dH, nc, PbLds{pb_sm, pb_ld(dH.M)}, src, dst);
     st = pb_reduce<PB_NT>(st);
-    if (threadIdx.x == 0) S[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = st;
+    if (threadIdx.x == 0) S[(int64_t)by * gridDim.x + bx] = st;
 }
 
-// Final: grid (2 channels, pair-pairs).  The blocks' peaks and energies give the channel's
-// peak s* and total energy; with the energy of the (2h+1)^2 cells around s*, the PCE.
+// Peak and neighbourhood: grid (2 G, pair-pairs), workgroup (channel, group g of CF of the
+// 2h+1 columns around the peak).  Each workgroup merges the blocks' statistics into the
+// channel's peak s* and total energy (the same in every workgroup), transforms its columns
+// again and writes their energy inside the (2h+1)^2 neighbourhood to E; group 0 also writes
+// the channel's totals to T.
 template <bool BLUE>
-__global__ __launch_bounds__(PB_NT) void k_pb_final(const float2 *__restrict__ Q, const PbStat *__restrict__ S, int nblk,
-                                                    const int4 *__restrict__ pp, const int *__restrict__ live, int H,
-                                                    int W, int logCB, int h, int CF, PbDim dH, int64_t n,
-                                                    float *__restrict__ out, uint32_t *__restrict__ peak_out)
+__global__ __launch_bounds__(PB_NT) void k_pb_peak(const float2 *__restrict__ Q, const PbStat *__restrict__ S, int nblk,
+                                                   const int4 *__restrict__ pp, int H, int W, int logCB, int h, int CF,
+                                                   PbDim dH, PbStat *__restrict__ T, double *__restrict__ E)
 {
     extern __shared__ float2 pb_sm[];
-    const int ch = blockIdx.x;
+    const int ch = blockIdx.x & 1, g = blockIdx.x >> 1, G = gridDim.x >> 1;
     const int4 p = pp[blockIdx.y];
     if (ch == 1 && p.z < 0) return;  // a single pair: no second channel (uniform over the workgroup)
     const PbStat *s = S + (int64_t)blockIdx.y * nblk;
     PbStat r{-INFINITY, -INFINITY, 0x7fffffff, 0x7fffffff, 0.0, 0.0};
     for (int b = threadIdx.x; b < nblk; b += PB_NT) pb_merge(r, s[b].v0, s[b].v1, s[b].i0, s[b].i1, s[b].e0, s[b].e1);
     r = pb_reduce<PB_NT>(r);
-    __shared__ PbStat tot;
-    if (threadIdx.x == 0) tot = r;
+    __shared__ int pk;
+    if (threadIdx.x == 0) pk = ch ? r.i1 : r.i0;
     pb_barrier();
-    const int pk = ch ? tot.i1 : tot.i0;
     const bool found = pk != 0x7fffffff;  // false only for NaN surfaces
     const int CB = 1 << logCB, Wp = ((W + CB - 1) >> logCB) << logCB;
-    const double inside = pb_inside<BLUE>(Q + (int64_t)blockIdx.y * H * Wp, H, W, logCB, h, CF, found ? pk / W : 0,
-                                    found ? pk % W : 0, ch, dH, PbLds{pb_sm, pb_ld(dH.M)});
+    const int k0 = g * CF;
+    const double inside = pb_inside<BLUE>(Q + (int64_t)blockIdx.y * H * Wp, H, W, logCB, h, k0,
+                                          min(CF, 2 * h + 1 - k0), found ? pk / W : 0, found ? pk % W : 0, ch, dH,
+                                          PbLds{pb_sm, pb_ld(dH.M)});
     if (threadIdx.x == 0) {
-        const double pv = ch ? tot.v1 : tot.v0, rest = (ch ? tot.e1 : tot.e0) - inside;
-        const double num = pv * pv * (double)((int64_t)H * W - (int64_t)(2 * h + 1) * (2 * h + 1));
-        const int64_t i = ch ? p.z : p.x, j = ch ? p.w : p.y;
-        const int64_t pidx = i * n - i * (i + 1) / 2 + (j - i - 1);
-        const bool ok = found && live[i] && live[j] && rest > 0.0;
-        out[pidx] = ok ? (float)(num / rest) : __builtin_nanf("");
-        if (peak_out) peak_out[pidx] = ok ? (uint32_t)pk : 0u;
+        E[((int64_t)blockIdx.y * 2 + ch) * G + g] = inside;
+        if (g == 0) T[(int64_t)blockIdx.y * 2 + ch] = r;
     }
+}
+
+// PCE per pair: one thread per (pair-pair, channel) of the batch, the neighbourhood energy
+// summed over the G groups in order.
+__global__ void k_pb_pce(const PbStat *__restrict__ T, const double *__restrict__ E, int G, int nb,
+                         const int4 *__restrict__ pp, const int *__restrict__ live, int H, int W, int h, int64_t n,
+                         float *__restrict__ out, uint32_t *__restrict__ peak_out)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x, q = t >> 1, ch = t & 1;
+    if (q >= nb) return;
+    const int4 p = pp[q];
+    if (ch == 1 && p.z < 0) return;
+    const PbStat r = T[t];
+    double inside = 0.0;
+    for (int g = 0; g < G; ++g) inside += E[(int64_t)t * G + g];
+    const int pk = ch ? r.i1 : r.i0;
+    const double pv = ch ? r.v1 : r.v0, rest = (ch ? r.e1 : r.e0) - inside;
+    const double num = pv * pv * (double)((int64_t)H * W - (int64_t)(2 * h + 1) * (2 * h + 1));
+    const int64_t i = ch ? p.z : p.x, j = ch ? p.w : p.y;
+    const int64_t pidx = i * n - i * (i + 1) / 2 + (j - i - 1);
+    const bool ok = pk != 0x7fffffff && live[i] && live[j] && rest > 0.0;
+    out[pidx] = ok ? (float)(num / rest) : __builtin_nanf("");
+    if (peak_out) peak_out[pidx] = ok ? (uint32_t)pk : 0u;
 }
 
 int log2_exact(int64_t v)
@@ -704,8 +797,8 @@ rocket_status pce_big_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n
     for (const PbDim *d : {&dH, &dW}) {
         hipLaunchKernelGGL(k_pb_twiddles, dim3(8), dim3(256), 0, s, (float2 *)d->tw, d->logM);
         if (d->M != d->N)
-            hipLaunchKernelGGL(k_pb_chirp, dim3((unsigned)((d->M + 255) / 256)), dim3(256), 0, s, d->N, d->M,
-                               (float2 *)d->chirp, (float2 *)d->filt);
+            hipLaunchKernelGGL(k_pb_chirp, dim3((unsigned)d->M), dim3(64), 0, s, d->N, d->M, (float2 *)d->chirp,
+                               (float2 *)d->filt);
         RK_HIP(hipGetLastError());
     }
     if (n > 0) {
@@ -794,11 +887,16 @@ rocket_status pce_big_compare(rocket_ctx *ctx, float *out, uint32_t *peak, int h
     const int nblk = (W + CBS - 1) / CBS;  // column-pass workgroups (and statistics) per transform
     // row-pass workgroups: KP mirror row pairs, 2 KP vectors of MW values (1024 threads when a
     // row pair of the longest transforms needs 16K values)
+    // (8K-point rows: one row per workgroup)
     const bool wide = 2 * l.MW > PB_TILE;
-    const int KP = std::max(1, std::min(H / 2, (wide ? 2 : 1) * PB_TILE / (2 * l.MW)));
+    const int KP = wide ? 1 : std::max(1, std::min(H / 2, PB_TILE / (2 * l.MW)));
     const int lhw = log2_exact(W / 2);
-    // batch of pair-pairs: one staged H x Wp complex transform and nblk block statistics each
-    const int64_t per = (int64_t)H * Wp * (int64_t)sizeof(float2) + nblk * (int64_t)sizeof(PbStat);
+    // neighbourhood columns transformed again per workgroup, G groups of them
+    const int CF = std::min(2 * h + 1, PB_TILE / l.MH), G = (2 * h + CF) / CF;
+    // batch of pair-pairs: one staged H x Wp complex transform, nblk block statistics, and per
+    // channel the totals and G neighbourhood energies each
+    const int64_t per = (int64_t)H * Wp * (int64_t)sizeof(float2) + (nblk + 2) * (int64_t)sizeof(PbStat) +
+                        2 * G * (int64_t)sizeof(double);
     // default: as many transforms as 512 MiB holds (64 of 1024 x 1024), plus their statistics
     int64_t budget = (ctx->opt[ROCKET_OPT_PCE_BATCH] > 0 ? ctx->opt[ROCKET_OPT_PCE_BATCH]
                                                           : std::max<int64_t>(1, PB_STAGE_BYTES / ((int64_t)H * Wp * 8))) *
@@ -814,17 +912,18 @@ rocket_status pce_big_compare(rocket_ctx *ctx, float *out, uint32_t *peak, int h
     RK_TRY(ws_get(ctx, WS_PCE_STAGE, (size_t)(B * per), &stage));
     float2 *Q = (float2 *)stage;
     PbStat *S = (PbStat *)((char *)stage + B * (int64_t)H * Wp * sizeof(float2));
+    PbStat *T = S + B * nblk;
+    double *E = (double *)(T + 2 * B);
     const int4 *pp = (const int4 *)ctx->ws[WS_QUEUE_ITEMS].ptr;
-    const size_t rl = tile_lds(2 * KP, l.MW), cl = tile_lds(CBS, l.MH);
-    // Bluestein instantiations per axis; the wide row pass exists only for those (MW = 8192)
+    const size_t rl = tile_lds(wide ? 1 : 2 * KP, l.MW), cl = tile_lds(CBS, l.MH);
+    // Bluestein instantiations per axis; 8K-point rows occur only with Bluestein (W <= 4096)
     const bool bw = l.MW != W, bh = l.MH != H;
     const auto kr = bw ? &k_pb_rowpass<PB_NT, true> : &k_pb_rowpass<PB_NT, false>;
-    const auto kw = &k_pb_rowpass<2 * PB_NT, true>;
+    const auto kw = &k_pb_rowpass_one<true>;
     const auto kc = bh ? &k_pb_colpass<true> : &k_pb_colpass<false>;
-    const auto kf = bh ? &k_pb_final<true> : &k_pb_final<false>;
+    const auto kf = bh ? &k_pb_peak<true> : &k_pb_peak<false>;
     RK_TRY(set_lds(ctx, wide ? (const void *)kw : (const void *)kr, rl));
     RK_TRY(set_lds(ctx, (const void *)kc, cl));
-    const int CF = std::min(2 * h + 1, PB_TILE / l.MH);  // neighbourhood columns transformed at a time
     const size_t fl = tile_lds(CF, l.MH);
     RK_TRY(set_lds(ctx, (const void *)kf, fl));
     ctx->stats.grid = B;
@@ -833,13 +932,15 @@ rocket_status pce_big_compare(rocket_ctx *ctx, float *out, uint32_t *peak, int h
     for (int64_t q0 = 0; q0 < npp; q0 += B) {
         const unsigned nb = (unsigned)std::min<int64_t>(B, npp - q0);
         if (wide)
-            hipLaunchKernelGGL(kw, dim3(rgrid, nb), dim3(2 * PB_NT), rl, s, F, pp + q0, H, W, lhw, KP, logCB, dW, Q);
+            hipLaunchKernelGGL(kw, dim3(H, nb), dim3(PB_NT), rl, s, F, pp + q0, H, W, logCB, dW, Q);
         else
             hipLaunchKernelGGL(kr, dim3(rgrid, nb), dim3(PB_NT), rl, s, F, pp + q0, H, W, lhw, KP, logCB, dW, Q);
         hipLaunchKernelGGL(kc, dim3((unsigned)nblk, nb), dim3(PB_NT), cl, s, (const float2 *)Q, H, W, logCB, CBS,
                            dH, S);
-        hipLaunchKernelGGL(kf, dim3(2, nb), dim3(PB_NT), fl, s, (const float2 *)Q, (const PbStat *)S, nblk, pp + q0,
-                           live, H, W, logCB, h, CF, dH, n, out, peak);
+        hipLaunchKernelGGL(kf, dim3(2 * G, nb), dim3(PB_NT), fl, s, (const float2 *)Q, (const PbStat *)S, nblk,
+                           pp + q0, H, W, logCB, h, CF, dH, T, E);
+        hipLaunchKernelGGL(k_pb_pce, dim3((2 * nb + 255) / 256), dim3(256), 0, s, (const PbStat *)T, (const double *)E, G,
+                           (int)nb, pp + q0, live, H, W, h, n, out, peak);
         RK_HIP(hipGetLastError());
     }
     RK_TRY(timing_end(ctx, s));
