@@ -24,8 +24,9 @@
 //   pce          per pair-pair and channel: the neighbourhood energy summed, and the PCE.
 // The staged transform of a pair-pair is stored as ceil(W/CB) blocks of H x CB values, so
 // that the column-pass workgroups of a block read one contiguous piece.  Every FFT kernel
-// works on one tile of 8K complex values in LDS with 512 threads (1024 for a row pair of
-// 8K-point transforms): radix-16 Stockham passes in registers
+// works on one tile of 8K complex values in LDS with 512 threads (two workgroups per CU; the
+// column pass takes 4K values with 256 threads where a column fits, four per CU, and rows of
+// 8K-point transforms run one per workgroup): radix-16 Stockham passes in registers
 // (natural order in and out; pass twiddles computed in FP64 and rounded once), one padding
 // slot per 16 values against bank conflicts.  An axis of N values, N not a power of two, is
 // an M-point FFT, its product with the chirp filter's spectrum and an inverse M-point FFT in
@@ -446,8 +447,8 @@ __device__ __forceinline__ int pb_row(int q, int slot, int H) { return q == 0 ? 
 // W - c (0 < c < W/2) is conj(Z1) + i conj(Z2) taken at the mirror row, column c.  Rows are
 // transformed and written to Q, which holds each pair-pair's transform as ceil(W / CB)
 // blocks of H x CB values (CB = 2^logCB).  lhw = log2(W / 2), or -1 if W / 2 is not a power of two.
-template <int NT, bool BLUE>
-__global__ __launch_bounds__(NT) void k_pb_rowpass(const float2 *__restrict__ F, const int4 *__restrict__ pp, int H,
+template <bool BLUE>
+__global__ __launch_bounds__(PB_NT) void k_pb_rowpass(const float2 *__restrict__ F, const int4 *__restrict__ pp, int H,
                                                    int W, int lhw, int KP, int logCB, PbDim dW, float2 *__restrict__ Q)
 {
     extern __shared__ float2 pb_sm[];
@@ -458,7 +459,7 @@ __global__ __launch_bounds__(NT) void k_pb_rowpass(const float2 *__restrict__ F,
     const float2 *fa = F + p.x * NH, *fb = F + p.y * NH;
     const float2 *fc = F + (two ? p.z : p.x) * NH, *fd = F + (two ? p.w : p.y) * NH;
     const bool same_a = p.z == p.x;  // consecutive pairs of a tile row share their first item
-    // columns 0 .. W/2 - 1 of every row and their mirrors (at most NT * PB_EPT / 2 elements: all
+    // columns 0 .. W/2 - 1 of every row and their mirrors (at most PB_TILE / 2 elements: all
     // loads of a thread are issued before the first LDS store), then column W/2
     constexpr int G = PB_EPT / 2;
     const int nmain = 2 * nq * hw;
@@ -474,7 +475,7 @@ __global__ __launch_bounds__(NT) void k_pb_rowpass(const float2 *__restrict__ F,
     float2 va[G], vb[G], vc[G], vd[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        const int t = threadIdx.x + g * NT;
+        const int t = threadIdx.x + g * PB_NT;
         if (t < nmain) {
             int v, c;
             split(t, v, c);
@@ -487,7 +488,7 @@ __global__ __launch_bounds__(NT) void k_pb_rowpass(const float2 *__restrict__ F,
     }
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        const int t = threadIdx.x + g * NT;
+        const int t = threadIdx.x + g * PB_NT;
         if (t < nmain) {
             int v, c;
             split(t, v, c);
@@ -515,7 +516,7 @@ __global__ __launch_bounds__(NT) void k_pb_rowpass(const float2 *__restrict__ F,
     auto dst = [&](int v, int e, float2 val) {
         q[((int64_t)(e >> logCB) * H + pb_row(q0 + (v >> 1), v & 1, H)) * (cbm + 1) + (e & cbm)] = val;
     };
-    pb_dft<BLUE, false, false, NT>(dW, 2 * nq, lds, lds, dst);
+    pb_dft<BLUE, false, false, PB_NT>(dW, 2 * nq, lds, lds, dst);
 }
 
 // Row pass for rows of 8K-point transforms: grid (H, pair-pairs), one row per workgroup of
@@ -638,8 +639,8 @@ __device__ double pb_inside(const float2 *__restrict__ q, int H, int W, int logC
 // last) are transformed from the row-pass output (left as it is), and the workgroup's peak
 // (largest value, smallest shift index on ties) and FP64 energy per channel go to S.  CBS
 // divides the block width CB, or one workgroup covers all W columns.
-template <bool BLUE>
-__global__ __launch_bounds__(PB_NT) void k_pb_colpass(const float2 *__restrict__ Q, int H, int W, int logCB, int CBS,
+template <int NT, bool BLUE>
+__global__ __launch_bounds__(NT) void k_pb_colpass(const float2 *__restrict__ Q, int H, int W, int logCB, int CBS,
                                                       PbDim dH, PbStat *__restrict__ S)
 {
     extern __shared__ float2 pb_sm[];
@@ -654,8 +655,8 @@ __global__ __launch_bounds__(PB_NT) void k_pb_colpass(const float2 *__restrict__
         const int idx = e * W + c0 + v;
         pb_merge(st, val.x, val.y, idx, idx, (double)val.x * val.x, (double)val.y * val.y);
     };
-    pb_dft<BLUE, true, false, PB_NT>(dH, nc, PbLds{pb_sm, pb_ld(dH.M)}, src, dst);
-    st = pb_reduce<PB_NT>(st);
+    pb_dft<BLUE, true, false, NT>(dH, nc, PbLds{pb_sm, pb_ld(dH.M)}, src, dst);
+    st = pb_reduce<NT>(st);
     if (threadIdx.x == 0) S[(int64_t)by * gridDim.x + bx] = st;
 }
 
@@ -880,7 +881,9 @@ rocket_status pce_big_compare(rocket_ctx *ctx, float *out, uint32_t *peak, int h
     // column block by column block ([ceil(W / CB)][H][CB], CB a power of two >= CBS, at least 8
     // where W allows, so that the row pass stores runs of 64 bytes or more), so that the
     // workgroups of one block read one contiguous piece
-    const int CBS = std::min(W, PB_TILE / l.MH);
+    // (256-thread workgroups over 4K values where a column fits: four per CU)
+    const int CNT = l.MH <= PB_TILE / 2 ? PB_NT / 2 : PB_NT;
+    const int CBS = std::min(W, CNT * PB_EPT / l.MH);
     int CB = 1;
     while (CB < std::min(W, std::max(CBS, 8))) CB *= 2;
     const int logCB = log2_exact(CB), Wp = (W + CB - 1) / CB * CB;
@@ -918,9 +921,10 @@ rocket_status pce_big_compare(rocket_ctx *ctx, float *out, uint32_t *peak, int h
     const size_t rl = tile_lds(wide ? 1 : 2 * KP, l.MW), cl = tile_lds(CBS, l.MH);
     // Bluestein instantiations per axis; 8K-point rows occur only with Bluestein (W <= 4096)
     const bool bw = l.MW != W, bh = l.MH != H;
-    const auto kr = bw ? &k_pb_rowpass<PB_NT, true> : &k_pb_rowpass<PB_NT, false>;
+    const auto kr = bw ? &k_pb_rowpass<true> : &k_pb_rowpass<false>;
     const auto kw = &k_pb_rowpass_one<true>;
-    const auto kc = bh ? &k_pb_colpass<true> : &k_pb_colpass<false>;
+    const auto kc = CNT < PB_NT ? (bh ? &k_pb_colpass<PB_NT / 2, true> : &k_pb_colpass<PB_NT / 2, false>)
+                                : (bh ? &k_pb_colpass<PB_NT, true> : &k_pb_colpass<PB_NT, false>);
     const auto kf = bh ? &k_pb_peak<true> : &k_pb_peak<false>;
     RK_TRY(set_lds(ctx, wide ? (const void *)kw : (const void *)kr, rl));
     RK_TRY(set_lds(ctx, (const void *)kc, cl));
@@ -935,7 +939,7 @@ rocket_status pce_big_compare(rocket_ctx *ctx, float *out, uint32_t *peak, int h
             hipLaunchKernelGGL(kw, dim3(H, nb), dim3(PB_NT), rl, s, F, pp + q0, H, W, logCB, dW, Q);
         else
             hipLaunchKernelGGL(kr, dim3(rgrid, nb), dim3(PB_NT), rl, s, F, pp + q0, H, W, lhw, KP, logCB, dW, Q);
-        hipLaunchKernelGGL(kc, dim3((unsigned)nblk, nb), dim3(PB_NT), cl, s, (const float2 *)Q, H, W, logCB, CBS,
+        hipLaunchKernelGGL(kc, dim3((unsigned)nblk, nb), dim3(CNT), cl, s, (const float2 *)Q, H, W, logCB, CBS,
                            dH, S);
         hipLaunchKernelGGL(kf, dim3(2 * G, nb), dim3(PB_NT), fl, s, (const float2 *)Q, (const PbStat *)S, nblk,
                            pp + q0, H, W, logCB, h, CF, dH, T, E);
