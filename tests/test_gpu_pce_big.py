@@ -140,6 +140,25 @@ def test_camera_sensor_size(ctx):
     _check_shifts(gpk, c, sh, H, W)
 
 
+@pytest.mark.parametrize("H,W", [(32, 64), (48, 40)])
+def test_one_and_two_items(ctx, H, W):
+    # one item: no pairs (prepare runs, compare has nothing to do); two items: one pair-pair
+    # holding a single pair (no second channel)
+    import torch
+    announce("pce staged n=1 and n=2 %dx%d" % (H, W))
+    X, _, _ = synth.noise_images(2, (H, W), nsrc=1, amp=1.0, p_shift=1.0, config=6, salt=H * W)
+    ctx.set(pce_width=W)
+    try:
+        v1 = ctx.allpairs(torch.from_numpy(X[:1]).cuda(), "pce")
+        torch.cuda.synchronize()
+        assert v1.numel() == 0
+    finally:
+        ctx.set(pce_width=0)
+    got, gpk = _run(ctx, X, W)
+    assert got.shape == (1,)
+    _check(got, gpk, X, H, W, [(0, 1)])
+
+
 def test_shifted_copies_and_constant_item(ctx):
     announce("pce staged shifted copies 256x1024")
     H, W = 256, 1024
