@@ -320,7 +320,11 @@ typedef enum {
                                        64 always use 4) */
     ROCKET_OPT_PCE_WIDTH = 17,      /* ROCKET_PCE: image width W (items are dim / W rows of W values); 0: square */
     ROCKET_OPT_PCE_BATCH = 18,      /* ROCKET_PCE, staged path: pair-pairs per batch of staged transforms (0: as
-                                       many as fit in 512 MiB of staging; the cap and the arena bound it too) */
+                                       many as 512 MiB holds; the cap and the arena bound it too).  Two
+                                       staging buffers where the workspace holds two batches, the row pass of one
+                                       batch overlapping the column pass of the other on a second stream of the
+                                       context; one buffer and the caller's stream only in the allocation-free
+                                       entry point */
     ROCKET_OPT_TRACE = 19           /* 1: the persistent kernels time-stamp every work item (rocket_get_trace); set
                                        before rocket_prepare, like ROCKET_OPT_LEDGER */
 } rocket_option;

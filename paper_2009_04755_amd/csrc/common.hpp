@@ -119,6 +119,12 @@ struct PceState {
     bool big = false;  // H x W items through the staged multi-pass path
     int H = 0, W = 0;
     std::vector<int4> h_pp;  // pair-pairs (i, j, k, l) in tile order (staged path)
+    // staged path, two staging buffers: the row pass of batch k + 1 (caller's stream) runs
+    // while the column pass of batch k runs on `side`
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    hipEvent_t staged[2] = {nullptr, nullptr};    // row pass done: buffer k holds a batch
+    hipEvent_t consumed[2] = {nullptr, nullptr};  // column/peak/PCE kernels done with buffer k
 };
 
 // Composition-vector builder: whether the dense K-string count array is all zeros.

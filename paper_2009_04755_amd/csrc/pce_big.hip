@@ -22,6 +22,8 @@
 //                code, so to the same values) for their energy inside the (2h+1)^2 cells
 //                around the peak;
 //   pce          per pair-pair and channel: the neighbourhood energy summed, and the PCE.
+// With two staging buffers the row pass of batch b + 1 (caller's stream) runs beside the other
+// three kernels of batch b (a second stream of the context), ordered by events.
 // The staged transform of a pair-pair is stored as ceil(W/CB) blocks of H x CB values, so
 // that the column-pass workgroups of a block read one contiguous piece.  Every FFT kernel
 // works on one tile of 8K complex values in LDS with 512 threads (two workgroups per CU; the
@@ -900,23 +902,24 @@ rocket_status pce_big_compare(rocket_ctx *ctx, float *out, uint32_t *peak, int h
     // channel the totals and G neighbourhood energies each
     const int64_t per = (int64_t)H * Wp * (int64_t)sizeof(float2) + (nblk + 2) * (int64_t)sizeof(PbStat) +
                         2 * G * (int64_t)sizeof(double);
-    // default: as many transforms as 512 MiB holds (64 of 1024 x 1024), plus their statistics
-    int64_t budget = (ctx->opt[ROCKET_OPT_PCE_BATCH] > 0 ? ctx->opt[ROCKET_OPT_PCE_BATCH]
-                                                          : std::max<int64_t>(1, PB_STAGE_BYTES / ((int64_t)H * Wp * 8))) *
-                     per;
+    // Two staging buffers where the workspace allows two batches and the library may create a
+    // stream (not in the allocation-free arena): the row pass of batch b + 1 (caller's stream)
+    // then runs while the column, peak and PCE kernels of batch b run on a second stream.
+    // Batch: ROCKET_OPT_PCE_BATCH pair-pairs, else as many as 512 MiB holds (64 of 1024 x 1024,
+    // so 1 GiB of staging with two buffers).
+    int64_t room = INT64_MAX;  // transforms the workspace cap (or the arena) leaves room for
     const int64_t held = (int64_t)ctx->ws[WS_PCE_STAGE].bytes;
     if (ctx->arena)  // a slot that grows takes a new piece of the arena
-        budget = std::min<int64_t>(budget, std::max<int64_t>(held, (int64_t)(ctx->arena_cap - ctx->arena_used)) - 256);
+        room = (std::max<int64_t>(held, (int64_t)(ctx->arena_cap - ctx->arena_used)) - 256) / per;
     else if (ctx->opt[ROCKET_OPT_WORKSPACE_CAP] > 0)  // allocations are rounded up to 2 MiB
-        budget = std::min<int64_t>(budget, ctx->opt[ROCKET_OPT_WORKSPACE_CAP] - ws_total(ctx) + held - ((int64_t)2 << 20));
-    const int64_t B = std::min<int64_t>({npp, 65535, budget / per});
-    if (B < 1) return fail(ctx, ROCKET_E_OOM, "workspace cap leaves no room for one staged PCE transform");
+        room = (ctx->opt[ROCKET_OPT_WORKSPACE_CAP] - ws_total(ctx) + held - ((int64_t)2 << 20)) / per;
+    if (room < 1) return fail(ctx, ROCKET_E_OOM, "workspace cap leaves no room for one staged PCE transform");
+    const bool two = !ctx->arena && room >= 2 && npp >= 2;
+    const int64_t fill = std::max<int64_t>(1, PB_STAGE_BYTES / ((int64_t)H * Wp * 8));
+    const int64_t want = ctx->opt[ROCKET_OPT_PCE_BATCH] > 0 ? ctx->opt[ROCKET_OPT_PCE_BATCH] : fill;
+    const int64_t B = std::min<int64_t>({npp, 65535, want, two ? room / 2 : room});
     void *stage = nullptr;
-    RK_TRY(ws_get(ctx, WS_PCE_STAGE, (size_t)(B * per), &stage));
-    float2 *Q = (float2 *)stage;
-    PbStat *S = (PbStat *)((char *)stage + B * (int64_t)H * Wp * sizeof(float2));
-    PbStat *T = S + B * nblk;
-    double *E = (double *)(T + 2 * B);
+    RK_TRY(ws_get(ctx, WS_PCE_STAGE, (size_t)((two ? 2 : 1) * B * per), &stage));
     const int4 *pp = (const int4 *)ctx->ws[WS_QUEUE_ITEMS].ptr;
     const size_t rl = tile_lds(wide ? 1 : 2 * KP, l.MW), cl = tile_lds(CBS, l.MH);
     // Bluestein instantiations per axis; 8K-point rows occur only with Bluestein (W <= 4096)
@@ -930,22 +933,49 @@ rocket_status pce_big_compare(rocket_ctx *ctx, float *out, uint32_t *peak, int h
     RK_TRY(set_lds(ctx, (const void *)kc, cl));
     const size_t fl = tile_lds(CF, l.MH);
     RK_TRY(set_lds(ctx, (const void *)kf, fl));
+    if (two && !p.side) {
+        RK_HIP(hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking));
+        for (hipEvent_t *e : {&p.fork, &p.join, &p.staged[0], &p.staged[1], &p.consumed[0], &p.consumed[1]})
+            RK_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
+    }
+    const hipStream_t cs = two ? p.side : s;  // stream of the column, peak and PCE kernels
     ctx->stats.grid = B;
     RK_TRY(timing_begin(ctx, s));
+    if (two) {  // the second stream starts after everything queued on the caller's stream
+        RK_HIP(hipEventRecord(p.fork, s));
+        RK_HIP(hipStreamWaitEvent(cs, p.fork, 0));
+    }
     const unsigned rgrid = (unsigned)((H / 2 + KP - 1) / KP);
-    for (int64_t q0 = 0; q0 < npp; q0 += B) {
+    int64_t b = 0;
+    for (int64_t q0 = 0; q0 < npp; q0 += B, ++b) {
         const unsigned nb = (unsigned)std::min<int64_t>(B, npp - q0);
+        const int k = two ? (int)(b & 1) : 0;
+        char *buf = (char *)stage + k * B * per;  // buffer k: Q [B][H][Wp] | S [B][nblk] | T [B][2] | E [B][2][G]
+        float2 *Q = (float2 *)buf;
+        PbStat *S = (PbStat *)(buf + B * (int64_t)H * Wp * sizeof(float2));
+        PbStat *T = S + B * nblk;
+        double *E = (double *)(T + 2 * B);
+        if (two && b >= 2) RK_HIP(hipStreamWaitEvent(s, p.consumed[k], 0));  // batch b - 2 is done with buffer k
         if (wide)
             hipLaunchKernelGGL(kw, dim3(H, nb), dim3(PB_NT), rl, s, F, pp + q0, H, W, logCB, dW, Q);
         else
             hipLaunchKernelGGL(kr, dim3(rgrid, nb), dim3(PB_NT), rl, s, F, pp + q0, H, W, lhw, KP, logCB, dW, Q);
-        hipLaunchKernelGGL(kc, dim3((unsigned)nblk, nb), dim3(CNT), cl, s, (const float2 *)Q, H, W, logCB, CBS,
+        if (two) {
+            RK_HIP(hipEventRecord(p.staged[k], s));
+            RK_HIP(hipStreamWaitEvent(cs, p.staged[k], 0));
+        }
+        hipLaunchKernelGGL(kc, dim3((unsigned)nblk, nb), dim3(CNT), cl, cs, (const float2 *)Q, H, W, logCB, CBS,
                            dH, S);
-        hipLaunchKernelGGL(kf, dim3(2 * G, nb), dim3(PB_NT), fl, s, (const float2 *)Q, (const PbStat *)S, nblk,
+        hipLaunchKernelGGL(kf, dim3(2 * G, nb), dim3(PB_NT), fl, cs, (const float2 *)Q, (const PbStat *)S, nblk,
                            pp + q0, H, W, logCB, h, CF, dH, T, E);
-        hipLaunchKernelGGL(k_pb_pce, dim3((2 * nb + 255) / 256), dim3(256), 0, s, (const PbStat *)T, (const double *)E, G,
-                           (int)nb, pp + q0, live, H, W, h, n, out, peak);
+        hipLaunchKernelGGL(k_pb_pce, dim3((2 * nb + 255) / 256), dim3(256), 0, cs, (const PbStat *)T, (const double *)E,
+                           G, (int)nb, pp + q0, live, H, W, h, n, out, peak);
         RK_HIP(hipGetLastError());
+        if (two) RK_HIP(hipEventRecord(p.consumed[k], cs));
+    }
+    if (two) {  // the caller's stream continues after the second stream's last kernel
+        RK_HIP(hipEventRecord(p.join, cs));
+        RK_HIP(hipStreamWaitEvent(s, p.join, 0));
     }
     RK_TRY(timing_end(ctx, s));
     return ROCKET_OK;

@@ -235,6 +235,10 @@ void rocket_destroy(rocket_ctx *ctx)
         if (oc.copied[k]) (void)hipEventDestroy(oc.copied[k]);
         if (oc.freed[k]) (void)hipEventDestroy(oc.freed[k]);
     }
+    rk::PceState &pc = ctx->pce;
+    if (pc.side) (void)hipStreamDestroy(pc.side);
+    for (hipEvent_t e : {pc.fork, pc.join, pc.staged[0], pc.staged[1], pc.consumed[0], pc.consumed[1]})
+        if (e) (void)hipEventDestroy(e);
     (void)hipSetDevice(prev);
     delete ctx;
 }

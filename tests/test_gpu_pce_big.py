@@ -188,13 +188,14 @@ def test_batches_change_only_the_schedule(ctx):
         assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)) and np.array_equal(gpk, rpk)
     # a capped workspace bounds the batch the same way: room for k staged transforms of
     # 128 x 256 complex f32 and their block statistics (a few hundred bytes each, counted
-    # here as 4 KiB; allocations are rounded to 2 MiB) gives batches of k; room for less
-    # than one transform fails with E_OOM
+    # here as 4 KiB; allocations are rounded to 2 MiB) gives two staging buffers of k // 2
+    # transforms (the row pass of one batch overlapping the column pass of the other), room
+    # for one a single buffer, and room for less than one transform fails with E_OOM
     from paper_2009_04755_amd import Context
     from paper_2009_04755_amd._lib import RocketError, E_OOM
     Xd = torch.from_numpy(X).cuda()
     per = 128 * 256 * 8 + 4096
-    for k, ok in ((3, True), (1, True), (0, False)):
+    for k, ok in ((5, True), (1, True), (0, False)):
         c2 = Context(0).set(pce_width=256)
         c2.prepare(Xd, "pce")
         base = c2.stats()["workspace_bytes"]
@@ -202,7 +203,7 @@ def test_batches_change_only_the_schedule(ctx):
         if ok:
             got, gpk = c2.compare(counts=True)
             assert np.array_equal(got.cpu().numpy().view(np.uint32), ref.view(np.uint32))
-            assert c2.stats()["grid"] == k
+            assert c2.stats()["grid"] == (k // 2 if k >= 2 else k)
         else:
             with pytest.raises(RocketError) as e:
                 c2.compare()
