@@ -787,6 +787,11 @@ bool pce_big_shape(int64_t H, int64_t W)
 rocket_status pce_big_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, int H, int W, hipStream_t s)
 {
     PceState &p = ctx->pce;
+    if (!ctx->arena && !p.side) {  // the compare's second stream and its events, made here and not under a capture
+        for (hipEvent_t *e : {&p.fork, &p.join, &p.staged[0], &p.staged[1], &p.consumed[0], &p.consumed[1]})
+            if (!*e) RK_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
+        RK_HIP(hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking));  // last: a set stream means all events exist
+    }
     const int WH = W / 2 + 1;
     const PbLayout l = layout(n, H, W);
     ctx->trace_valid = false;  // batched launches, no persistent queue to trace
@@ -914,7 +919,7 @@ rocket_status pce_big_compare(rocket_ctx *ctx, float *out, uint32_t *peak, int h
     else if (ctx->opt[ROCKET_OPT_WORKSPACE_CAP] > 0)  // allocations are rounded up to 2 MiB
         room = (ctx->opt[ROCKET_OPT_WORKSPACE_CAP] - ws_total(ctx) + held - ((int64_t)2 << 20)) / per;
     if (room < 1) return fail(ctx, ROCKET_E_OOM, "workspace cap leaves no room for one staged PCE transform");
-    const bool two = !ctx->arena && room >= 2 && npp >= 2;
+    const bool two = !ctx->arena && p.side && room >= 2 && npp >= 2;
     const int64_t fill = std::max<int64_t>(1, PB_STAGE_BYTES / ((int64_t)H * Wp * 8));
     const int64_t want = ctx->opt[ROCKET_OPT_PCE_BATCH] > 0 ? ctx->opt[ROCKET_OPT_PCE_BATCH] : fill;
     const int64_t B = std::min<int64_t>({npp, 65535, want, two ? room / 2 : room});
@@ -933,11 +938,6 @@ rocket_status pce_big_compare(rocket_ctx *ctx, float *out, uint32_t *peak, int h
     RK_TRY(set_lds(ctx, (const void *)kc, cl));
     const size_t fl = tile_lds(CF, l.MH);
     RK_TRY(set_lds(ctx, (const void *)kf, fl));
-    if (two && !p.side) {
-        RK_HIP(hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking));
-        for (hipEvent_t *e : {&p.fork, &p.join, &p.staged[0], &p.staged[1], &p.consumed[0], &p.consumed[1]})
-            RK_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
-    }
     const hipStream_t cs = two ? p.side : s;  // stream of the column, peak and PCE kernels
     ctx->stats.grid = B;
     RK_TRY(timing_begin(ctx, s));
