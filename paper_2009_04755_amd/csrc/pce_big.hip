@@ -504,7 +504,7 @@ __global__ __launch_bounds__(PB_NT) void k_pb_rowpass(const float2 *__restrict__
             }
         }
     }
-    if (threadIdx.x < 2 * nq) {  // column W/2 is its own mirror
+    if ((int)threadIdx.x < 2 * nq) {  // column W/2 is its own mirror
         const int v = threadIdx.x;
         const int64_t e = (int64_t)pb_row(q0 + (v >> 1), v & 1, H) * WH + hw;
         const float2 z1 = pb_cjmul(fa[e], fb[e]);
@@ -919,10 +919,11 @@ rocket_status pce_big_compare(rocket_ctx *ctx, float *out, uint32_t *peak, int h
     else if (ctx->opt[ROCKET_OPT_WORKSPACE_CAP] > 0)  // allocations are rounded up to 2 MiB
         room = (ctx->opt[ROCKET_OPT_WORKSPACE_CAP] - ws_total(ctx) + held - ((int64_t)2 << 20)) / per;
     if (room < 1) return fail(ctx, ROCKET_E_OOM, "workspace cap leaves no room for one staged PCE transform");
-    const bool two = !ctx->arena && p.side && room >= 2 && npp >= 2;
     const int64_t fill = std::max<int64_t>(1, PB_STAGE_BYTES / ((int64_t)H * Wp * 8));
     const int64_t want = ctx->opt[ROCKET_OPT_PCE_BATCH] > 0 ? ctx->opt[ROCKET_OPT_PCE_BATCH] : fill;
-    const int64_t B = std::min<int64_t>({npp, 65535, want, two ? room / 2 : room});
+    const int64_t B1 = std::min<int64_t>({npp, 65535, want, room});  // batch with one buffer
+    const bool two = !ctx->arena && p.side && room >= 2 && npp > B1;  // more than one batch to overlap
+    const int64_t B = two ? std::min<int64_t>(B1, room / 2) : B1;
     void *stage = nullptr;
     RK_TRY(ws_get(ctx, WS_PCE_STAGE, (size_t)((two ? 2 : 1) * B * per), &stage));
     const int4 *pp = (const int4 *)ctx->ws[WS_QUEUE_ITEMS].ptr;
