@@ -518,7 +518,7 @@ def pce_big_pair_fn(ctx, with_cpu=True, n=256, H=1024, W=1024, nsrc=16, sample=1
            "roofline": {"bound": "hbm", "achieved": npp * per_pp / kern / 1e9, "peak": PEAK_HBM, "unit": "GB/s",
                         "frac": npp * per_pp / kern / 1e9 / PEAK_HBM, "bytes_per_pair_pair": per_pp,
                         "model": "4 half spectra read + staged H x W complex transform written and read once, "
-                                 "per two-pair transform (row pass, column pass and final kernels together)"},
+                                 "per two-pair transform (row pass, column pass, peak and PCE kernels together)"},
            "fft_flop_rate": {"achieved": npp * flops_pp / kern / 1e12, "unit": "TFLOP/s", "peak": PEAK_FP32_VALU,
                              "frac": npp * flops_pp / kern / 1e12 / PEAK_FP32_VALU, "flops_per_pair_pair": flops_pp,
                              "model": "5 M log2 M per M-point FFT; an axis that is not a power of two costs two "

@@ -80,10 +80,11 @@ def test_all_pairs_1024(ctx):
             assert gpk[idx] == ((sh[i, 0] - sh[j, 0]) % 1024) * 1024 + (sh[i, 1] - sh[j, 1]) % 1024
 
 
-@pytest.mark.parametrize("L", [16, 2048])
+@pytest.mark.parametrize("L", [16, 2048, 4096])
 def test_smallest_and_largest_square(ctx, L):
-    # the size limits of the staged path: 16 x 16 (one radix-16 pass per axis) and 2048 x 2048
-    n = 3 if L == 2048 else 12
+    # the size limits of the staged path: 16 x 16 (one radix-16 pass per axis) and 4096 x 4096
+    # (2^24 values per item), with 2048 x 2048 between
+    n = {16: 12, 2048: 3, 4096: 2}[L]
     announce("pce staged all pairs n=%d %dx%d" % (n, L, L))
     # one source, strong enough that the true shift beats the noise maxima at 256 shifts
     X, c, sh = synth.noise_images(n, L, nsrc=1, amp=2.0 if L == 16 else 0.5, p_shift=0.7, config=6, salt=L + 7)
@@ -118,8 +119,8 @@ def test_all_pairs_not_powers_of_two(ctx, H, W):
 
 @pytest.mark.parametrize("H,W", [(2050, 16), (16, 4094), (4096, 16)])
 def test_longest_axes(ctx, H, W):
-    # 8192-point transforms: Bluestein columns one per group in the column pass (2050), Bluestein
-    # rows through the 1024-thread row pass (4094), and the longest power-of-two side (4096)
+    # 8192-point transforms: Bluestein columns one per column-pass workgroup (2050), Bluestein rows
+    # one per row-pass workgroup (4094), and the longest power-of-two side (4096)
     n = 6
     announce("pce staged all pairs n=%d %dx%d" % (n, H, W))
     X, c, sh = synth.noise_images(n, (H, W), nsrc=2, amp=1.0, p_shift=0.7, config=6, salt=H + 9 * W)
