@@ -48,7 +48,9 @@
  * Every call is stream-ordered; calls return once the work is enqueued, except
  * where a comment says the call synchronises.  A context must not be used from
  * two host threads at once; calls on one context must not overlap on the device
- * with different streams.
+ * with different streams.  The staged PCE compare also runs kernels on a stream of
+ * its own (created by rocket_prepare), forked from and joined back to `stream` with
+ * events, so the call stays ordered on `stream` as a whole.
  *
  * ERRORS.  Every entry point returns a rocket_status.  Argument checks (null
  * pointers, negative sizes, ld < dim, unknown function) happen before anything is
