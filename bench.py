@@ -257,6 +257,10 @@ def ncc_small(ctx, with_cpu=True):
     rho, tau = oracle.ncc(X, pi, pj)
     dto = time.perf_counter() - t0
     res = {"workload": "NCC all pairs of 256 patterns x 4096 f32 values (8 sources, amp 0.05)", "pairs": P}
+    # the library's default shape for this size (64-item tiles, 256-element K chunks): the
+    # context may hold the shape the autotuner chose for the 4096 x 2^20 headline
+    keep = {k: ctx.get(k) for k in ("ncc_tile", "ncc_waves", "ncc_kchunk")}
+    ctx.set(**{k: 0 for k in keep})
     for fn, peak, ops in (("ncc_fp32", PEAK_FP32_MFMA, 1), ("ncc_bf16x6", PEAK_BF16, 6)):
         dt, kern = _time_fn(ctx, Xd, fn, out, 20, 3)
         st = ctx.stats()
@@ -266,6 +270,7 @@ def ncc_small(ctx, with_cpu=True):
                                 "frac": flop / kern / 1e12 / peak},
                    "tile": st["tile"], "kchunk": st["kchunk"], "work_items": st["work_items"],
                    "errors": _errors(out.cpu().numpy(), rho, floor=tau)}
+    ctx.set(**keep)
     if with_cpu:
         base = {"value": P / dto, "unit": "pairs/s", "cores": oracle.num_threads(), "kind": "oracle",
                 "sample": "all 32,640 pairs (FP64 stats + pair loop)"}
