@@ -383,7 +383,9 @@ rocket_status rocket_get_ledger(rocket_ctx *ctx, int32_t *out /* host */, int64_
 /* Autotuner of the tile shapes for the prepared set (the batching of uneven items into one
  * persistent launch, and the dense Gram tiles): every candidate is prepared and one whole
  * compare is timed with HIP events; the fastest is kept in the context's options (readable
- * with rocket_get_option) and the set is prepared with it.  Candidates:
+ * with rocket_get_option) and the set is prepared with it.  Those options stay in effect for
+ * later prepares on the context, whatever their size: set them back to 0 (the library's
+ * defaults for each size) or tune again before preparing a set of another size.  Candidates:
  *   NCC:     tile {256, 128} (n >= 1536) or {128, 64}, waves {8, 4}, K chunk {default,
  *            default/2} (never longer than the default: FP32 accumulation in the matrix
  *            cores loses accuracy with chunk length);
