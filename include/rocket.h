@@ -128,7 +128,7 @@ typedef enum {
      *   (smallest shift index r*W + c on ties),  PCE = C(s*)^2 (H W - |N|) / sum_{s outside N} C(s)^2,
      * N the (2h+1) x (2h+1) cyclic neighbourhood of s*, h = ROCKET_OPT_PCE_RADIUS (5 if 0),
      * h < min(H, W)/2.  Square items with L = 32, 64 or 128 run one f32 2-D FFT per pair
-     * inside LDS; otherwise H and W must be even and in [16, 4096] (else
+     * inside LDS; otherwise H and W must be in [16, 4096] (else
      * ROCKET_E_UNSUPPORTED) and the pair transforms are staged in HBM: two pairs per
      * complex 2-D FFT, a row pass, a column pass and a peak/energy pass over batches of
      * pair-pairs (ROCKET_OPT_PCE_BATCH).  A side that is not a power of two is transformed

@@ -446,7 +446,7 @@ rocket_status pce_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, hi
         if (!H || !pce_big_shape(H, W))
             return fail(ctx, ROCKET_E_UNSUPPORTED,
                         "PCE items must be L x L with L = 32, 64 or 128, or H x W (W = ROCKET_OPT_PCE_WIDTH, square "
-                        "if 0) with H and W even and in [16, 4096]");
+                        "if 0) with H and W in [16, 4096]");
         p.big = true;
         p.H = (int)H;
         p.W = (int)W;

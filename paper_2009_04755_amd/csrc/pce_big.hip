@@ -1,7 +1,6 @@
 // PCE over all cyclic shifts for images larger than one LDS tile (Section V-A's PCE variant
-// of the pattern comparison at the size of the forensics patterns): H x W items, H and W
-// even and in [16, 4096] (a side that is not a power of two by Bluestein's chirp
-// convolution).  The quantities are those of the in-LDS path:
+// of the pattern comparison at the size of the forensics patterns): H x W items, H and W in
+// [16, 4096] (a side that is not a power of two by Bluestein's chirp convolution).  The quantities are those of the in-LDS path:
 //   C(s) = sum_x a(x + s) b(x),  s* = argmax C,  PCE = C(s*)^2 (HW - |N|) / sum_{s not in N} C(s)^2.
 //
 // Prepare (per item): FP64 mean and norm, then the 2-D DFT of the centred unit-norm image as
@@ -440,38 +439,42 @@ __global__ __launch_bounds__(PB_NT) void k_pb_prep_cols(float2 *__restrict__ F, 
 }
 
 // Rows of the pair-pair spectrum P = conj(F_a) F_b + i conj(F_c) F_d come in mirror pairs:
-// row pair q = 0 holds rows 0 and H/2 (each its own mirror), q > 0 rows q and H - q.
+// row pair q = 0 holds rows 0 and H/2 (each its own mirror; for odd H row 0 alone, slot 1
+// empty), q > 0 rows q and H - q; (H + 1) / 2 row pairs in all.
 __device__ __forceinline__ int pb_row(int q, int slot, int H) { return q == 0 ? (slot ? H / 2 : 0) : (slot ? H - q : q); }
+__device__ __forceinline__ bool pb_empty(int q, int slot, int H) { return q == 0 && slot && (H & 1); }
 
-// Row pass: grid (ceil(H / (2 KP)), pair-pairs of the batch), KP mirror row pairs per workgroup
-// (the last may hold fewer).  pp[q] = (a, b, c, d): the pairs (a, b) and (c, d) (c < 0: no
-// second pair).  Column c <= W/2 of a row comes from the half spectra at that row; column
-// W - c (0 < c < W/2) is conj(Z1) + i conj(Z2) taken at the mirror row, column c.  Rows are
-// transformed and written to Q, which holds each pair-pair's transform as ceil(W / CB)
-// blocks of H x CB values (CB = 2^logCB).  lhw = log2(W / 2), or -1 if W / 2 is not a power of two.
+// Row pass: grid (ceil((H + 1) / 2 / KP), pair-pairs of the batch), KP mirror row pairs per
+// workgroup (the last may hold fewer).  pp[q] = (a, b, c, d): the pairs (a, b) and (c, d)
+// (c < 0: no second pair).  Column c <= W/2 of a row comes from the half spectra at that row;
+// column W - c (0 < c, W - c > W/2) is conj(Z1) + i conj(Z2) taken at the mirror row, column
+// c.  Rows are transformed and written to Q, which holds each pair-pair's transform as
+// ceil(W / CB) blocks of H x CB values (CB = 2^logCB).  lhc = log2 of hc = (W + 1) / 2, or -1
+// if hc is not a power of two.
 template <bool BLUE>
 __global__ __launch_bounds__(PB_NT) void k_pb_rowpass(const float2 *__restrict__ F, const int4 *__restrict__ pp, int H,
-                                                   int W, int lhw, int KP, int logCB, PbDim dW, float2 *__restrict__ Q)
+                                                   int W, int lhc, int KP, int logCB, PbDim dW, float2 *__restrict__ Q)
 {
     extern __shared__ float2 pb_sm[];
     const int4 p = pp[blockIdx.y];
-    const int q0 = blockIdx.x * KP, nq = min(KP, H / 2 - q0), lw = pb_ld(dW.M), WH = W / 2 + 1, hw = W / 2;
+    const int q0 = blockIdx.x * KP, nq = min(KP, (H + 1) / 2 - q0), lw = pb_ld(dW.M), WH = W / 2 + 1, hw = W / 2;
+    const int hc = (W + 1) / 2;  // columns 0 .. hc - 1 with their mirrors (odd W: all but none)
     const int64_t NH = (int64_t)H * WH;
     const bool two = p.z >= 0;
     const float2 *fa = F + p.x * NH, *fb = F + p.y * NH;
     const float2 *fc = F + (two ? p.z : p.x) * NH, *fd = F + (two ? p.w : p.y) * NH;
     const bool same_a = p.z == p.x;  // consecutive pairs of a tile row share their first item
-    // columns 0 .. W/2 - 1 of every row and their mirrors (at most PB_TILE / 2 elements: all
-    // loads of a thread are issued before the first LDS store), then column W/2
+    // columns 0 .. hc - 1 of every row and their mirrors (at most PB_TILE / 2 elements: all
+    // loads of a thread are issued before the first LDS store), then for even W column W/2
     constexpr int G = PB_EPT / 2;
-    const int nmain = 2 * nq * hw;
+    const int nmain = 2 * nq * hc;
     auto split = [&](int t, int &v, int &c) {
-        if (lhw >= 0) {
-            v = t >> lhw;
-            c = t & (hw - 1);
+        if (lhc >= 0) {
+            v = t >> lhc;
+            c = t & (hc - 1);
         } else {
-            v = t / hw;
-            c = t - v * hw;
+            v = t / hc;
+            c = t - v * hc;
         }
     };
     float2 va[G], vb[G], vc[G], vd[G];
@@ -504,7 +507,7 @@ __global__ __launch_bounds__(PB_NT) void k_pb_rowpass(const float2 *__restrict__
             }
         }
     }
-    if ((int)threadIdx.x < 2 * nq) {  // column W/2 is its own mirror
+    if (!(W & 1) && (int)threadIdx.x < 2 * nq) {  // even W: column W/2 is its own mirror
         const int v = threadIdx.x;
         const int64_t e = (int64_t)pb_row(q0 + (v >> 1), v & 1, H) * WH + hw;
         const float2 z1 = pb_cjmul(fa[e], fb[e]);
@@ -516,7 +519,8 @@ __global__ __launch_bounds__(PB_NT) void k_pb_rowpass(const float2 *__restrict__
     const PbLds lds{pb_sm, lw};
     const int cbm = (1 << logCB) - 1;
     auto dst = [&](int v, int e, float2 val) {
-        q[((int64_t)(e >> logCB) * H + pb_row(q0 + (v >> 1), v & 1, H)) * (cbm + 1) + (e & cbm)] = val;
+        if (!pb_empty(q0 + (v >> 1), v & 1, H))
+            q[((int64_t)(e >> logCB) * H + pb_row(q0 + (v >> 1), v & 1, H)) * (cbm + 1) + (e & cbm)] = val;
     };
     pb_dft<BLUE, false, false, PB_NT>(dW, 2 * nq, lds, lds, dst);
 }
@@ -525,7 +529,8 @@ __global__ __launch_bounds__(PB_NT) void k_pb_rowpass(const float2 *__restrict__
 // PB_NT threads and one LDS vector (two workgroups per CU).  Row r takes columns 0 .. W/2 from
 // the half spectra at row r and columns W - c from its mirror row (as in k_pb_rowpass); the
 // two workgroups of a mirror pair are neighbours in the XCD-aware order, so the second
-// reads the shared spectra rows from the same L2.
+// reads the shared spectra rows from the same L2.  Workgroup b takes slot b of the row pairs
+// in order (for odd H, row pair 0 holds row 0 only, and b > 0 counts from slot 2).
 template <bool BLUE>
 __global__ __launch_bounds__(PB_NT) void k_pb_rowpass_one(const float2 *__restrict__ F, const int4 *__restrict__ pp,
                                                           int H, int W, int logCB, PbDim dW, float2 *__restrict__ Q)
@@ -534,18 +539,19 @@ __global__ __launch_bounds__(PB_NT) void k_pb_rowpass_one(const float2 *__restri
     int bx, by;
     pb_xcd_order(true, bx, by);
     const int4 p = pp[by];
-    const int q0 = bx >> 1, slot = bx & 1, WH = W / 2 + 1, hw = W / 2;
+    const int b2 = (H & 1) && bx > 0 ? bx + 1 : bx;
+    const int q0 = b2 >> 1, slot = b2 & 1, WH = W / 2 + 1, hw = W / 2, hc = (W + 1) / 2;
     const int r = pb_row(q0, slot, H), rm = pb_row(q0, q0 ? slot ^ 1 : slot, H);  // rows 0, H/2: own mirrors
     const int64_t NH = (int64_t)H * WH;
     const bool two = p.z >= 0;
     const float2 *fa = F + p.x * NH, *fb = F + p.y * NH;
     const float2 *fc = F + (two ? p.z : p.x) * NH, *fd = F + (two ? p.w : p.y) * NH;
     // column c of row r is z1 + i z2 at (r, c); column W - c is conj(z1) + i conj(z2) at (rm, c)
-    constexpr int G = 4096 / 2 / PB_NT;  // columns 0 .. W/2 - 1 per thread (W <= 4096)
+    constexpr int G = 4096 / 2 / PB_NT;  // columns 0 .. hc - 1 per thread (W <= 4096)
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         const int c = threadIdx.x + g * PB_NT;
-        if (c < hw) {
+        if (c < hc) {
             const int64_t e = (int64_t)r * WH + c, em = (int64_t)rm * WH + c;
             const float2 u1 = pb_cjmul(fa[e], fb[e]), m1 = pb_cjmul(fa[em], fb[em]);
             const float2 u2 = two ? pb_cjmul(fc[e], fd[e]) : make_float2(0.f, 0.f);
@@ -554,7 +560,7 @@ __global__ __launch_bounds__(PB_NT) void k_pb_rowpass_one(const float2 *__restri
             if (c > 0) pb_sm[pb_pad(W - c)] = make_float2(m1.x + m2.y, m2.x - m1.y);
         }
     }
-    if (threadIdx.x == 0) {  // column W/2 is its own mirror
+    if (!(W & 1) && threadIdx.x == 0) {  // even W: column W/2 is its own mirror
         const int64_t e = (int64_t)r * WH + hw;
         const float2 z1 = pb_cjmul(fa[e], fb[e]);
         const float2 z2 = two ? pb_cjmul(fc[e], fd[e]) : make_float2(0.f, 0.f);
@@ -780,8 +786,8 @@ rocket_status set_lds(rocket_ctx *ctx, const void *k, size_t bytes)
 
 bool pce_big_shape(int64_t H, int64_t W)
 {
-    // even sides in [16, 4096] (FFT lengths up to 8192: one LDS tile), at most 2^24 values
-    return H >= 16 && W >= 16 && H <= 4096 && W <= 4096 && H % 2 == 0 && W % 2 == 0 && H * W <= ((int64_t)1 << 24);
+    // sides in [16, 4096] (FFT lengths up to 8192: one LDS tile)
+    return H >= 16 && W >= 16 && H <= 4096 && W <= 4096;
 }
 
 rocket_status pce_big_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, int H, int W, hipStream_t s)
@@ -899,8 +905,9 @@ rocket_status pce_big_compare(rocket_ctx *ctx, float *out, uint32_t *peak, int h
     // row pair of the longest transforms needs 16K values)
     // (8K-point rows: one row per workgroup)
     const bool wide = 2 * l.MW > PB_TILE;
-    const int KP = wide ? 1 : std::max(1, std::min(H / 2, PB_TILE / (2 * l.MW)));
-    const int lhw = log2_exact(W / 2);
+    const int NQ = (H + 1) / 2;  // row pairs (odd H: the first holds row 0 alone)
+    const int KP = wide ? 1 : std::max(1, std::min(NQ, PB_TILE / (2 * l.MW)));
+    const int lhc = log2_exact((W + 1) / 2);
     // neighbourhood columns transformed again per workgroup, G groups of them
     const int CF = std::min(2 * h + 1, PB_TILE / l.MH), G = (2 * h + CF) / CF;
     // batch of pair-pairs: one staged H x Wp complex transform, nblk block statistics, and per
@@ -946,7 +953,7 @@ rocket_status pce_big_compare(rocket_ctx *ctx, float *out, uint32_t *peak, int h
         RK_HIP(hipEventRecord(p.fork, s));
         RK_HIP(hipStreamWaitEvent(cs, p.fork, 0));
     }
-    const unsigned rgrid = (unsigned)((H / 2 + KP - 1) / KP);
+    const unsigned rgrid = (unsigned)((NQ + KP - 1) / KP);
     int64_t b = 0;
     for (int64_t q0 = 0; q0 < npp; q0 += B, ++b) {
         const unsigned nb = (unsigned)std::min<int64_t>(B, npp - q0);
@@ -960,7 +967,7 @@ rocket_status pce_big_compare(rocket_ctx *ctx, float *out, uint32_t *peak, int h
         if (wide)
             hipLaunchKernelGGL(kw, dim3(H, nb), dim3(PB_NT), rl, s, F, pp + q0, H, W, logCB, dW, Q);
         else
-            hipLaunchKernelGGL(kr, dim3(rgrid, nb), dim3(PB_NT), rl, s, F, pp + q0, H, W, lhw, KP, logCB, dW, Q);
+            hipLaunchKernelGGL(kr, dim3(rgrid, nb), dim3(PB_NT), rl, s, F, pp + q0, H, W, lhc, KP, logCB, dW, Q);
         if (two) {
             RK_HIP(hipEventRecord(p.staged[k], s));
             RK_HIP(hipStreamWaitEvent(cs, p.staged[k], 0));

@@ -1,6 +1,7 @@
 """GPU PCE of images larger than one LDS tile (forensics PCE variant, Section V-A) against
-the FP64 oracle: H x W items with H and W even (a side that is not a power of two by
-Bluestein's chirp convolution), pair transforms staged in HBM.
+the FP64 oracle: H x W items with sides in [16, 4096] (a side that is not a power of two by
+Bluestein's chirp convolution; odd sides pair their rows and columns without a middle one),
+pair transforms staged in HBM.
 
 Pass metric as for the in-LDS sizes: |g - r| <= 1e-5 * r, with r the oracle's PCE at the
 GPU's peak shift; that peak must be the oracle's argmax, or (where the two largest
@@ -117,11 +118,24 @@ def test_all_pairs_not_powers_of_two(ctx, H, W):
     _check_shifts(gpk, c, sh, H, W)
 
 
-@pytest.mark.parametrize("H,W", [(2050, 16), (16, 4094), (4096, 16)])
+@pytest.mark.parametrize("H,W", [(17, 33), (45, 64), (64, 45), (31, 31), (99, 101)])
+def test_all_pairs_odd_sides(ctx, H, W):
+    # odd sides: row 0 (and no row H/2) pairs with itself, column W/2 does not exist
+    n = 9
+    announce("pce staged odd sides all pairs n=%d %dx%d" % (n, H, W))
+    X, c, sh = synth.noise_images(n, (H, W), nsrc=2, amp=1.0, p_shift=0.7, config=6, salt=7 * H + W)
+    got, gpk = _run(ctx, X, W)
+    pairs = [(i, j) for i in range(n) for j in range(i + 1, n)]
+    announce("max rel err %.2e" % _check(got, gpk, X, H, W, pairs, h=min(5, min(H, W) // 2 - 1)))
+    _check_shifts(gpk, c, sh, H, W)
+
+
+@pytest.mark.parametrize("H,W", [(2050, 16), (16, 4094), (4096, 16), (4095, 16), (16, 4095), (3001, 2001)])
 def test_longest_axes(ctx, H, W):
-    # 8192-point transforms: Bluestein columns one per column-pass workgroup (2050), Bluestein rows
-    # one per row-pass workgroup (4094), and the longest power-of-two side (4096)
-    n = 6
+    # 8192-point transforms: Bluestein columns one per column-pass workgroup (2050, 4095), Bluestein
+    # rows one per row-pass workgroup (4094, 4095), the longest power-of-two side (4096), and an odd
+    # camera-like size
+    n = 3 if H * W > 10 ** 6 else 6
     announce("pce staged all pairs n=%d %dx%d" % (n, H, W))
     X, c, sh = synth.noise_images(n, (H, W), nsrc=2, amp=1.0, p_shift=0.7, config=6, salt=H + 9 * W)
     got, gpk = _run(ctx, X, W)
@@ -225,9 +239,8 @@ def test_errors(ctx):
     import torch
     from paper_2009_04755_amd._lib import RocketError, E_INVALID, E_UNSUPPORTED
     announce("pce staged errors")
-    bad = [(45 * 45, 0), (64 * 99, 99), (99 * 64, 64), (1000, 64), (4098 * 16, 16),
-           (16 * 4098, 4098), (8 * 64, 64)]
-    for dim, w in bad:  # odd sides, width not dividing, a side above 4096 or below 16
+    bad = [(1000, 64), (4097 * 16, 16), (16 * 4097, 4097), (8 * 64, 64), (64 * 15, 15), (15 * 15, 0)]
+    for dim, w in bad:  # width not dividing, a side above 4096 or below 16
         ctx.set(pce_width=w)
         try:
             with pytest.raises(RocketError) as e:

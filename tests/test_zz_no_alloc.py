@@ -116,9 +116,9 @@ def test_gmm_and_pce_two_calls():
         ref, _ = _call_ex("gmm_l2", cl)
         assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
     # 256 x 256 takes the staged path: at n = 40 its transforms run in batches bounded by
-    # what is left of the scratch array (the reference runs them in one batch); 96 x 96 and
-    # 48 x 48 take it with Bluestein transforms
-    for n, L in ((40, 64), (12, 32), (40, 256), (12, 256), (20, 96), (8, 48)):
+    # what is left of the scratch array (the reference runs them in one batch); 96 x 96, 48 x 48
+    # and 45 x 45 (odd sides) take it with Bluestein transforms
+    for n, L in ((40, 64), (12, 32), (40, 256), (12, 256), (20, 96), (8, 48), (6, 45)):
         announce("noalloc pce n=%d L=%d" % (n, L))
         X, _, _ = synth.noise_images(n, L, nsrc=4, amp=0.4, salt=n)
         Xd = torch.from_numpy(X).cuda()
