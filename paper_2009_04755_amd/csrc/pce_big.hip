@@ -255,22 +255,22 @@ __device__ void pb_dft(const PbDim &d, int nv, const PbLds &lds, const Src &src,
 {
     if constexpr (!BLUE) {
         pb_fft<VF1, VF, NT>(d.logM, nv, d.tw, lds, src, dst);
-        return;
+    } else {
+        const float2 *w = d.chirp, *B = d.filt;
+        const int N = d.N;
+        auto src1 = [&](int v, int e) { return e < N ? pb_mul(src(v, e), w[e]) : make_float2(0.f, 0.f); };
+        auto dst1 = [&](int v, int e, float2 val) {
+            const float2 z = pb_mul(val, B[e]);
+            lds(v, e, make_float2(z.x, -z.y));
+        };
+        pb_fft<VF1, VF, NT>(d.logM, nv, d.tw, lds, src1, dst1);
+        pb_barrier();
+        const float inv = 1.f / (float)d.M;
+        auto dst2 = [&](int v, int e, float2 val) {
+            if (e < N) dst(v, e, pb_mul(make_float2(val.x * inv, -val.y * inv), w[e]));
+        };
+        pb_fft<VF, VF, NT>(d.logM, nv, d.tw, lds, lds, dst2);
     }
-    const float2 *w = d.chirp, *B = d.filt;
-    const int N = d.N;
-    auto src1 = [&](int v, int e) { return e < N ? pb_mul(src(v, e), w[e]) : make_float2(0.f, 0.f); };
-    auto dst1 = [&](int v, int e, float2 val) {
-        const float2 z = pb_mul(val, B[e]);
-        lds(v, e, make_float2(z.x, -z.y));
-    };
-    pb_fft<VF1, VF, NT>(d.logM, nv, d.tw, lds, src1, dst1);
-    pb_barrier();
-    const float inv = 1.f / (float)d.M;
-    auto dst2 = [&](int v, int e, float2 val) {
-        if (e < N) dst(v, e, pb_mul(make_float2(val.x * inv, -val.y * inv), w[e]));
-    };
-    pb_fft<VF, VF, NT>(d.logM, nv, d.tw, lds, lds, dst2);
 }
 
 // The passes' twiddles W_(R Ns)^(r k) for an N-point transform, FP64 rounded once.
@@ -890,20 +890,19 @@ rocket_status pce_big_compare(rocket_ctx *ctx, float *out, uint32_t *peak, int h
     const int *live = (const int *)((const char *)F + l.spec + l.stats);
     PbDim dH, dW;
     axes(l, H, W, (float2 *)((const char *)live + l.live), dH, dW);
-    // column-pass workgroups: CBS columns each (one LDS tile).  The staged transform is stored
-    // column block by column block ([ceil(W / CB)][H][CB], CB a power of two >= CBS, at least 8
-    // where W allows, so that the row pass stores runs of 64 bytes or more), so that the
-    // workgroups of one block read one contiguous piece
-    // (256-thread workgroups over 4K values where a column fits: four per CU)
+    // column-pass workgroups: CBS columns each (one LDS tile; 256 threads over 4K values where
+    // a column fits, four workgroups per CU).  The staged transform is stored column block by
+    // column block ([ceil(W / CB)][H][CB], CB a power of two >= CBS, at least 8 where W allows,
+    // so that the row pass stores runs of 64 bytes or more), so that the workgroups of one
+    // block read one contiguous piece
     const int CNT = l.MH <= PB_TILE / 2 ? PB_NT / 2 : PB_NT;
     const int CBS = std::min(W, CNT * PB_EPT / l.MH);
     int CB = 1;
     while (CB < std::min(W, std::max(CBS, 8))) CB *= 2;
     const int logCB = log2_exact(CB), Wp = (W + CB - 1) / CB * CB;
     const int nblk = (W + CBS - 1) / CBS;  // column-pass workgroups (and statistics) per transform
-    // row-pass workgroups: KP mirror row pairs, 2 KP vectors of MW values (1024 threads when a
-    // row pair of the longest transforms needs 16K values)
-    // (8K-point rows: one row per workgroup)
+    // row-pass workgroups: KP mirror row pairs, 2 KP vectors of MW values; rows of 8K-point
+    // transforms one per workgroup (k_pb_rowpass_one)
     const bool wide = 2 * l.MW > PB_TILE;
     const int NQ = (H + 1) / 2;  // row pairs (odd H: the first holds row 0 alone)
     const int KP = wide ? 1 : std::max(1, std::min(NQ, PB_TILE / (2 * l.MW)));
