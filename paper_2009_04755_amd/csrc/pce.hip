@@ -500,7 +500,7 @@ rocket_status pce_compare(rocket_ctx *ctx, float *out, uint32_t *peak, hipStream
     PceState &p = ctx->pce;
     if (!p.valid) return fail(ctx, ROCKET_E_STATE, "PCE set not prepared");
     const int h = ctx->opt[ROCKET_OPT_PCE_RADIUS] ? (int)ctx->opt[ROCKET_OPT_PCE_RADIUS] : 5;
-    if (h >= (p.big ? std::min(p.H, p.W) : p.L) / 2)
+    if (2 * h + 1 > (p.big ? std::min(p.H, p.W) : p.L))  // h < min(H, W) / 2: the neighbourhood does not wrap
         return fail(ctx, ROCKET_E_INVALID, "PCE neighbourhood radius must be < min(H, W)/2");
     if (p.n < 2 || p.tiles == 0) return ROCKET_OK;
     if (p.big) return pce_big_compare(ctx, out, peak, h, s);

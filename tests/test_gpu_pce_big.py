@@ -226,13 +226,16 @@ def test_batches_change_only_the_schedule(ctx):
         c2.close()
 
 
-def test_radius_option(ctx):
-    announce("pce staged radius 64x128")
-    X, _, _ = synth.noise_images(6, (64, 128), nsrc=2, amp=0.4, config=6, salt=8)
+@pytest.mark.parametrize("H,W", [(64, 128), (45, 64)])
+def test_radius_option(ctx, H, W):
+    # the smallest radius and the largest allowed one (h < min(H, W) / 2), also with an odd
+    # side taken by Bluestein
+    announce("pce staged radius %dx%d" % (H, W))
+    X, _, _ = synth.noise_images(6, (H, W), nsrc=2, amp=0.4, config=6, salt=8 + H)
     pairs = [(i, j) for i in range(6) for j in range(i + 1, 6)]
-    for h in (1, 31):
-        got, gpk = _run(ctx, X, 128, pce_radius=h)
-        _check(got, gpk, X, 64, 128, pairs, h=h)
+    for h in (1, (min(H, W) - 1) // 2):
+        got, gpk = _run(ctx, X, W, pce_radius=h)
+        _check(got, gpk, X, H, W, pairs, h=h)
 
 
 def test_errors(ctx):
@@ -248,13 +251,14 @@ def test_errors(ctx):
             assert e.value.status == E_UNSUPPORTED, (dim, w)
         finally:
             ctx.set(pce_width=0)
-    ctx.set(pce_width=64, pce_radius=8)  # 16 x 64: h must be below 8
-    try:
-        with pytest.raises(RocketError) as e:
-            ctx.allpairs(torch.zeros((3, 1024), device="cuda"), "pce")
-        assert e.value.status == E_INVALID
-    finally:
-        ctx.set(pce_width=0, pce_radius=0)
+    for dim, w, h in ((16 * 64, 64, 8), (45 * 64, 64, 23)):  # h < min(H, W) / 2: below 8, at most 22
+        ctx.set(pce_width=w, pce_radius=h)
+        try:
+            with pytest.raises(RocketError) as e:
+                ctx.allpairs(torch.zeros((3, dim), device="cuda"), "pce")
+            assert e.value.status == E_INVALID
+        finally:
+            ctx.set(pce_width=0, pce_radius=0)
 
 
 def test_workload_sampled(ctx):
