@@ -941,7 +941,8 @@ def main():
         rec["cv_build"] = cv_pipeline(ctx, not args.no_cpu_baseline)
         rec["pair_fns"]["pce"] = pce_pair_fn(ctx, not args.no_cpu_baseline)
         rec["pair_fns"]["pce_1024"] = pce_big_pair_fn(ctx, not args.no_cpu_baseline)
-        # a camera sensor's pixel grid: both sides by Bluestein (8192-point FFTs)
+        # the image size of the forensics data set (Section V-A): both sides by Bluestein
+        # (8192-point FFTs)
         rec["pair_fns"]["pce_3648x2736"] = pce_big_pair_fn(ctx, not args.no_cpu_baseline, n=32, H=3648, W=2736,
                                                            nsrc=4, sample=16)
     print(json.dumps(rec))

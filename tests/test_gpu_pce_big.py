@@ -145,7 +145,8 @@ def test_longest_axes(ctx, H, W):
 
 
 def test_camera_sensor_size(ctx):
-    # 3648 x 2736, a camera sensor's pixel grid: both axes by Bluestein with 8192-point FFTs
+    # 3648 x 2736, the image size of the forensics data set (Section V-A): both axes by
+    # Bluestein with 8192-point FFTs
     H, W, n = 3648, 2736, 3
     announce("pce staged bluestein n=%d %dx%d" % (n, H, W))
     X, c, sh = synth.noise_images(n, (H, W), nsrc=1, amp=0.3, p_shift=1.0, config=6, salt=3648)
