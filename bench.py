@@ -13,10 +13,12 @@ Prints ONE JSON line.  ``value`` is pairs/s; ``roofline`` is the Gram kernel's a
 committed counter file when its kernel-source hash matches); ``cpu_baseline`` times the
 FP64 oracle on a bounded sample of the same workload on this host.  Extra fields report the
 plain FP32 and two-term split paths at the same shape, the same workload through the
-out-of-core device cache, the Gaussian-overlap, GMM and registration-gradient costs over
+out-of-core device cache, the NCC of 256 x 4096 and of 1024 patterns of 3648 x 2736 values
+(the forensics images' size), the Gaussian-overlap, GMM and registration-gradient costs over
 2048 point clouds (also with a full covariance per point, and the registration on each GMM
 score), the sparse cosine of 8192 k-mer vectors, the PCE of 1024 images of 128 x 128 (one
-LDS tile per pair) and of 256 images of 1024 x 1024 (transforms staged in HBM), and the
+LDS tile per pair), of 256 images of 1024 x 1024 and of 32 of 3648 x 2736 (transforms staged
+in HBM), and the
 composition-vector construction of 128 proteomes, each with its own roofline and, where
 cheap enough, the oracle on a sample.  ``--only`` runs one of those workloads alone (for
 profiling).
@@ -276,6 +278,57 @@ def ncc_small(ctx, with_cpu=True):
                 "sample": "all 32,640 pairs (FP64 stats + pair loop)"}
         base.update(_host_info())
         res["cpu_baseline"] = base
+    return res
+
+
+def forensics_ncc(ctx, with_cpu=True):
+    """NCC (BF16x6) of all pairs of 1024 synthetic patterns at the size of the forensics data
+    set's images, 3648 x 2736 = 9,980,928 values each (Section V-A), with the library's
+    default shape for this size."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_2009_04755_amd import synth
+
+    n, d = 1024, 3648 * 2736
+    X, _ = synth.dense_patterns_device(n, d, 64, 0.02, seed=3, device="cuda")
+    P = n * (n - 1) // 2
+    out = torch.empty(P, device="cuda")
+    keep = {k: ctx.get(k) for k in ("ncc_tile", "ncc_waves", "ncc_kchunk")}
+    ctx.set(**{k: 0 for k in keep})
+    dt, kern = _time_fn(ctx, X, "ncc_bf16x6", out, 3, 1)
+    st = ctx.stats()
+    ctx.set(**keep)
+    flop = 2.0 * d * P
+    res = {"workload": "NCC all pairs of 1024 patterns x 3648 x 2736 f32 values (64 sources, amp 0.02), BF16x6",
+           "pairs_per_s": 3 * P / dt, "ms_per_step": dt / 3 * 1e3, "kernel_ms": kern * 1e3,
+           "us_per_pair": dt / 3 / P * 1e6, "tile": st["tile"], "kchunk": st["kchunk"],
+           "work_items": st["work_items"],
+           "roofline": {"bound": "mfma", "achieved": flop / kern / 1e12, "peak": PEAK_BF16, "unit": "TFLOP/s",
+                        "frac": flop / kern / 1e12 / PEAK_BF16},
+           "paper_context": "1.1 ms per pair for the same comparison on a TitanX (Maxwell) GPU (another machine)"}
+    if with_cpu:
+        # 32 random pairs against the oracle (FP64), timed on the host cores
+        g = np.random.default_rng(11)
+        pi = g.integers(0, n, 48)
+        pj = g.integers(0, n, 48)
+        keepp = pi != pj
+        pi, pj = np.minimum(pi, pj)[keepp][:32], np.maximum(pi, pj)[keepp][:32]
+        rows = np.unique(np.concatenate([pi, pj]))
+        Xs = X[torch.from_numpy(rows).cuda()].cpu().numpy()
+        loc = {r: k for k, r in enumerate(rows.tolist())}
+        li = np.array([loc[a] for a in pi.tolist()])
+        lj = np.array([loc[b] for b in pj.tolist()])
+        t0 = time.perf_counter()
+        rho, tau = oracle.ncc(Xs, li, lj)
+        dto = time.perf_counter() - t0
+        idx = pi * n - pi * (pi + 1) // 2 + (pj - pi - 1)
+        res["errors"] = _errors(out.cpu().numpy()[idx], rho, floor=tau)
+        res["cpu_baseline"] = dict({"value": len(li) / dto, "unit": "pairs/s", "cores": oracle.num_threads(),
+                                    "kind": "oracle", "sample": "%d random pairs (FP64 stats + dot)" % len(li)},
+                                   **_host_info())
+    del X, out
+    torch.cuda.empty_cache()
     return res
 
 
@@ -826,10 +879,11 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM counter scaling)")
     ap.add_argument("--only", choices=["clouds", "sparse", "cv", "pce", "pce_big", "pce_camera", "ooc", "small",
-                                             "valu"],
+                                             "valu", "forensics"],
                     help="run only this secondary workload (for profiling it) and print its record; "
                          "clouds = overlap, GMM L2 / Bhattacharya and the registration gradient; "
-                         "small = the 256 x 4096 NCC workload")
+                         "small = the 256 x 4096 NCC workload; forensics = NCC of 1024 patterns of "
+                         "3648 x 2736 values")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: there is no multi-GPU path (requested %d)" % args.gpus,
@@ -861,7 +915,7 @@ def main():
                "cv": lambda: cv_pipeline(ctx, cpu), "pce": lambda: pce_pair_fn(ctx, cpu),
                "pce_big": lambda: pce_big_pair_fn(ctx, cpu), "valu": valu_probe,
                "pce_camera": lambda: pce_big_pair_fn(ctx, cpu, n=32, H=3648, W=2736, nsrc=4, sample=16),
-               "small": lambda: ncc_small(ctx, cpu)}[args.only]
+               "small": lambda: ncc_small(ctx, cpu), "forensics": lambda: forensics_ncc(ctx, cpu)}[args.only]
         print(json.dumps({"only": args.only, "record": run()}))
         sys.stdout.flush()
         return
@@ -935,6 +989,7 @@ def main():
         rec["ncc_out_of_core"] = out_of_core(ctx, X, out)
         del X
         torch.cuda.empty_cache()
+        rec["ncc_forensics_size"] = forensics_ncc(ctx, not args.no_cpu_baseline)
         rec["valu_probe"] = valu_probe()
         rec["pair_fns"] = other_pair_fns(ctx, not args.no_cpu_baseline, not args.no_autotune)
         rec["pair_fns"]["sparse_cosine"] = sparse_pair_fn(ctx, not args.no_cpu_baseline, not args.no_autotune)

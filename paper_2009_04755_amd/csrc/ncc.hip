@@ -13,8 +13,8 @@
 //                 16-deep K slice in LDS (three stages, copies two slices ahead) and
 //                 accumulates the tile's Gram block with MFMA, FP32 accumulation; writes
 //                 one partial tile per item
-//   k_ncc_finish  per output pair: fixed-order sum of the K-chunk partials, rescale by
-//                 1/(s_i s_j), scatter to the packed upper triangle
+//   k_ncc_finish  per output pair: fixed-order FP64 sum of the K-chunk partials, rescale by
+//                 1/(s_i s_j) in FP64, rounded once, scatter to the packed upper triangle
 #include <cmath>
 #include <type_traits>
 
@@ -574,29 +574,22 @@ __global__ __launch_bounds__(256) void k_ncc_finish(const float *__restrict__ pa
     const int64_t i0 = (int64_t)tl.x * BM + row0;
     if (j >= n || i0 >= j) return;
     const float4 *p = (const float4 *)(partial + slot * nchunks * (int64_t)BM * BN) + t;
-    // fixed order: groups of 16 consecutive chunks, then the group sums
-    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int k0 = 0; k0 < nchunks; k0 += 16) {
-        float4 g = p[(int64_t)k0 * (BM * BN / 4)];
-        const int k1 = min(nchunks, k0 + 16);
-        for (int k = k0 + 1; k < k1; ++k) {
-            const float4 v = p[(int64_t)k * (BM * BN / 4)];
-            g.x += v.x;
-            g.y += v.y;
-            g.z += v.z;
-            g.w += v.w;
-        }
-        s.x += g.x;
-        s.y += g.y;
-        s.z += g.z;
-        s.w += g.w;
+    // fixed order, in FP64: a long K (thousands of chunks) would otherwise add the FP32
+    // rounding of every running sum to the result
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (int k = 0; k < nchunks; ++k) {
+        const float4 v = p[(int64_t)k * (BM * BN / 4)];
+        s0 += v.x;
+        s1 += v.y;
+        s2 += v.z;
+        s3 += v.w;
     }
-    const float vals[4] = {s.x, s.y, s.z, s.w};
-    const float sj = inv_s[j];
+    const double vals[4] = {s0, s1, s2, s3};
+    const double sj = inv_s[j];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const int64_t i = i0 + e;
-        if (i < j) out[i * n - i * (i + 1) / 2 + (j - i - 1)] = vals[e] * inv_s[i] * sj;
+        if (i < j) out[i * n - i * (i + 1) / 2 + (j - i - 1)] = (float)(vals[e] * (double)inv_s[i] * sj);
     }
 }
 

@@ -80,4 +80,5 @@ def test_profile_commands_use_existing_bench_flags():
             assert flag in helptext, (name, flag)
         m = re.search(r"--only (\S+)", args)
         if m:
-            assert m.group(1) in ("clouds", "sparse", "cv", "pce", "pce_big", "pce_camera", "ooc", "small", "valu"), (name, m.group(1))
+            assert m.group(1) in ("clouds", "sparse", "cv", "pce", "pce_big", "pce_camera", "ooc", "small", "valu",
+                                  "forensics"), (name, m.group(1))
