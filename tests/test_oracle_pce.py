@@ -74,6 +74,30 @@ def test_rectangular_correlation_matches_explicit_sum():
     np.testing.assert_allclose(pce.correlation(a, b), C, rtol=0, atol=1e-12)
 
 
+def test_odd_shape_correlation_matches_explicit_sum():
+    # odd sides: no self-mirror middle row or column in the spectrum; the cyclic sum is the same
+    g = np.random.default_rng(5)
+    a = g.standard_normal((5, 7))
+    b = g.standard_normal((5, 7))
+    A, B = a - a.mean(), b - b.mean()
+    C = np.zeros((5, 7))
+    for sr in range(5):
+        for sc in range(7):
+            C[sr, sc] = sum(A[(r + sr) % 5, (c + sc) % 7] * B[r, c] for r in range(5) for c in range(7))
+    np.testing.assert_allclose(pce.correlation(a, b), C, rtol=0, atol=1e-12)
+
+
+def test_neighbourhood_spanning_an_odd_side():
+    # 9 x 11 with h = 4: 2h + 1 = 9 rows, so the neighbourhood of (4, 5) holds every row and
+    # columns 1 .. 9; PCE = 10^2 (99 - 81) / (energy outside) with only C[0, 0] outside
+    C = np.zeros((9, 11))
+    C[4, 5] = 10.0
+    C[8, 9] = 3.0   # row distance 4, column distance 4: inside, excluded
+    C[0, 0] = 2.0   # column distance 5: outside
+    v, p = pce.pce_of_surface(C, h=4)
+    assert p == 4 * 11 + 5 and abs(v - 100.0 * 18 / 4.0) < 1e-9
+
+
 @pytest.mark.parametrize("H,W", [(256, 512), (1024, 1024), (96, 40)])
 def test_large_correlation_matches_explicit_sums_at_sampled_shifts(H, W):
     g = np.random.default_rng(H + W)
