@@ -291,7 +291,10 @@ rocket_status rocket_cost_grad(rocket_ctx *ctx, const rocket_items *items, int64
 /* Tunables.  0 means "choose automatically" for every option. */
 typedef enum {
     ROCKET_OPT_NCC_TILE = 1,        /* NCC output tile edge: 64, 128 or 256 items */
-    ROCKET_OPT_NCC_KCHUNK = 2,      /* NCC split-K chunk length, a multiple of 16 elements */
+    ROCKET_OPT_NCC_KCHUNK = 2,      /* NCC split-K chunk length, a multiple of 16 elements (0: enough chunks
+                                       for ~2048 work items within [256, 2048]; for BF16x6 also at most
+                                       2^32 / dim, since the matrix cores' accumulation error grows with
+                                       chunk x dim relative to the pass bar) */
     ROCKET_OPT_GRID = 3,            /* persistent grid size in workgroups */
     ROCKET_OPT_QUEUE_ORDER = 4,     /* 0 planned (D&C order in per-XCD segments), 1 shuffled (by ROCKET_OPT_SEED),
                                        2 planned order in one segment */

@@ -646,15 +646,20 @@ static int ncc_waves(rocket_ctx *ctx, int bm)
 }
 
 // Split-K chunk length: enough chunks for ~2048 work items, within [256, 2048] elements.
-static int64_t ncc_kchunk(rocket_ctx *ctx, int64_t d_pad, int64_t tiles)
+// BF16x6: the accumulation inside the matrix cores loses accuracy with the chunk length, and
+// relative to the dot product's error scale the loss grows with the item length (measured
+// pass metric, median ~2.2e-6 sqrt((chunk / 2048) (d / 2^20))); chunk x d is kept at most
+// 2^32, which leaves 2048 at d = 2^20 and gives 416 at 3648 x 2736 (max 4.8e-6 at 512 there,
+// 9.8e-6 at 2048).
+static int64_t ncc_kchunk(rocket_ctx *ctx, int64_t d_pad, int64_t tiles, int scheme)
 {
     int64_t kc = ctx->opt[ROCKET_OPT_NCC_KCHUNK];
     if (!kc) {
         const int64_t want_chunks = std::max<int64_t>(1, (2048 + tiles - 1) / std::max<int64_t>(tiles, 1));
         kc = round_up((d_pad + want_chunks - 1) / want_chunks, 16);
-        // FP32 accumulation error of a chunk grows like sqrt(chunk length): 2048-element
-        // chunks keep it well inside 1e-5 of the dot product's error scale at 2^20 elements
-        kc = std::max<int64_t>(256, std::min<int64_t>(kc, 2048));
+        int64_t kmax = 2048;
+        if (scheme == SCH_X6) kmax = std::min<int64_t>(kmax, ((int64_t)1 << 32) / std::max<int64_t>(d_pad, 1) / 16 * 16);
+        kc = std::max<int64_t>(256, std::min<int64_t>(kc, kmax));
     }
     return std::min<int64_t>(kc, d_pad);
 }
@@ -741,7 +746,7 @@ rocket_status ncc_prepare(rocket_ctx *ctx, const rocket_items *it, int64_t n, in
         pc.pc_nchunks = -1;
     }
     st.tiles = (int64_t)pc.h_tiles.size();
-    const int64_t kc = ncc_kchunk(ctx, st.d_pad, st.tiles);
+    const int64_t kc = ncc_kchunk(ctx, st.d_pad, st.tiles, scheme);
     st.kt_per_chunk = (int)(kc / 16);
     st.nchunks = (int)((st.nkt + st.kt_per_chunk - 1) / st.kt_per_chunk);
     const int halves = 1;  // column slices per tile (the kernels use square blocks)
@@ -973,7 +978,7 @@ rocket_status ncc_allpairs_host(rocket_ctx *ctx, const float *host, int64_t n, i
     std::vector<int2> leaves;
     plan_leaves(n, T, leaves);
     st.tiles = (int64_t)leaves.size();
-    const int64_t kc = ncc_kchunk(ctx, st.d_pad, st.tiles);
+    const int64_t kc = ncc_kchunk(ctx, st.d_pad, st.tiles, scheme);
     st.kt_per_chunk = (int)(kc / 16);
     st.nchunks = (int)((st.nkt + st.kt_per_chunk - 1) / st.kt_per_chunk);
     st.items = st.tiles * st.nchunks;
