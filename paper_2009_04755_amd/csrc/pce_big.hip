@@ -1,6 +1,7 @@
 // PCE over all cyclic shifts for images larger than one LDS tile (Section V-A's PCE variant
 // of the pattern comparison at the size of the forensics patterns): H x W items, H and W in
-// [16, 4096] (a side that is not a power of two by Bluestein's chirp convolution).  The quantities are those of the in-LDS path:
+// [16, 4096] (a side that is not a power of two by Bluestein's chirp convolution).  The
+// quantities are those of the in-LDS path:
 //   C(s) = sum_x a(x + s) b(x),  s* = argmax C,  PCE = C(s*)^2 (HW - |N|) / sum_{s not in N} C(s)^2.
 //
 // Prepare (per item): FP64 mean and norm, then the 2-D DFT of the centred unit-norm image as
@@ -10,9 +11,9 @@
 // Compare: pairs are visited tile by tile (T x T items, divide-and-conquer leaves), two at a
 // time: P = conj(F_a) F_b + i conj(F_c) F_d is the spectrum of H W (C_1 + i C_2), both C real.
 // A batch of such pair-pairs runs as four kernels with the transform staged in HBM:
-//   row pass     per pair-pair and group of mirror row pairs {q, H - q}: build those rows of P
-//                over all W columns from the four half spectra (Hermitian mirror for columns
-//                > W/2) and transform them along the row;
+//   row pass     per pair-pair and group of mirror row pairs {q, H - q} (row 0 alone for odd
+//                H): build those rows of P over all W columns from the four half spectra
+//                (Hermitian mirror for columns > W/2) and transform them along the row;
 //   column pass  per pair-pair and group of columns: transform along the columns and keep
 //                only the group's peak (largest value, smallest shift index r W + c on ties)
 //                and its FP64 energy per channel (H W C is not written back);
